@@ -1,0 +1,209 @@
+/*
+ * ldpc.h -- batched sum-product decoding of quasi-cyclic LDPC block codes and
+ * of LDPC convolutional codes unwrapped from them, on one AMD Instinct MI355X
+ * (gfx950).
+ *
+ * Method: Y. Zhao and F. C. M. Lau, "Implementation of Decoders for LDPC Block
+ * Codes and LDPC Convolutional Codes Based on GPUs" (arXiv:1204.0334).
+ * Gamma codewords that share one Tanner graph are decoded together (Sec. IV-A)
+ * with the flooding belief-propagation of Algorithm 1: check-node update
+ * (horizontal step), variable-node update and a-posteriori LLR (vertical
+ * step), hard decision.
+ *
+ * Conventions for every entry point
+ *   - Return value: LDPC_OK (0) or a negative ldpc_status.  Nothing throws
+ *     across this interface.
+ *   - All arguments are validated on the host before anything is enqueued; a
+ *     call that returns an error has launched nothing and written nothing.
+ *   - "device" pointers are HIP device memory of the current device; "host"
+ *     pointers are ordinary CPU memory.  The caller owns every buffer; the
+ *     library never allocates device memory (the decoders take a caller
+ *     workspace sized by ldpc_workspace_size).
+ *   - Decoding is asynchronous on `stream` (a hipStream_t; NULL = the null
+ *     stream): outputs are valid once the caller has synchronised the stream.
+ *     Calls on different streams need different workspaces.
+ *   - A graph is an immutable host object; it may be shared across threads
+ *     and streams.
+ *   - Bit and LLR conventions (Sec. II-B): bit c maps to x = 1 - 2c; channel
+ *     LLRs are mu = ln P(c=0|y)/P(c=1|y) = 2y/sigma^2; a hard decision is 0
+ *     when the posterior LLR is >= 0 (Eq. 6; -0.0 decides 0).
+ *   - Saturation (not stated in the paper): every variable-to-check message,
+ *     including the initial one, is clipped to [-30, 30], and so is every
+ *     returned posterior; decisions use the unclipped posterior.
+ */
+#ifndef LDPC_H
+#define LDPC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ldpc_graph ldpc_graph;
+
+typedef enum {
+    LDPC_OK = 0,
+    LDPC_EINVAL = -1,        /* bad argument (NULL pointer, out-of-range value, wrong graph kind) */
+    LDPC_EWORKSPACE = -2,    /* workspace NULL or smaller than ldpc_workspace_size */
+    LDPC_EHIP = -3,          /* a HIP runtime call or kernel launch failed */
+    LDPC_EUNSUPPORTED = -4,  /* valid code, but outside this build's limits (degrees, sizes) */
+    LDPC_ENOMEM = -5         /* host allocation failed */
+} ldpc_status;
+
+typedef enum { LDPC_GRAPH_QC = 0, LDPC_GRAPH_CONV = 1 } ldpc_graph_kind;
+
+typedef struct {
+    int32_t kind;            /* ldpc_graph_kind */
+    int32_t n, m, E;         /* variables, checks, edges (ones of H) */
+    int32_t dv_max, dc_max;  /* largest column / row weight */
+    int32_t J, L, p;         /* QC base: J x L circulants of size p (the QC code; for a
+                                convolutional graph built from a QC base, that base) */
+    int32_t ms, T;           /* convolutional: syndrome-former memory, period */
+    int32_t Jb, Lb;          /* convolutional: circulant rows per check layer, columns per position */
+    int32_t c, c_minus_b;    /* convolutional: bits per code position, checks per layer */
+    int32_t positions;       /* convolutional: code positions kept (terminated chain) */
+    int32_t layers;          /* convolutional: check layers kept */
+    double design_rate;      /* 1 - J/L (QC), b/c (convolutional) */
+} ldpc_graph_info;
+
+/* Limits of this build. */
+#define LDPC_MAX_BLOCKS      256   /* nonzero circulants in a base / syndrome-former table */
+#define LDPC_MAX_BASE_ROWS   32
+#define LDPC_MAX_BASE_COLS   64
+#define LDPC_MAX_ROW_WEIGHT  32
+#define LDPC_MAX_COL_WEIGHT  16
+#define LDPC_MAX_ITERS       100000
+
+/*
+ * Quasi-cyclic LDPC code of Eq. 2: H is J x L blocks of p x p circulants.
+ * shifts: host, int32 [J][L] row-major.  Block (j,l) is the identity with its
+ * columns shifted cyclically to the right shifts[j][l] times, i.e. row r of
+ * the block has its one in column (r + shifts[j][l]) mod p; -1 is the zero
+ * block (footnote of Sec. IV-B).  Requires 0 <= shift < p or shift == -1.
+ * Check (j, s) is row j*p + s; variable (l, t) is column l*p + t.
+ * The shift table is copied; *out receives a graph to release with
+ * ldpc_graph_destroy.  Errors: EINVAL (NULL, J/L/p <= 0, shift out of range),
+ * EUNSUPPORTED (beyond the limits above), ENOMEM.
+ */
+ldpc_status ldpc_graph_create_qc(const int32_t* shifts, int32_t J, int32_t L, int32_t p,
+                                 ldpc_graph** out);
+
+/*
+ * LDPC convolutional code derived from a QC code by unwrapping (Sec. II-D):
+ * Lambda = gcd(J, L); the base is cut into Lambda x Lambda sub-blocks
+ * H_{i,j}; the lower part (j <= i) is kept on the block diagonal and the
+ * strictly upper part pasted below it, and the pair repeats down the
+ * diagonal.  Period T = Lambda, memory ms = Lambda - 1; a code position
+ * (frame) holds c = p L / Lambda bits, a check layer c - b = p J / Lambda
+ * checks.  Check layer tau meets position tau - d (d = 0..ms) through
+ * sub-block H_{tau mod T, (tau - d) mod T}.
+ * The chain holds `positions` code positions (variables indexed
+ * position-major: variable q*p + u of position t is column t*c + q*p + u);
+ * terminate = 1 keeps the ms tail layers that close the chain
+ * (positions + ms layers), terminate = 0 keeps layers 0..positions-1.
+ * Errors as ldpc_graph_create_qc, plus EINVAL for positions <= 0.
+ */
+ldpc_status ldpc_graph_create_ldpccc_from_qc(const int32_t* shifts, int32_t J, int32_t L, int32_t p,
+                                             int32_t positions, int32_t terminate,
+                                             ldpc_graph** out);
+
+/*
+ * Periodic LDPC convolutional code given by its syndrome-former components
+ * (Eq. of H_[0,inf] in Sec. II-C): check layer tau of class i = tau mod T
+ * meets position tau - d through H_d(tau), d = 0..ms, each a Jb x Lb array of
+ * p x p circulants.  sf: host, int32 [T][ms+1][Jb][Lb] row-major, same shift
+ * convention as ldpc_graph_create_qc.  positions / terminate as above.
+ */
+ldpc_status ldpc_graph_create_ldpccc_sf(const int32_t* sf, int32_t T, int32_t ms, int32_t Jb,
+                                        int32_t Lb, int32_t p, int32_t positions, int32_t terminate,
+                                        ldpc_graph** out);
+
+/* Fills *info.  Errors: EINVAL for NULL arguments. */
+ldpc_status ldpc_graph_get_info(const ldpc_graph* g, ldpc_graph_info* info);
+
+/* Releases a graph; NULL is ignored. */
+void ldpc_graph_destroy(ldpc_graph* g);
+
+/*
+ * Device workspace needed by ldpc_decode (window == 0) or ldpc_decode_window
+ * (window = W >= 1) for `gamma` frames and at most `max_iters` iterations
+ * (per window for the window decoder).  Errors: EINVAL, EUNSUPPORTED
+ * (the block decoder on a convolutional graph or the reverse).
+ */
+ldpc_status ldpc_workspace_size(const ldpc_graph* g, int32_t gamma, int32_t max_iters,
+                                int32_t window, size_t* bytes);
+
+/*
+ * Flooding sum-product decoding of `gamma` frames of a QC graph
+ * (Algorithm 1: initialisation beta = mu; horizontal step Eq. 3; vertical
+ * step Eq. 4; posterior Eq. 5; hard decision Eq. 6).
+ *   llr        device, float [gamma][n]: channel LLRs; not modified
+ *   max_iters  >= 1 iterations (one iteration = all check nodes, then all
+ *              variable nodes)
+ *   early_stop 0: run max_iters iterations.  1: test the syndrome of the
+ *              hard decisions after every iteration and freeze a frame at
+ *              the first iteration whose syndrome is zero (the paper always
+ *              runs the full count; this is an addition)
+ *   post       device, float [gamma][n]: clip(posterior LLR, +-30) of the
+ *              returned iteration
+ *   bits       device, uint8 [gamma][n]: hard decisions, 0/1
+ *   iters      device, int32 [gamma] or NULL: iterations run per frame
+ *   converged  device, uint8 [gamma] or NULL: 1 if the returned decisions
+ *              satisfy every check
+ *   workspace  device, >= ldpc_workspace_size(g, gamma, max_iters, 0) bytes,
+ *              256-byte aligned; its contents on entry do not matter
+ * Errors: EINVAL (NULL required pointer, gamma < 1, max_iters outside
+ * [1, LDPC_MAX_ITERS], convolutional graph), EWORKSPACE, EHIP.
+ */
+ldpc_status ldpc_decode(const ldpc_graph* g, const float* llr, int32_t gamma, int32_t max_iters,
+                        int32_t early_stop, float* post, uint8_t* bits, int32_t* iters,
+                        uint8_t* converged, void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * Sliding-window decoding of `gamma` independent streams of a terminated
+ * convolutional graph (Sec. II-E: checks span at most ms+1 positions).  For
+ * target position s = 0..positions-1: the window holds check layers
+ * s..s+W-1 and active positions s..s+W-1 (those that exist); a position
+ * entering the window starts from beta = clip(mu) on its edges, messages of
+ * the previous window are kept, and positions s-ms..s-1 keep the messages
+ * they last sent; `iters_per_window` flooding iterations run over the window
+ * (horizontal step on its layers, vertical step on its active positions,
+ * summing only messages from window layers); position s is then decided
+ * from mu plus the window layers' messages.
+ *   llr   device, float [gamma][positions * c]
+ *   post  device, float [gamma][positions * c]: clip(posterior, +-30)
+ *   bits  device, uint8 [gamma][positions * c]
+ *   W     window length in positions, ms + 1 <= W
+ * Errors: EINVAL (QC graph, W < ms+1, iters_per_window < 1, NULL pointers),
+ * EWORKSPACE, EHIP.
+ */
+ldpc_status ldpc_decode_window(const ldpc_graph* conv, const float* llr, int32_t gamma, int32_t W,
+                               int32_t iters_per_window, float* post, uint8_t* bits,
+                               void* workspace, size_t workspace_bytes, void* stream);
+
+/* Static description of a status code. */
+const char* ldpc_status_str(ldpc_status s);
+
+/*
+ * Kernel timing for measurement.  While enabled, every kernel the decoders
+ * enqueue is bracketed by a pair of HIP events on its stream, grouped by
+ * kernel class; ldpc_timing_read synchronises those events and returns, per
+ * class, the launch count and the summed device time in milliseconds, then
+ * clears them.  Classes (index into the arrays, capacity >= LDPC_TIMING_CLASSES):
+ *   0 ingest, 1 check-node, 2 variable-node, 3 syndrome, 4 output,
+ *   5 frame status, 6 window ingest, 7 window init, 8 window check-node,
+ *   9 window variable-node, 10 window output.
+ * ldpc_kernel_class_name returns a static name for a class index.
+ */
+#define LDPC_TIMING_CLASSES 11
+ldpc_status ldpc_timing_enable(int32_t enable);
+ldpc_status ldpc_timing_read(int64_t* launches, double* total_ms, int32_t capacity);
+const char* ldpc_kernel_class_name(int32_t cls);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LDPC_H */

@@ -84,15 +84,24 @@ static void free_colview(colview* cv) {
 }
 
 /* Horizontal step (Eq. 3) for one row: every outgoing alpha from the other
- * edges' beta, product taken directly (no division, no "total minus own"). */
-static void check_update(const int32_t* row_ptr, int r, const double* beta, double* alpha) {
+ * edges' beta, product taken directly (no division, no "total minus own").
+ * th is caller scratch of at least the row weight. */
+static void check_update(const int32_t* row_ptr, int r, const double* beta, double* alpha, double* th) {
     int e0 = row_ptr[r], e1 = row_ptr[r + 1];
+    for (int f = e0; f < e1; ++f) th[f - e0] = tanh(beta[f] / 2.0);
     for (int e = e0; e < e1; ++e) {
         double prod = 1.0;
         for (int f = e0; f < e1; ++f)
-            if (f != e) prod *= tanh(beta[f] / 2.0);
+            if (f != e) prod *= th[f - e0];
         alpha[e] = 2.0 * atanh(prod);
     }
+}
+
+static int max_row_weight(int m, const int32_t* row_ptr) {
+    int w = 1;
+    for (int r = 0; r < m; ++r)
+        if (row_ptr[r + 1] - row_ptr[r] > w) w = row_ptr[r + 1] - row_ptr[r];
+    return w;
 }
 
 /* Syndrome of hard decisions c: returns 1 if every row has even parity. */
@@ -141,7 +150,8 @@ int oracle_decode_block(int n, int m, const int32_t* row_ptr, const int32_t* col
         double* alpha = (double*)malloc(sizeof(double) * (size_t)(ne > 0 ? ne : 1));
         double* L = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
         uint8_t* c = (uint8_t*)malloc((size_t)(n > 0 ? n : 1));
-        if (!mu || !beta || !alpha || !L || !c) {
+        double* th = (double*)malloc(sizeof(double) * (size_t)max_row_weight(m, row_ptr));
+        if (!mu || !beta || !alpha || !L || !c || !th) {
             #pragma omp atomic write
             status = -1;
         } else {
@@ -158,7 +168,7 @@ int oracle_decode_block(int n, int m, const int32_t* row_ptr, const int32_t* col
                 if (syn_trace) memset(syn_trace + (size_t)g * max_iters, 0, (size_t)max_iters);
                 for (int it = 1; it <= max_iters; ++it) {
                     /* horizontal step */
-                    for (int r = 0; r < m; ++r) check_update(row_ptr, r, beta, alpha);
+                    for (int r = 0; r < m; ++r) check_update(row_ptr, r, beta, alpha, th);
                     /* vertical step, a-posteriori LLR and hard decision */
                     for (int v = 0; v < n; ++v) {
                         int k0 = cv.col_ptr[v], k1 = cv.col_ptr[v + 1];
@@ -188,7 +198,7 @@ int oracle_decode_block(int n, int m, const int32_t* row_ptr, const int32_t* col
                 if (min_abs) min_abs[g] = mina;
             }
         }
-        free(mu); free(beta); free(alpha); free(L); free(c);
+        free(mu); free(beta); free(alpha); free(L); free(c); free(th);
     }
     free_colview(&cv);
     return status;
@@ -259,7 +269,8 @@ int oracle_decode_window(int n, int m, const int32_t* row_ptr, const int32_t* co
         {
             double* beta = (double*)calloc((size_t)(ne > 0 ? ne : 1), sizeof(double));
             double* alpha = (double*)calloc((size_t)(ne > 0 ? ne : 1), sizeof(double));
-            if (beta && alpha) {
+            double* th = (double*)malloc(sizeof(double) * (size_t)max_row_weight(m, row_ptr));
+            if (beta && alpha && th) {
                 #pragma omp for schedule(dynamic, 1)
                 for (int g = 0; g < gamma; ++g) {
                     const float* y = llr + (size_t)g * n;
@@ -283,7 +294,7 @@ int oracle_decode_window(int n, int m, const int32_t* row_ptr, const int32_t* co
                         for (int it = 0; it < K; ++it) {
                             for (int t = lay_lo; t <= lay_hi; ++t)
                                 for (int q = lay_ptr[t]; q < lay_ptr[t + 1]; ++q)
-                                    check_update(row_ptr, lay_row[q], beta, alpha);
+                                    check_update(row_ptr, lay_row[q], beta, alpha, th);
                             for (int t = s; t <= pos_hi; ++t)
                                 for (int q = pos_ptr[t]; q < pos_ptr[t + 1]; ++q) {
                                     int v = pos_col[q];
@@ -316,7 +327,7 @@ int oracle_decode_window(int n, int m, const int32_t* row_ptr, const int32_t* co
                 #pragma omp atomic write
                 status = -1;
             }
-            free(beta); free(alpha);
+            free(beta); free(alpha); free(th);
         }
     }
     free(lay_ptr); free(lay_row); free(pos_ptr); free(pos_col);

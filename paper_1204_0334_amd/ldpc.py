@@ -1,0 +1,233 @@
+"""Python binding of the C ABI in include/ldpc.h (ctypes).
+
+Argument marshalling only: every step of decoding runs in the HIP library
+libldpc_hip.so.  PyTorch supplies device memory (the LLR, output and
+workspace tensors) and the current HIP stream.  If the library has not been
+built, importing this module raises: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+# torch first: its wheel carries its own HIP runtime (same soname as the system
+# one).  Loading torch before the library makes the library bind to that
+# runtime, so the process has one HIP runtime and torch's streams and memory
+# are valid in the library's calls.
+import torch  # noqa: F401
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libldpc_hip.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with paper_1204_0334_amd.build.build()")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+_vp, _i32, _i64, _sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+
+OK, EINVAL, EWORKSPACE, EHIP, EUNSUPPORTED, ENOMEM = 0, -1, -2, -3, -4, -5
+GRAPH_QC, GRAPH_CONV = 0, 1
+TIMING_CLASSES = 11
+MAX_ITERS = 100000
+
+
+class GraphInfo(ctypes.Structure):
+    _fields_ = [("kind", _i32), ("n", _i32), ("m", _i32), ("E", _i32), ("dv_max", _i32), ("dc_max", _i32),
+                ("J", _i32), ("L", _i32), ("p", _i32), ("ms", _i32), ("T", _i32), ("Jb", _i32), ("Lb", _i32),
+                ("c", _i32), ("c_minus_b", _i32), ("positions", _i32), ("layers", _i32),
+                ("design_rate", ctypes.c_double)]
+
+
+def _sig(name, res, args):
+    f = getattr(_lib, name)
+    f.restype = res
+    f.argtypes = args
+    return f
+
+
+_create_qc = _sig("ldpc_graph_create_qc", _i32, [_vp, _i32, _i32, _i32, ctypes.POINTER(_vp)])
+_create_cc = _sig("ldpc_graph_create_ldpccc_from_qc", _i32, [_vp, _i32, _i32, _i32, _i32, _i32, ctypes.POINTER(_vp)])
+_create_sf = _sig("ldpc_graph_create_ldpccc_sf", _i32,
+                  [_vp, _i32, _i32, _i32, _i32, _i32, _i32, _i32, ctypes.POINTER(_vp)])
+_get_info = _sig("ldpc_graph_get_info", _i32, [_vp, ctypes.POINTER(GraphInfo)])
+_destroy = _sig("ldpc_graph_destroy", None, [_vp])
+_ws_size = _sig("ldpc_workspace_size", _i32, [_vp, _i32, _i32, _i32, ctypes.POINTER(_sz)])
+_decode = _sig("ldpc_decode", _i32, [_vp, _vp, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _sz, _vp])
+_decode_window = _sig("ldpc_decode_window", _i32, [_vp, _vp, _i32, _i32, _i32, _vp, _vp, _vp, _sz, _vp])
+_status_str = _sig("ldpc_status_str", ctypes.c_char_p, [_i32])
+_timing_enable = _sig("ldpc_timing_enable", _i32, [_i32])
+_timing_read = _sig("ldpc_timing_read", _i32, [ctypes.POINTER(_i64), ctypes.POINTER(ctypes.c_double), _i32])
+_class_name = _sig("ldpc_kernel_class_name", ctypes.c_char_p, [_i32])
+
+EXPORTED = ["ldpc_graph_create_qc", "ldpc_graph_create_ldpccc_from_qc", "ldpc_graph_create_ldpccc_sf",
+            "ldpc_graph_get_info", "ldpc_graph_destroy", "ldpc_workspace_size", "ldpc_decode",
+            "ldpc_decode_window", "ldpc_status_str", "ldpc_timing_enable", "ldpc_timing_read",
+            "ldpc_kernel_class_name"]
+
+
+class LdpcError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        super().__init__(f"{what}: {status_str(status)} ({status})")
+        self.status = status
+
+
+def status_str(status: int) -> str:
+    return _status_str(int(status)).decode()
+
+
+def _check(status: int, what: str):
+    if status != OK:
+        raise LdpcError(status, what)
+
+
+def _int32_table(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.int64).astype(np.int32))
+
+
+class Graph:
+    """Host graph handle (QC block code or terminated convolutional code)."""
+
+    def __init__(self, handle):
+        self._h = handle
+        info = GraphInfo()
+        _check(_get_info(self._h, ctypes.byref(info)), "ldpc_graph_get_info")
+        self.info = {k: getattr(info, k) for k, _ in GraphInfo._fields_}
+
+    @classmethod
+    def qc(cls, shifts, p: int) -> "Graph":
+        a = _int32_table(shifts)
+        if a.ndim != 2:
+            raise ValueError("shifts must be a 2-D table")
+        h = _vp()
+        _check(_create_qc(a.ctypes.data, a.shape[0], a.shape[1], int(p), ctypes.byref(h)), "ldpc_graph_create_qc")
+        return cls(h)
+
+    @classmethod
+    def ldpccc_from_qc(cls, shifts, p: int, positions: int, terminate: bool = True) -> "Graph":
+        a = _int32_table(shifts)
+        if a.ndim != 2:
+            raise ValueError("shifts must be a 2-D table")
+        h = _vp()
+        _check(_create_cc(a.ctypes.data, a.shape[0], a.shape[1], int(p), int(positions), int(bool(terminate)),
+                          ctypes.byref(h)), "ldpc_graph_create_ldpccc_from_qc")
+        return cls(h)
+
+    @classmethod
+    def ldpccc_sf(cls, sf, p: int, positions: int, terminate: bool = True) -> "Graph":
+        a = _int32_table(sf)
+        if a.ndim != 4:
+            raise ValueError("sf must be [T][ms+1][Jb][Lb]")
+        T, ms1, Jb, Lb = a.shape
+        h = _vp()
+        _check(_create_sf(a.ctypes.data, T, ms1 - 1, Jb, Lb, int(p), int(positions), int(bool(terminate)),
+                          ctypes.byref(h)), "ldpc_graph_create_ldpccc_sf")
+        return cls(h)
+
+    @property
+    def handle(self):
+        return self._h
+
+    @property
+    def n(self) -> int:
+        return self.info["n"]
+
+    def workspace_size(self, gamma: int, max_iters: int = 1, window: int = 0) -> int:
+        out = _sz()
+        _check(_ws_size(self._h, int(gamma), int(max_iters), int(window), ctypes.byref(out)), "ldpc_workspace_size")
+        return int(out.value)
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h and _destroy is not None:   # module globals may be gone at interpreter exit
+            _destroy(h)
+        self._h = None
+
+    def __del__(self):
+        self.close()
+
+
+def _torch():
+    return torch
+
+
+def _stream_handle(stream):
+    torch = _torch()
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _need(t, dtype, shape, what):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError(f"{what} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype or tuple(t.shape) != tuple(shape) or not t.is_contiguous():
+        raise ValueError(f"{what} must be a contiguous {dtype} tensor of shape {tuple(shape)}")
+
+
+def workspace(g: Graph, gamma: int, max_iters: int = 1, window: int = 0, device=None):
+    torch = _torch()
+    nbytes = g.workspace_size(gamma, max_iters, window)
+    return torch.empty(max(nbytes, 1), dtype=torch.uint8, device=device or "cuda")
+
+
+def decode(g: Graph, llr, max_iters: int, early_stop: bool = False, out=None, ws=None, stream=None):
+    """Decode llr [gamma, n] (float32, device).  Returns (post, bits, iters,
+    converged) device tensors; enqueued on `stream` (default: current)."""
+    torch = _torch()
+    if llr.dim() != 2:
+        raise ValueError("llr must be [gamma, n]")
+    gamma, n = llr.shape
+    _need(llr, torch.float32, (gamma, g.n), "llr")
+    dev = llr.device
+    if out is None:
+        out = (torch.empty((gamma, n), dtype=torch.float32, device=dev),
+               torch.empty((gamma, n), dtype=torch.uint8, device=dev),
+               torch.empty((gamma,), dtype=torch.int32, device=dev),
+               torch.empty((gamma,), dtype=torch.uint8, device=dev))
+    post, bits, iters, conv = out
+    _need(post, torch.float32, (gamma, n), "post")
+    _need(bits, torch.uint8, (gamma, n), "bits")
+    _need(iters, torch.int32, (gamma,), "iters")
+    _need(conv, torch.uint8, (gamma,), "converged")
+    if ws is None:
+        ws = workspace(g, gamma, max_iters, 0, dev)
+    _check(_decode(g.handle, llr.data_ptr(), gamma, int(max_iters), int(bool(early_stop)), post.data_ptr(),
+                   bits.data_ptr(), iters.data_ptr(), conv.data_ptr(), ws.data_ptr(), ws.numel(),
+                   _stream_handle(stream)), "ldpc_decode")
+    return post, bits, iters, conv
+
+
+def decode_window(g: Graph, llr, W: int, iters_per_window: int, out=None, ws=None, stream=None):
+    """Sliding-window decoding of llr [gamma, positions * c].  Returns (post, bits)."""
+    torch = _torch()
+    if llr.dim() != 2:
+        raise ValueError("llr must be [gamma, n]")
+    gamma, n = llr.shape
+    _need(llr, torch.float32, (gamma, g.n), "llr")
+    dev = llr.device
+    if out is None:
+        out = (torch.empty((gamma, n), dtype=torch.float32, device=dev),
+               torch.empty((gamma, n), dtype=torch.uint8, device=dev))
+    post, bits = out
+    _need(post, torch.float32, (gamma, n), "post")
+    _need(bits, torch.uint8, (gamma, n), "bits")
+    if ws is None:
+        ws = workspace(g, gamma, 1, W, dev)
+    _check(_decode_window(g.handle, llr.data_ptr(), gamma, int(W), int(iters_per_window), post.data_ptr(),
+                          bits.data_ptr(), ws.data_ptr(), ws.numel(), _stream_handle(stream)),
+           "ldpc_decode_window")
+    return post, bits
+
+
+def timing_enable(on: bool = True):
+    _check(_timing_enable(int(bool(on))), "ldpc_timing_enable")
+
+
+def timing_read() -> dict:
+    """Per kernel class: (launches, summed device ms) since the last read."""
+    cnt = (_i64 * TIMING_CLASSES)()
+    ms = (ctypes.c_double * TIMING_CLASSES)()
+    _check(_timing_read(cnt, ms, TIMING_CLASSES), "ldpc_timing_read")
+    return {_class_name(c).decode(): (int(cnt[c]), float(ms[c])) for c in range(TIMING_CLASSES)}

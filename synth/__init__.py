@@ -144,36 +144,31 @@ def ebn0_to_sigma2(ebn0_db: float, rate: float) -> float:
 
 def gaussian(seed: int, frame0: int, gamma: int, n: int, tag: int = _TAG_NOISE) -> np.ndarray:
     """Standard normal samples [gamma, n] in float64.  Sample (g, i) depends
-    only on (seed, frame0 + g, i)."""
-    if gamma == 0 or n == 0:
-        return np.zeros((gamma, n), dtype=np.float64)
-    nblk = (n + 3) // 4
-    f = np.repeat(np.arange(frame0, frame0 + gamma, dtype=np.uint64), nblk)
-    b = np.tile(np.arange(nblk, dtype=np.uint64), gamma)
-    ctr = np.stack([b, f & np.uint64(0xFFFFFFFF), np.full_like(b, tag), f >> np.uint64(32)],
-                   axis=1).astype(np.uint32)
-    w = philox4x32_10(ctr, _key(seed))
-    u = _uniform_open(w)
-    r0 = np.sqrt(-2.0 * np.log(u[:, 0]))
-    r1 = np.sqrt(-2.0 * np.log(u[:, 2]))
-    z = np.stack([r0 * np.cos(2 * np.pi * u[:, 1]), r0 * np.sin(2 * np.pi * u[:, 1]),
-                  r1 * np.cos(2 * np.pi * u[:, 3]), r1 * np.sin(2 * np.pi * u[:, 3])], axis=1)
-    return z.reshape(gamma, nblk * 4)[:, :n]
+    only on (seed, frame0 + g, i): block i // 4 of frame f uses the Philox
+    counter (i // 4, f mod 2^32, tag, f >> 32) and its four words feed two
+    Box-Muller pairs."""
+    z = np.empty((gamma, n), dtype=np.float64)
+    if gamma and n:
+        _lib().synth_gaussian(int(seed) & 0xFFFFFFFFFFFFFFFF, int(frame0), int(gamma), int(n), int(tag),
+                              z.ctypes.data)
+    return z
 
 
 def bpsk_awgn_llr(codewords, sigma2: float, seed: int, frame0: int = 0,
                   gamma: int | None = None, n: int | None = None) -> np.ndarray:
-    """Channel LLRs mu = 2 y / sigma^2 as float32 [gamma, n].
+    """Channel LLRs mu = 2 y / sigma^2 as float32 [gamma, n], y = (1 - 2c) + sigma z.
     codewords: uint8 [gamma, n] of 0/1, or None for the all-zero codeword
     (then gamma and n must be given)."""
     if codewords is None:
-        x = np.ones((gamma, n), dtype=np.float64)
+        cw = None
     else:
-        cw = np.asarray(codewords, dtype=np.uint8)
+        cw = np.ascontiguousarray(np.asarray(codewords, dtype=np.uint8))
         gamma, n = cw.shape
-        x = 1.0 - 2.0 * cw.astype(np.float64)
-    y = x + math.sqrt(sigma2) * gaussian(seed, frame0, gamma, n)
-    return (2.0 * y / sigma2).astype(np.float32)
+    out = np.empty((gamma, n), dtype=np.float32)
+    if gamma and n:
+        _lib().synth_llr(int(seed) & 0xFFFFFFFFFFFFFFFF, int(frame0), int(gamma), int(n), _TAG_NOISE,
+                         cw.ctypes.data if cw is not None else None, float(sigma2), out.ctypes.data)
+    return out
 
 
 def random_bits(seed: int, frame0: int, gamma: int, k: int) -> np.ndarray:
@@ -195,8 +190,8 @@ def random_bits(seed: int, frame0: int, gamma: int, k: int) -> np.ndarray:
 
 def build_lib(force: bool = True) -> str:
     if force or not os.path.exists(_LIB_PATH):
-        subprocess.check_call(["gcc", "-O3", "-fopenmp", "-fPIC", "-shared", "-std=c11",
-                               os.path.join(_HERE, "gf2.c"), "-o", _LIB_PATH])
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11",
+                               os.path.join(_HERE, "synth.c"), "-o", _LIB_PATH, "-lm"])
     return _LIB_PATH
 
 
@@ -213,7 +208,23 @@ def _lib():
     lib.gf2_encode.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]
     lib.gf2_destroy.restype = None
     lib.gf2_destroy.argtypes = [ctypes.c_void_p]
+    u64, i64 = ctypes.c_uint64, ctypes.c_int64
+    lib.synth_gaussian.restype = None
+    lib.synth_gaussian.argtypes = [u64, i64, i64, i64, ctypes.c_uint32, ctypes.c_void_p]
+    lib.synth_llr.restype = None
+    lib.synth_llr.argtypes = [u64, i64, i64, i64, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_double,
+                              ctypes.c_void_p]
+    lib.synth_philox_many.restype = None
+    lib.synth_philox_many.argtypes = [ctypes.c_void_p, i64, u64, ctypes.c_void_p]
     return lib
+
+
+def philox4x32_10_c(counters: np.ndarray, seed: int) -> np.ndarray:
+    """The C implementation of philox4x32_10 (key = seed split into two words)."""
+    c = np.ascontiguousarray(np.asarray(counters, dtype=np.uint32))
+    out = np.empty_like(c)
+    _lib().synth_philox_many(c.ctypes.data, c.shape[0], int(seed) & 0xFFFFFFFFFFFFFFFF, out.ctypes.data)
+    return out
 
 
 class QCEncoder:
@@ -244,8 +255,11 @@ class QCEncoder:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h:
-            _lib().gf2_destroy(h)
+        if h and _lib is not None:
+            try:
+                _lib().gf2_destroy(h)
+            except Exception:
+                pass
             self._h = None
 
 

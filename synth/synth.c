@@ -1,8 +1,17 @@
 /*
- * Seeded synthetic inputs: GF(2) systematic encoder for quasi-cyclic
- * parity-check matrices.
+ * Seeded synthetic inputs: counter-based random numbers, BPSK/AWGN channel
+ * LLRs, and a GF(2) systematic encoder for quasi-cyclic parity-check
+ * matrices.
  *
- * This file produces codewords to transmit; it is not part of any decoder.
+ * This file produces what is transmitted and received; it is not part of any
+ * decoder.
+ *
+ * Random numbers: Philox-4x32-10 (Salmon, Moraes, Dror, Shaw, SC 2011):
+ * ten rounds of two 32x32->64-bit multiplications by 0xD2511F53 and
+ * 0xCD9E8D57, the key bumped by the Weyl constants 0x9E3779B9 and
+ * 0xBB67AE85 between rounds.
+ *
+ * Encoder:
  * The parity-check matrix is lifted from a base matrix of circulant shifts
  * (the paper's Eq. 2: block (j,l) is the p x p identity with its columns
  * shifted cyclically right a[j][l] times, so row r of that block has its one
@@ -11,9 +20,95 @@
  * columns P; the remaining columns F carry the information bits.  A codeword
  * takes c_F = u and c_{P_i} = sum_f R[i][f] u_f (mod 2), so H c^T = 0.
  */
+#include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+
+static void philox_round(uint32_t c[4], const uint32_t k[2]) {
+    uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
+    uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
+    uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+    uint32_t n0 = hi1 ^ c[1] ^ k[0], n2 = hi0 ^ c[3] ^ k[1];
+    c[0] = n0; c[1] = lo1; c[2] = n2; c[3] = lo0;
+}
+
+/* out[4] = Philox-4x32-10(ctr, key) */
+void synth_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+    uint32_t c[4] = {ctr[0], ctr[1], ctr[2], ctr[3]};
+    uint32_t k[2] = {key[0], key[1]};
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) { k[0] += 0x9E3779B9u; k[1] += 0xBB67AE85u; }
+        philox_round(c, k);
+    }
+    out[0] = c[0]; out[1] = c[1]; out[2] = c[2]; out[3] = c[3];
+}
+
+/* many counters at once: ctr [count][4], out [count][4] */
+void synth_philox_many(const uint32_t* ctr, int64_t count, uint64_t seed, uint32_t* out) {
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    #pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < count; ++i) synth_philox(ctr + 4 * i, key, out + 4 * i);
+}
+
+static double uniform_open(uint32_t w) { return ((double)w + 0.5) * (1.0 / 4294967296.0); }
+
+/*
+ * Standard normal samples z [gamma][n] (double): sample (g, i) depends only
+ * on (seed, frame0 + g, i).  Block b = i / 4 of frame f uses the counter
+ * (b, f mod 2^32, tag, f >> 32); its four words (u0, u1, u2, u3) give two
+ * Box-Muller pairs: r0 = sqrt(-2 ln u0) (cos, sin)(2 pi u1) and likewise
+ * for (u2, u3).
+ */
+void synth_gaussian(uint64_t seed, int64_t frame0, int64_t gamma, int64_t n, uint32_t tag, double* z) {
+    const int64_t nblk = (n + 3) / 4;
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    const double two_pi = 6.283185307179586476925286766559;
+    #pragma omp parallel for schedule(static)
+    for (int64_t g = 0; g < gamma; ++g) {
+        const uint64_t f = (uint64_t)(frame0 + g);
+        for (int64_t b = 0; b < nblk; ++b) {
+            uint32_t ctr[4] = {(uint32_t)b, (uint32_t)f, tag, (uint32_t)(f >> 32)}, w[4];
+            synth_philox(ctr, key, w);
+            double r0 = sqrt(-2.0 * log(uniform_open(w[0])));
+            double r1 = sqrt(-2.0 * log(uniform_open(w[2])));
+            double v[4] = {r0 * cos(two_pi * uniform_open(w[1])), r0 * sin(two_pi * uniform_open(w[1])),
+                           r1 * cos(two_pi * uniform_open(w[3])), r1 * sin(two_pi * uniform_open(w[3]))};
+            for (int q = 0; q < 4; ++q) {
+                int64_t i = 4 * b + q;
+                if (i < n) z[g * n + i] = v[q];
+            }
+        }
+    }
+}
+
+/* Channel LLRs mu = 2 y / sigma^2 with y = (1 - 2c) + sigma z, as float.
+ * cw: [gamma][n] bits or NULL for the all-zero codeword. */
+void synth_llr(uint64_t seed, int64_t frame0, int64_t gamma, int64_t n, uint32_t tag, const uint8_t* cw,
+               double sigma2, float* llr) {
+    const int64_t nblk = (n + 3) / 4;
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    const double two_pi = 6.283185307179586476925286766559, sigma = sqrt(sigma2);
+    #pragma omp parallel for schedule(static)
+    for (int64_t g = 0; g < gamma; ++g) {
+        const uint64_t f = (uint64_t)(frame0 + g);
+        for (int64_t b = 0; b < nblk; ++b) {
+            uint32_t ctr[4] = {(uint32_t)b, (uint32_t)f, tag, (uint32_t)(f >> 32)}, w[4];
+            synth_philox(ctr, key, w);
+            double r0 = sqrt(-2.0 * log(uniform_open(w[0])));
+            double r1 = sqrt(-2.0 * log(uniform_open(w[2])));
+            double v[4] = {r0 * cos(two_pi * uniform_open(w[1])), r0 * sin(two_pi * uniform_open(w[1])),
+                           r1 * cos(two_pi * uniform_open(w[3])), r1 * sin(two_pi * uniform_open(w[3]))};
+            for (int q = 0; q < 4; ++q) {
+                int64_t i = 4 * b + q;
+                if (i >= n) break;
+                double x = (cw && (cw[g * n + i] & 1)) ? -1.0 : 1.0;
+                llr[g * n + i] = (float)(2.0 * (x + sigma * v[q]) / sigma2);
+            }
+        }
+    }
+}
 
 typedef struct {
     int n, m, rank, words;

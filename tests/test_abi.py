@@ -1,0 +1,177 @@
+"""C-ABI library on the CPU: it loads, exports every declared entry point,
+builds and describes graphs, and rejects bad arguments before touching the
+GPU (every call below returns before any HIP runtime call)."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from conftest import ROOT
+from paper_1204_0334_amd import ldpc
+
+HEADER = os.path.join(ROOT, "include", "ldpc.h")
+FAKE = 1 << 20          # non-NULL pointer value that is never dereferenced
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ldpc_[a-z_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported():
+    names = declared_functions()
+    assert len(names) >= 12
+    lib = ctypes.CDLL(ldpc.LIB_PATH)
+    for name in names:
+        assert hasattr(lib, name), name
+    assert sorted(ldpc.EXPORTED) == names
+
+
+def test_qc_graph_info():
+    a = synth.draw_qc_shifts(3, 6, 64, 1)
+    g = ldpc.Graph.qc(a, 64)
+    i = g.info
+    assert (i["kind"], i["n"], i["m"], i["E"], i["dv_max"], i["dc_max"]) == (ldpc.GRAPH_QC, 384, 192, 1152, 3, 6)
+    assert (i["J"], i["L"], i["p"]) == (3, 6, 64)
+    assert i["design_rate"] == pytest.approx(0.5)
+
+
+def test_irregular_qc_graph_info():
+    a = np.array([[0, 3, -1, 2], [-1, 1, 4, -1]])
+    g = ldpc.Graph.qc(a, 5)
+    assert (g.info["E"], g.info["dv_max"], g.info["dc_max"]) == (5 * 5, 2, 3)
+
+
+@pytest.mark.parametrize("J,L,p,positions,terminate", [(3, 6, 512, 128, 1), (3, 6, 16, 10, 0), (4, 24, 7, 9, 1),
+                                                       (4, 6, 8, 7, 1)])
+def test_conv_graph_matches_reference_unwrapping(J, L, p, positions, terminate):
+    a = np.arange(J * L).reshape(J, L) % p
+    g = ldpc.Graph.ldpccc_from_qc(a, p, positions, terminate=bool(terminate))
+    H, info = oracle.unwrap_qc(a, p, positions, terminate=bool(terminate))
+    i = g.info
+    lam = math.gcd(J, L)
+    assert (i["kind"], i["T"], i["ms"], i["Jb"], i["Lb"]) == (ldpc.GRAPH_CONV, lam, lam - 1, J // lam, L // lam)
+    assert (i["c"], i["c_minus_b"], i["positions"], i["layers"]) == (info["c"], info["cb"], positions, info["nlayers"])
+    assert (i["n"], i["m"], i["E"]) == (H.n, H.m, H.ne)
+    deg_r = np.diff(H.row_ptr)
+    deg_c = np.bincount(H.col_idx, minlength=H.n)
+    assert i["dc_max"] == deg_r.max() and i["dv_max"] == deg_c.max()
+
+
+def test_syndrome_former_form_equals_unwrapped_qc():
+    a = synth.draw_qc_shifts(3, 6, 32, 2)
+    lam, Jb, Lb = 3, 1, 2
+    sf = np.full((lam, lam, Jb, Lb), -1)
+    for i in range(lam):
+        for d in range(lam):
+            jc = (i - d) % lam
+            sf[i, d] = a[i * Jb:(i + 1) * Jb, jc * Lb:(jc + 1) * Lb]
+    g1 = ldpc.Graph.ldpccc_from_qc(a, 32, 20)
+    g2 = ldpc.Graph.ldpccc_sf(sf, 32, 20)
+    for k in ("n", "m", "E", "dv_max", "dc_max", "c", "c_minus_b", "layers", "ms", "T"):
+        assert g1.info[k] == g2.info[k], k
+
+
+def _create_status(shifts, J, L, p):
+    h = ctypes.c_void_p()
+    a = np.ascontiguousarray(np.asarray(shifts, dtype=np.int32))
+    return ldpc._create_qc(a.ctypes.data if a.size else None, J, L, p, ctypes.byref(h)), h
+
+
+def test_graph_creation_rejects_bad_input():
+    ok = np.zeros((2, 3), dtype=np.int32)
+    assert _create_status(ok, 2, 3, 5)[0] == ldpc.OK
+    for bad in ([[5, 0, 0], [0, 0, 0]], [[-2, 0, 0], [0, 0, 0]]):
+        st, h = _create_status(bad, 2, 3, 5)
+        assert st == ldpc.EINVAL and not h.value
+    assert _create_status(ok, 2, 3, 0)[0] == ldpc.EINVAL
+    assert _create_status(ok, 0, 3, 5)[0] == ldpc.EINVAL
+    assert ldpc._create_qc(None, 2, 3, 5, ctypes.byref(ctypes.c_void_p())) == ldpc.EINVAL
+    a = ok
+    assert ldpc._create_qc(a.ctypes.data, 2, 3, 5, None) == ldpc.EINVAL
+    # beyond the build's limits
+    assert _create_status(np.zeros((2, 40), dtype=np.int32), 2, 40, 5)[0] == ldpc.EUNSUPPORTED   # row weight 40
+    assert _create_status(np.zeros((20, 20), dtype=np.int32), 20, 20, 5)[0] == ldpc.EUNSUPPORTED  # column weight
+    with pytest.raises(ldpc.LdpcError):
+        ldpc.Graph.ldpccc_from_qc(ok, 5, 0)
+    with pytest.raises(ldpc.LdpcError):
+        ldpc.Graph.ldpccc_sf(np.zeros((2, 2, 1, 1)), 5, -1)
+
+
+def test_graph_functions_are_null_safe():
+    assert ldpc._get_info(None, ctypes.byref(ldpc.GraphInfo())) == ldpc.EINVAL
+    ldpc._destroy(None)
+    assert ldpc.status_str(ldpc.EWORKSPACE) == "workspace missing or too small"
+    assert ldpc.status_str(123) == "unknown status"
+    assert ldpc._class_name(1).decode() == "check_node" and ldpc._class_name(99).decode() == "unknown"
+
+
+def test_workspace_size_rules():
+    qc = ldpc.Graph.qc(synth.draw_qc_shifts(3, 6, 64, 1), 64)
+    cc = ldpc.Graph.ldpccc_from_qc(synth.draw_qc_shifts(3, 6, 32, 2), 32, 16)
+    s64 = qc.workspace_size(64, 20)
+    assert s64 >= 64 * 4 * (2 * qc.n + qc.info["E"])
+    assert qc.workspace_size(1024, 20) > qc.workspace_size(512, 20) > s64
+    assert qc.workspace_size(64, 30) >= s64
+    assert cc.workspace_size(64, 1, window=6) > 0
+    out = ctypes.c_size_t()
+    assert ldpc._ws_size(qc.handle, 64, 20, 6, ctypes.byref(out)) == ldpc.EUNSUPPORTED
+    assert ldpc._ws_size(cc.handle, 64, 20, 0, ctypes.byref(out)) == ldpc.EUNSUPPORTED
+    assert ldpc._ws_size(cc.handle, 64, 20, 2, ctypes.byref(out)) == ldpc.EINVAL     # W < ms + 1
+    assert ldpc._ws_size(qc.handle, 0, 20, 0, ctypes.byref(out)) == ldpc.EINVAL
+    assert ldpc._ws_size(qc.handle, 64, 0, 0, ctypes.byref(out)) == ldpc.EINVAL
+    assert ldpc._ws_size(qc.handle, 64, 20, 0, None) == ldpc.EINVAL
+
+
+def test_decode_validates_before_launching():
+    qc = ldpc.Graph.qc(synth.draw_qc_shifts(3, 6, 64, 1), 64)
+    cc = ldpc.Graph.ldpccc_from_qc(synth.draw_qc_shifts(3, 6, 32, 2), 32, 16)
+    ws = qc.workspace_size(64, 20)
+    d = ldpc._decode
+    assert d(qc.handle, None, 64, 20, 1, FAKE, FAKE, FAKE, FAKE, FAKE, ws, None) == ldpc.EINVAL
+    assert d(qc.handle, FAKE, 64, 20, 1, None, FAKE, FAKE, FAKE, FAKE, ws, None) == ldpc.EINVAL
+    assert d(qc.handle, FAKE, 64, 20, 1, FAKE, None, FAKE, FAKE, FAKE, ws, None) == ldpc.EINVAL
+    assert d(None, FAKE, 64, 20, 1, FAKE, FAKE, FAKE, FAKE, FAKE, ws, None) == ldpc.EINVAL
+    assert d(qc.handle, FAKE, 0, 20, 1, FAKE, FAKE, FAKE, FAKE, FAKE, ws, None) == ldpc.EINVAL
+    assert d(qc.handle, FAKE, 64, 0, 1, FAKE, FAKE, FAKE, FAKE, FAKE, ws, None) == ldpc.EINVAL
+    assert d(qc.handle, FAKE, 64, ldpc.MAX_ITERS + 1, 1, FAKE, FAKE, FAKE, FAKE, FAKE, ws, None) == ldpc.EINVAL
+    assert d(cc.handle, FAKE, 64, 20, 1, FAKE, FAKE, FAKE, FAKE, FAKE, ws, None) == ldpc.EINVAL
+    assert d(qc.handle, FAKE, 64, 20, 1, FAKE, FAKE, FAKE, FAKE, FAKE, ws - 1, None) == ldpc.EWORKSPACE
+    assert d(qc.handle, FAKE, 64, 20, 1, FAKE, FAKE, FAKE, FAKE, None, ws, None) == ldpc.EWORKSPACE
+    assert d(qc.handle, FAKE, 64, 20, 1, FAKE, FAKE, FAKE, FAKE, FAKE + 4, ws, None) == ldpc.EINVAL   # alignment
+    # a larger batch needs more workspace than the one handed over
+    assert d(qc.handle, FAKE, 1024, 20, 1, FAKE, FAKE, FAKE, FAKE, FAKE, ws, None) == ldpc.EWORKSPACE
+
+
+def test_decode_window_validates_before_launching():
+    qc = ldpc.Graph.qc(synth.draw_qc_shifts(3, 6, 64, 1), 64)
+    cc = ldpc.Graph.ldpccc_from_qc(synth.draw_qc_shifts(3, 6, 32, 2), 32, 16)
+    ws = cc.workspace_size(64, 1, window=6)
+    d = ldpc._decode_window
+    assert d(qc.handle, FAKE, 64, 6, 10, FAKE, FAKE, FAKE, ws, None) == ldpc.EINVAL
+    assert d(cc.handle, None, 64, 6, 10, FAKE, FAKE, FAKE, ws, None) == ldpc.EINVAL
+    assert d(cc.handle, FAKE, 64, 2, 10, FAKE, FAKE, FAKE, ws, None) == ldpc.EINVAL
+    assert d(cc.handle, FAKE, 64, 6, 0, FAKE, FAKE, FAKE, ws, None) == ldpc.EINVAL
+    assert d(cc.handle, FAKE, 0, 6, 10, FAKE, FAKE, FAKE, ws, None) == ldpc.EINVAL
+    assert d(cc.handle, FAKE, 64, 6, 10, FAKE, FAKE, FAKE, ws - 1, None) == ldpc.EWORKSPACE
+    assert d(cc.handle, FAKE, 64, 8, 10, FAKE, FAKE, FAKE, ws, None) == ldpc.EWORKSPACE   # longer window, bigger ring
+
+
+def test_timing_read_without_launches():
+    ldpc.timing_enable(False)
+    t = ldpc.timing_read()
+    assert len(t) == ldpc.TIMING_CLASSES and all(v == (0, 0.0) for v in t.values())
+
+
+def test_library_shares_torch_hip_runtime():
+    # one HIP runtime per process: the library resolved libamdhip64 to the copy torch loaded
+    import torch
+    maps = open("/proc/self/maps").read()
+    runtimes = {line.split()[-1] for line in maps.splitlines() if "libamdhip64" in line}
+    assert len(runtimes) == 1, runtimes

@@ -115,3 +115,18 @@ def test_sigma_mapping():
     # Eb/N0 = 0 dB at rate 1/2 -> sigma^2 = 1
     assert synth.ebn0_to_sigma2(0.0, 0.5) == pytest.approx(1.0)
     assert synth.ebn0_to_sigma2(2.0, 0.5) == pytest.approx(0.630957, rel=1e-5)
+
+
+def test_c_gaussian_matches_numpy_philox_box_muller():
+    seed, f0, gamma, n = 0xDEADBEEF12345, 7, 5, 37
+    z = synth.gaussian(seed, f0, gamma, n)
+    nblk = (n + 3) // 4
+    for g in range(gamma):
+        f = f0 + g
+        ctr = np.array([[b, f & 0xFFFFFFFF, synth._TAG_NOISE, f >> 32] for b in range(nblk)], dtype=np.uint32)
+        w = synth.philox4x32_10(ctr, (seed & 0xFFFFFFFF, seed >> 32))
+        u = (w.astype(np.float64) + 0.5) / 2.0 ** 32
+        r0, r1 = np.sqrt(-2 * np.log(u[:, 0])), np.sqrt(-2 * np.log(u[:, 2]))
+        want = np.stack([r0 * np.cos(2 * np.pi * u[:, 1]), r0 * np.sin(2 * np.pi * u[:, 1]),
+                         r1 * np.cos(2 * np.pi * u[:, 3]), r1 * np.sin(2 * np.pi * u[:, 3])], 1).ravel()[:n]
+        np.testing.assert_allclose(z[g], want, rtol=1e-12, atol=1e-12)
