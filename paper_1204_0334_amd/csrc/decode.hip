@@ -264,7 +264,6 @@ struct ConvCol {
 struct BlockParams {
     float* msg;              // [tiles][E][Gt]
     const float* mu;         // [tiles][n][Gt]
-    float* post;             // [tiles][n][Gt] posterior (interleaved)
     uint64_t* bits;          // [tiles][n][FPL] packed decisions
     uint64_t* unsat;         // [max_iters+1][tiles][FPL]
     uint64_t* frozen;        // [max_iters+1][tiles][FPL]
@@ -369,20 +368,14 @@ __global__ void __launch_bounds__(kBlock) cn_block_kernel(const QCDesc D, const 
         if (R.valid(D, k)) store_frames<FPL>(mt + (size_t)R.pkg(D, k) * Gt, outv[k]);
 }
 
-// Variable-node pass of iteration P.iter: beta, posterior, decisions.
-template <int DVMAX, int FPL>
-__global__ void __launch_bounds__(kBlock) vn_block_kernel(const QCDesc D, const BlockParams P) {
-    constexpr int Gt = 64 * FPL;
-    const int lane = threadIdx.x & 63;
-    const int wave = blockIdx.x * kWavesPerBlock + wave_in_block();
-    const int tile = wave / D.n;
-    const int col = wave - tile * D.n;
-    if (tile >= P.tiles) return;
-    const int nvalid = min(P.gamma - tile * Gt, Gt);
-
-    // frames frozen before this iteration
-    uint64_t frz[FPL];
-    bool any = false, all = true;
+// Frames of a tile frozen before iteration P.iter (bit set = frozen; padding
+// frames count as frozen).  Frozen as of iteration i-1 = frozen as of i-2, or
+// the syndrome of iteration i-1 was zero.
+template <int FPL>
+__device__ __forceinline__ void frozen_words(const BlockParams& P, int tile, int nvalid, uint64_t (&frz)[FPL],
+                                             bool& any, bool& all) {
+    any = false;
+    all = true;
 #pragma unroll
     for (int f = 0; f < FPL; ++f) {
         uint64_t z = ~valid_word<FPL>(nvalid, f);
@@ -395,15 +388,17 @@ __global__ void __launch_bounds__(kBlock) vn_block_kernel(const QCDesc D, const 
         any = any || (z & valid_word<FPL>(nvalid, f)) != 0;
         all = all && (z == ~0ull);
     }
-    if (P.early && col == 0 && lane < FPL) {
-        uint64_t mine = frz[0];
-#pragma unroll
-        for (int f = 1; f < FPL; ++f)
-            if (lane == f) mine = frz[f];
-        P.frozen[((size_t)(P.iter - 1) * P.tiles + tile) * FPL + lane] = mine;
-    }
-    if (P.early && all) return;
+}
 
+// One variable (column col of tile) for the 64*FPL frames of the wave: reads
+// mu and the d_v incoming alphas, writes the outgoing betas (not after the
+// last iteration: nobody reads them), returns the posterior L, and with early
+// stopping or at the last iteration stores the packed decisions (frozen frames
+// keep their bits).
+template <int DVMAX, int FPL>
+__device__ __forceinline__ void vn_column(const QCDesc& D, const BlockParams& P, int tile, int col, int lane,
+                                          bool any, const uint64_t (&frz)[FPL], float (&L)[FPL]) {
+    constexpr int Gt = 64 * FPL;
     const QCCol C(D, col);
     const size_t lane_off = (size_t)lane * FPL;
     float* mt = P.msg + (size_t)tile * D.E * Gt + lane_off;
@@ -419,7 +414,6 @@ __global__ void __launch_bounds__(kBlock) vn_block_kernel(const QCDesc D, const 
             for (int f = 0; f < FPL; ++f) a[k][f] = 0.0f;
         }
     }
-    float L[FPL];
     float b[DVMAX][FPL];
 #pragma unroll
     for (int f = 0; f < FPL; ++f) {
@@ -438,10 +432,11 @@ __global__ void __launch_bounds__(kBlock) vn_block_kernel(const QCDesc D, const 
         }
         L[f] = mu[f] + pre;
     }
+    if (!P.last) {
 #pragma unroll
-    for (int k = 0; k < DVMAX; ++k)
-        if (C.valid(D, k)) store_frames<FPL>(mt + (size_t)C.pkg(D, k) * Gt, b[k]);
-
+        for (int k = 0; k < DVMAX; ++k)
+            if (C.valid(D, k)) store_frames<FPL>(mt + (size_t)C.pkg(D, k) * Gt, b[k]);
+    }
     if (P.early || P.last) {
         // decisions, packed: word f, bit i <-> frame FPL*i + f
         uint64_t* bw = P.bits + ((size_t)tile * D.n + C.v) * FPL;
@@ -453,14 +448,98 @@ __global__ void __launch_bounds__(kBlock) vn_block_kernel(const QCDesc D, const 
             if (lane == f) mine = w;
         }
         if (lane < FPL) bw[lane] = mine;
-        float* po = P.post + ((size_t)tile * D.n + C.v) * Gt + lane_off;
-        if (!any) {
-            store_frames<FPL>(po, L);
-        } else {
+    }
+}
+
+template <int FPL>
+__device__ __forceinline__ uint64_t pick_word(const uint64_t (&a)[FPL], int i);
+
+template <int FPL>
+__device__ __forceinline__ void publish_frozen(const BlockParams& P, int tile, int lane, const uint64_t (&frz)[FPL]) {
+    if (lane < FPL) P.frozen[((size_t)(P.iter - 1) * P.tiles + tile) * FPL + lane] = pick_word<FPL>(frz, lane);
+}
+
+// a[i] for a register array, blended with masks: a select chain or a
+// dynamic index gets turned into a private-memory array by the compiler
+template <int FPL>
+__device__ __forceinline__ uint64_t pick_word(const uint64_t (&a)[FPL], int i) {
+    uint64_t r = a[0];
 #pragma unroll
-            for (int f = 0; f < FPL; ++f)
-                if (!((frz[f] >> lane) & 1ull)) po[f] = L[f];
-        }
+    for (int f = 1; f < FPL; ++f) {
+        const uint64_t m = 0ull - (uint64_t)(i == f);
+        r = (a[f] & m) | (r & ~m);
+    }
+    return r;
+}
+
+// Variable-node pass of an iteration whose posterior is not returned
+// (no early stopping, not the last iteration): betas only.
+template <int DVMAX, int FPL>
+__global__ void __launch_bounds__(kBlock) vn_block_kernel(const QCDesc D, const BlockParams P) {
+    constexpr int Gt = 64 * FPL;
+    const int lane = threadIdx.x & 63;
+    const int wave = blockIdx.x * kWavesPerBlock + wave_in_block();
+    const int tile = wave / D.n;
+    const int col = wave - tile * D.n;
+    if (tile >= P.tiles) return;
+    const int nvalid = min(P.gamma - tile * Gt, Gt);
+    uint64_t frz[FPL];
+    bool any, all;
+    frozen_words<FPL>(P, tile, nvalid, frz, any, all);
+    float L[FPL];
+    vn_column<DVMAX, FPL>(D, P, tile, col, lane, any, frz, L);
+}
+
+// Variable-node pass that also returns the posterior and decisions in the
+// caller's frame-major layout (every iteration with early stopping, else the
+// last one).  A block of 16 waves covers 64 consecutive variables of one tile
+// (4 per wave); the posteriors go through LDS so that each store instruction
+// writes 64 consecutive values of one frame.  Frozen frames are not written.
+constexpr int kOutVars = 64;
+constexpr int kOutBlock = 1024;
+
+template <int DVMAX, int FPL>
+__global__ void __launch_bounds__(kOutBlock) vn_block_out_kernel(const QCDesc D, const BlockParams P, float* post,
+                                                                 uint8_t* bits_out) {
+    constexpr int Gt = 64 * FPL;
+    __shared__ float Ls[kOutVars][Gt + 1];
+    const int lane = threadIdx.x & 63;
+    const int wv = wave_in_block();
+    const int nchunks = (D.n + kOutVars - 1) / kOutVars;
+    const int tile = blockIdx.x / nchunks;
+    const int v0 = (blockIdx.x - tile * nchunks) * kOutVars;
+    const int nvalid = min(P.gamma - tile * Gt, Gt);
+    uint64_t frz[FPL];
+    bool any, all;
+    frozen_words<FPL>(P, tile, nvalid, frz, any, all);
+    if (P.early && v0 == 0 && wv == 0) publish_frozen<FPL>(P, tile, lane, frz);
+    if (P.early && all) return;   // the same for every wave of the block
+    constexpr int per_wave = kOutVars / (kOutBlock / 64);
+#pragma unroll 1
+    for (int i = 0; i < per_wave; ++i) {
+        const int vs = wv * per_wave + i;
+        const int col = v0 + vs;
+        if (col >= D.n) break;
+        float L[FPL];
+        vn_column<DVMAX, FPL>(D, P, tile, col, lane, any, frz, L);
+#pragma unroll
+        for (int f = 0; f < FPL; ++f) Ls[vs][lane * FPL + f] = L[f];
+    }
+    __syncthreads();
+    const int var = threadIdx.x & (kOutVars - 1);
+    const int col = v0 + var;
+    if (col >= D.n) return;
+    // this thread's frames fr = fr0, fr0 + 16, ... all lie in word fr0 % FPL
+    constexpr int fstep = kOutBlock / kOutVars;
+    static_assert(fstep % FPL == 0, "frame stride must keep the flag word fixed");
+    const int fr0 = threadIdx.x / kOutVars;
+    const uint64_t fw = pick_word<FPL>(frz, fr0 % FPL);
+    for (int fr = fr0; fr < nvalid; fr += fstep) {
+        if (any && ((fw >> (fr / FPL)) & 1ull)) continue;
+        const float L = Ls[var][fr];
+        const size_t o = (size_t)(tile * Gt + fr) * D.n + col;
+        post[o] = clip30(L);
+        bits_out[o] = (uint8_t)(L < 0.0f);
     }
 }
 
@@ -532,23 +611,22 @@ __global__ void frame_status_kernel(const BlockParams P, int max_iters, int32_t*
     if (converged) converged[g] = (uint8_t)ok;
 }
 
-__global__ void fill_u64_kernel(uint64_t* p, size_t count, uint64_t v) {
-    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < count) p[i] = v;
-}
-
 // ---------------------------------------------------------------------------
 // kernels: layout changes (frame-major <-> packages), through LDS
 // ---------------------------------------------------------------------------
 
 // src [gamma][ld], columns col0 .. col0+ncols-1  ->  dst[tile*dstride + col*Gt + frame]
 // (frames >= gamma are written as 0).  64 columns x 64 frames per block.
+// Block (0, 0) also clears `zero_count` words at `zero` (flag words of a decode).
 __global__ void __launch_bounds__(256) to_packages_kernel(const float* __restrict__ src, int64_t ld, int64_t col0,
                                                           int ncols, int gamma, int gpad, int Gt,
-                                                          float* __restrict__ dst, int64_t dstride) {
+                                                          float* __restrict__ dst, int64_t dstride,
+                                                          uint64_t* __restrict__ zero, int64_t zero_count) {
     __shared__ float tileS[64][65];
     const int c0 = blockIdx.x * 64, f0 = blockIdx.y * 64;
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    if (zero && blockIdx.x == 0 && blockIdx.y == 0)
+        for (int64_t i = threadIdx.x; i < zero_count; i += 256) zero[i] = 0ull;
 #pragma unroll 4
     for (int r = ty; r < 64; r += 4) {
         const int g = f0 + r, c = c0 + tx;
@@ -807,7 +885,7 @@ static Tiling choose_tiling(int gamma, const ldpc_graph* g) {
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct BlockLayout {
-    size_t mu, msg, post, bits, unsat, frozen, total;
+    size_t mu, msg, bits, flags, flag_words, total;   // flags: unsat words, then frozen words
 };
 
 static BlockLayout block_layout(const ldpc_graph* g, const Tiling& t, int max_iters) {
@@ -816,10 +894,9 @@ static BlockLayout block_layout(const ldpc_graph* g, const Tiling& t, int max_it
     auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
     L.mu = take((size_t)t.gpad * g->n * sizeof(float));
     L.msg = take((size_t)t.gpad * g->E * sizeof(float));
-    L.post = take((size_t)t.gpad * g->n * sizeof(float));
     L.bits = take((size_t)t.tiles * g->n * t.fpl * sizeof(uint64_t));
-    L.unsat = take((size_t)(max_iters + 1) * t.tiles * t.fpl * sizeof(uint64_t));
-    L.frozen = take((size_t)(max_iters + 1) * t.tiles * t.fpl * sizeof(uint64_t));
+    L.flag_words = (size_t)(max_iters + 1) * t.tiles * t.fpl;
+    L.flags = take(2 * L.flag_words * sizeof(uint64_t));
     L.total = off;
     return L;
 }
@@ -891,26 +968,24 @@ static void run_block(const ldpc_graph* g, const float* llr, int gamma, int max_
     BlockParams P{};
     P.msg = reinterpret_cast<float*>(ws + lay.msg);
     P.mu = reinterpret_cast<const float*>(ws + lay.mu);
-    P.post = reinterpret_cast<float*>(ws + lay.post);
     P.bits = reinterpret_cast<uint64_t*>(ws + lay.bits);
-    P.unsat = reinterpret_cast<uint64_t*>(ws + lay.unsat);
-    P.frozen = reinterpret_cast<uint64_t*>(ws + lay.frozen);
+    P.unsat = reinterpret_cast<uint64_t*>(ws + lay.flags);
+    P.frozen = P.unsat + lay.flag_words;
     P.gamma = gamma;
     P.tiles = tl.tiles;
     P.early = early;
 
     {
-        const size_t words = (size_t)(max_iters + 1) * tl.tiles * FPL;
         timing::Scope ts(0, st);
-        fill_u64_kernel<<<(unsigned)((words + 255) / 256), 256, 0, st>>>(P.unsat, words, 0ull);
-        fill_u64_kernel<<<(unsigned)((words + 255) / 256), 256, 0, st>>>(P.frozen, words, 0ull);
         dim3 grid((g->n + 63) / 64, tl.gpad / 64);
         to_packages_kernel<<<grid, 256, 0, st>>>(llr, g->n, 0, g->n, gamma, tl.gpad, tl.gt,
-                                                 reinterpret_cast<float*>(ws + lay.mu), (int64_t)g->n * tl.gt);
+                                                 reinterpret_cast<float*>(ws + lay.mu), (int64_t)g->n * tl.gt,
+                                                 P.unsat, (int64_t)(2 * lay.flag_words));
     }
     const int dcc = dc_class(D.dc_max), dvc = dv_class(D.dv_max);
     const unsigned cn_grid = grid_for_waves((int64_t)D.m * tl.tiles);
     const unsigned vn_grid = grid_for_waves((int64_t)D.n * tl.tiles);
+    const unsigned out_grid = (unsigned)(((D.n + kOutVars - 1) / kOutVars) * tl.tiles);
     for (int it = 1; it <= max_iters; ++it) {
         P.iter = it;
         P.last = (it == max_iters);
@@ -922,7 +997,11 @@ static void run_block(const ldpc_graph* g, const float* llr, int gamma, int max_
         }
         {
             timing::Scope ts(2, st);
-            LDPC_DV_SWITCH(dvc, (vn_block_kernel<DV, FPL><<<vn_grid, kBlock, 0, st>>>(D, P)));
+            if (early || P.last) {
+                LDPC_DV_SWITCH(dvc, (vn_block_out_kernel<DV, FPL><<<out_grid, kOutBlock, 0, st>>>(D, P, post, bits)));
+            } else {
+                LDPC_DV_SWITCH(dvc, (vn_block_kernel<DV, FPL><<<vn_grid, kBlock, 0, st>>>(D, P)));
+            }
         }
     }
     P.iter = max_iters;
@@ -930,12 +1009,6 @@ static void run_block(const ldpc_graph* g, const float* llr, int gamma, int max_
         timing::Scope ts(3, st);
         const int64_t threads = (int64_t)D.m * tl.tiles;
         syndrome_kernel<FPL><<<(unsigned)((threads + kBlock - 1) / kBlock), kBlock, 0, st>>>(D, P);
-    }
-    {
-        timing::Scope ts(4, st);
-        dim3 grid((g->n + 63) / 64, (gamma + 63) / 64);
-        from_packages_kernel<<<grid, 256, 0, st>>>(P.post, (int64_t)g->n * tl.gt, g->n, gamma, tl.gt, post, bits,
-                                                   g->n, 0);
     }
     if (iters || converged) {
         timing::Scope ts(5, st);
@@ -972,7 +1045,7 @@ static void run_window(const ldpc_graph* g, const float* llr, int gamma, int Wle
                 dim3 grid((npos * c + 63) / 64, tl.gpad / 64);
                 float* dst = reinterpret_cast<float*>(ws + lay.mu) + (size_t)(in_lo % lay.R) * c * tl.gt;
                 to_packages_kernel<<<grid, 256, 0, st>>>(llr, ld, (int64_t)in_lo * c, npos * c, gamma, tl.gpad,
-                                                         tl.gt, dst, (int64_t)lay.R * c * tl.gt);
+                                                         tl.gt, dst, (int64_t)lay.R * c * tl.gt, nullptr, 0);
             }
             {
                 timing::Scope ts(7, st);

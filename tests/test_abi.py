@@ -116,7 +116,7 @@ def test_workspace_size_rules():
     qc = ldpc.Graph.qc(synth.draw_qc_shifts(3, 6, 64, 1), 64)
     cc = ldpc.Graph.ldpccc_from_qc(synth.draw_qc_shifts(3, 6, 32, 2), 32, 16)
     s64 = qc.workspace_size(64, 20)
-    assert s64 >= 64 * 4 * (2 * qc.n + qc.info["E"])
+    assert s64 >= 64 * 4 * (qc.n + qc.info["E"])
     assert qc.workspace_size(1024, 20) > qc.workspace_size(512, 20) > s64
     assert qc.workspace_size(64, 30) >= s64
     assert cc.workspace_size(64, 1, window=6) > 0
