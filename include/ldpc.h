@@ -24,6 +24,10 @@
  *     Calls on different streams need different workspaces.
  *   - A graph is an immutable host object; it may be shared across threads
  *     and streams.
+ *   - Tuning: the environment variable LDPC_FRAMES_PER_LANE (1, 2 or 4)
+ *     overrides how many frames each GPU lane carries (frames are processed
+ *     in tiles of 64 * that many).  It changes speed and workspace size, never
+ *     results; read by ldpc_workspace_size and the decoders at each call.
  *   - Bit and LLR conventions (Sec. II-B): bit c maps to x = 1 - 2c; channel
  *     LLRs are mu = ln P(c=0|y)/P(c=1|y) = 2y/sigma^2; a hard decision is 0
  *     when the posterior LLR is >= 0 (Eq. 6; -0.0 decides 0).

@@ -39,6 +39,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <mutex>
 #include <vector>
 
@@ -868,11 +869,18 @@ static Tiling choose_tiling(int gamma, const ldpc_graph* g) {
     const int rs = row_slots(g);
     const int fmax = rs <= 8 ? 4 : (rs <= 16 ? 2 : 1);
     int fpl = 1;
-    for (int f : {4, 2}) {
-        if (f > fmax) continue;
-        const int gt = 64 * f;
-        const int pad = (gamma + gt - 1) / gt * gt;
-        if (pad * 8 <= base * 9) { fpl = f; break; }
+    // LDPC_FRAMES_PER_LANE (1, 2 or 4) overrides the choice, within the row-weight cap
+    const char* env = getenv("LDPC_FRAMES_PER_LANE");
+    const int forced = env ? atoi(env) : 0;
+    if (forced == 1 || forced == 2 || forced == 4) {
+        fpl = std::min(forced, fmax);
+    } else {
+        for (int f : {4, 2}) {
+            if (f > fmax) continue;
+            const int gt = 64 * f;
+            const int pad = (gamma + gt - 1) / gt * gt;
+            if (pad * 8 <= base * 9) { fpl = f; break; }
+        }
     }
     Tiling t;
     t.fpl = fpl;
