@@ -87,10 +87,36 @@ def window_algorithmic_bytes(info, W: int, gamma: int):
     return {"window_check_node": cn * gamma / L, "window_variable_node": vn * gamma / L}
 
 
-def bench_window(args):
-    """Sliding-window decoding of the LDPC convolutional code unwrapped from
-    the 3x6 base at p = 512: 128 positions (c = 1024 bits) + 2 tail layers,
-    512 streams, W = 6, 10 iterations per window."""
+def pipeline_algorithmic_bytes(info, I: int, gamma: int):
+    """Average algorithmic bytes per pipelined-decoder launch: a check-node
+    launch reads beta and writes alpha on every edge of its layers, a
+    variable-node launch reads alpha and mu and writes beta on every edge of
+    its frames (averaged over all slots, start-up and drain included)."""
+    c, ms, L, layers = info["c"], info["ms"], info["positions"], info["layers"]
+    per_pair = info["Jb"] * info["Lb"] * info["p"]
+    last = L - 1 + ms + (I - 1) * (ms + 1)
+    cn = vn = ncn = nvn = 0
+    for t in range(last + 1):
+        lays = [t - (i - 1) * (ms + 1) for i in range(1, I + 1)]
+        lays = [x for x in lays if 0 <= x < layers]
+        frames = [x - ms for x in [t - (i - 1) * (ms + 1) for i in range(1, I + 1)]]
+        frames = [f for f in frames if 0 <= f < L]
+        e_cn = sum(per_pair for x in lays for d in range(ms + 1) if 0 <= x - d < L)
+        e_vn = sum(per_pair for f in frames for d in range(ms + 1) if f + d < layers)
+        if lays:
+            cn += 8 * e_cn
+            ncn += 1
+        if frames:
+            vn += 8 * e_vn + 4 * c * len(frames)
+            nvn += 1
+    return {"pipeline_check_node": cn * gamma / ncn, "pipeline_variable_node": vn * gamma / nvn}
+
+
+def bench_window(args, pipeline: bool = False):
+    """The LDPC convolutional code unwrapped from the 3x6 base at p = 512:
+    128 positions (c = 1024 bits) + 2 tail layers, 512 streams; sliding-window
+    decoding with W = 6 and 10 iterations per window, or the pipelined decoder
+    with 20 processors."""
     import torch
 
     import synth
@@ -108,8 +134,15 @@ def bench_window(args):
     bits = torch.empty((gamma, n), dtype=torch.uint8, device=dev)
     ws = ldpc.workspace(g, gamma, 1, W, dev)
 
+    I = spec["pipeline_iters"]
+    if pipeline:
+        ws = ldpc.workspace(g, gamma, I, 0, dev)
+
     def step():
-        ldpc.decode_window(g, llr, W, K, out=(post, bits), ws=ws)
+        if pipeline:
+            ldpc.decode_pipeline(g, llr, I, out=(post, bits), ws=ws)
+        else:
+            ldpc.decode_window(g, llr, W, K, out=(post, bits), ws=ws)
 
     for _ in range(args.warmup):
         step()
@@ -128,26 +161,33 @@ def bench_window(args):
     torch.cuda.synchronize()
     ldpc.timing_enable(False)
     per_kernel = ldpc.timing_read()
-    algo = window_algorithmic_bytes(g.info, W, gamma)
+    algo = pipeline_algorithmic_bytes(g.info, I, gamma) if pipeline else window_algorithmic_bytes(g.info, W, gamma)
     dom = max(algo, key=lambda k: per_kernel[k][1])
     launches, ms = per_kernel[dom]
     avg_s = ms / launches * 1e-3
     achieved = algo[dom] / avg_s / 1e9
     ber = float(bits.float().mean().item())
+    if pipeline:
+        metric = "coded Mbit/s, pipelined LDPC-CC decoding (p=512, 128 positions, 20 processors, 512 streams)"
+        sched = f"pipelined decoder with {I} processors"
+    else:
+        metric = "coded Mbit/s, sliding-window LDPC-CC decoding (p=512, 128 positions, W=6, 10 iterations/window, 512 streams)"
+        sched = f"window {W}, {K} iterations per window"
     line = {
-        "metric": "coded Mbit/s, sliding-window LDPC-CC decoding (p=512, 128 positions, W=6, 10 iterations/window, 512 streams)",
+        "metric": metric,
         "value": round(gamma * n / (ms_per_step * 1e-3) / 1e6, 2), "unit": "coded Mbit/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"LDPC convolutional code unwrapped from the 3x6 base at p=512: {spec['positions']} "
                                f"positions x c={g.info['c']} bits + {g.info['ms']} tail layers; {gamma} streams; "
-                               f"window {W}, {K} iterations per window; all-zero codeword, BPSK/AWGN "
-                               f"{spec['ebn0_db']} dB", "n": n, "gamma": gamma, "window": W,
-                   "iters_per_window": K, "bit_error_rate": ber},
+                               f"{sched}; all-zero codeword, BPSK/AWGN {spec['ebn0_db']} dB",
+                   "n": n, "gamma": gamma, "schedule": "pipeline" if pipeline else "window",
+                   "window": None if pipeline else W, "iters_per_window": None if pipeline else K,
+                   "processors": I if pipeline else None, "bit_error_rate": ber},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
                      "avg_launch_us": round(avg_s * 1e6, 2), "algorithmic_bytes_per_launch": round(algo[dom]),
-                     "note": "window working set (~67 MB) is cache-resident; the fraction is of HBM peak"},
+                     "note": "fraction of HBM peak; the window ring (~67 MB) is cache-resident"},
         "cpu_baseline": None,
         "kernels": {k: {"launches": v[0], "avg_us": round(v[1] / v[0] * 1e3, 2)} for k, v in per_kernel.items() if v[0]},
     }
@@ -180,8 +220,9 @@ def main():
     ap.add_argument("--iters", type=int, default=20)
     ap.add_argument("--cpu-sample", type=int, default=96, help="frames decoded by the FP64 reference")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--workload", default="qc36_p3060", choices=["qc36_p3060", "cc36_p512"],
-                    help="qc36_p3060: the block-code benchmark; cc36_p512: the convolutional-code window decoder")
+    ap.add_argument("--workload", default="qc36_p3060", choices=["qc36_p3060", "cc36_p512", "cc36_p512_pipeline"],
+                    help="qc36_p3060: the block-code benchmark; cc36_p512: the convolutional-code window "
+                         "decoder; cc36_p512_pipeline: the pipelined convolutional-code decoder")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run 5 device-to-device copies of BYTES (counter calibration) and exit")
     args = ap.parse_args()
@@ -200,8 +241,8 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
-    if args.workload == "cc36_p512":
-        bench_window(args)
+    if args.workload in ("cc36_p512", "cc36_p512_pipeline"):
+        bench_window(args, pipeline=args.workload.endswith("pipeline"))
         return
 
     import numpy as np

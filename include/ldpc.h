@@ -131,10 +131,12 @@ ldpc_status ldpc_graph_get_info(const ldpc_graph* g, ldpc_graph_info* info);
 void ldpc_graph_destroy(ldpc_graph* g);
 
 /*
- * Device workspace needed by ldpc_decode (window == 0) or ldpc_decode_window
- * (window = W >= 1) for `gamma` frames and at most `max_iters` iterations
- * (per window for the window decoder).  Errors: EINVAL, EUNSUPPORTED
- * (the block decoder on a convolutional graph or the reverse).
+ * Device workspace needed for `gamma` frames by ldpc_decode (QC graph,
+ * window == 0, at most `max_iters` iterations), ldpc_decode_window
+ * (convolutional graph, window = W >= ms + 1; max_iters is ignored but must be
+ * >= 1) or ldpc_decode_pipeline (convolutional graph, window == 0, max_iters =
+ * number of processors).  Errors: EINVAL, EUNSUPPORTED (a window on a QC
+ * graph; W or processors above 64).
  */
 ldpc_status ldpc_workspace_size(const ldpc_graph* g, int32_t gamma, int32_t max_iters,
                                 int32_t window, size_t* bytes);
@@ -179,13 +181,33 @@ ldpc_status ldpc_decode(const ldpc_graph* g, const float* llr, int32_t gamma, in
  *   llr   device, float [gamma][positions * c]
  *   post  device, float [gamma][positions * c]: clip(posterior, +-30)
  *   bits  device, uint8 [gamma][positions * c]
- *   W     window length in positions, ms + 1 <= W
+ *   W     window length in positions, ms + 1 <= W <= 64
  * Errors: EINVAL (QC graph, W < ms+1, iters_per_window < 1, NULL pointers),
  * EWORKSPACE, EHIP.
  */
 ldpc_status ldpc_decode_window(const ldpc_graph* conv, const float* llr, int32_t gamma, int32_t W,
                                int32_t iters_per_window, float* post, uint8_t* bits,
                                void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * Pipelined decoding of `gamma` independent streams of a terminated
+ * convolutional graph with `iters` processors (Algorithm 2; Sec. IV-B): at
+ * time slot t frame t enters processor 1 with beta = clip(mu); processor i
+ * (i = 1..iters) updates check layer t - (i-1)(ms+1) (horizontal step, all
+ * processors first) and then frame t - (i-1)(ms+1) - ms (vertical step); the
+ * frame leaving the last processor is decided.  Slots continue until the
+ * last frame has left.  Every check layer and every frame is thereby updated
+ * exactly `iters` times, in flooding order, so the result equals `iters`
+ * flooding iterations on the whole terminated chain while the decoder holds
+ * only iters * (ms+1) frames (workspace from
+ * ldpc_workspace_size(conv, gamma, iters, 0)).
+ *   llr, post, bits as for ldpc_decode_window; 1 <= iters <= 64.
+ * Errors: EINVAL (QC graph, iters < 1, NULL pointers), EUNSUPPORTED
+ * (iters > 64), EWORKSPACE, EHIP.
+ */
+ldpc_status ldpc_decode_pipeline(const ldpc_graph* conv, const float* llr, int32_t gamma, int32_t iters,
+                                 float* post, uint8_t* bits, void* workspace, size_t workspace_bytes,
+                                 void* stream);
 
 /* Static description of a status code. */
 const char* ldpc_status_str(ldpc_status s);
@@ -197,11 +219,12 @@ const char* ldpc_status_str(ldpc_status s);
  * class, the launch count and the summed device time in milliseconds, then
  * clears them.  Classes (index into the arrays, capacity >= LDPC_TIMING_CLASSES):
  *   0 ingest, 1 check-node, 2 variable-node, 3 syndrome, 4 output,
- *   5 frame status, 6 window ingest, 7 window init, 8 window check-node,
- *   9 window variable-node, 10 window output.
+ *   5 frame status, 6 window ingest, 7 window check-node,
+ *   8 window variable-node, 9 pipeline ingest, 10 pipeline check-node,
+ *   11 pipeline variable-node.
  * ldpc_kernel_class_name returns a static name for a class index.
  */
-#define LDPC_TIMING_CLASSES 11
+#define LDPC_TIMING_CLASSES 12
 ldpc_status ldpc_timing_enable(int32_t enable);
 ldpc_status ldpc_timing_read(int64_t* launches, double* total_ms, int32_t capacity);
 const char* ldpc_kernel_class_name(int32_t cls);

@@ -17,9 +17,10 @@ Contents
         number of code positions;
       - `edge_lookup_tables` -- the LUT_c / LUT_v index tables of Sec. IV-A
         for message packages stored row by row, left to right;
-  * `decode_block` / `decode_window` -- ctypes wrappers of the C decoders in
-    bp.c (Algorithm 1 in FP64; the sliding-window schedule for the
-    terminated convolutional code);
+  * `decode_block` / `decode_window` / `decode_pipeline` -- ctypes wrappers of
+    the C decoders in bp.c (Algorithm 1 in FP64; the sliding-window schedule
+    and the pipelined schedule of Algorithm 2 for the terminated
+    convolutional code);
   * `map_decode` -- bitwise MAP by enumerating every codeword (tiny codes).
 """
 from __future__ import annotations
@@ -207,6 +208,8 @@ def _lib():
     lib.oracle_decode_window.restype = ci
     lib.oracle_decode_window.argtypes = [ci, ci, vp, vp, vp, vp, ci, ci, vp, ci, ci, ci, cd, ci,
                                          vp, vp]
+    lib.oracle_decode_pipeline.restype = ci
+    lib.oracle_decode_pipeline.argtypes = [ci, ci, vp, vp, vp, vp, ci, ci, ci, vp, ci, ci, cd, ci, vp, vp]
     return lib
 
 
@@ -257,6 +260,25 @@ def decode_window(H: SparseH, llr, W: int, K: int, lmax: float = LMAX, nthreads:
                                      _ptr(post), _ptr(bits))
     if rc != 0:
         raise ValueError("oracle_decode_window rejected its input")
+    return dict(post=post, bits=bits)
+
+
+def decode_pipeline(H: SparseH, llr, I: int, ms: int, lmax: float = LMAX, nthreads: int = 0):
+    """Algorithm 2 with I processors on a terminated convolutional code built
+    by `unwrap_qc` (syndrome-former memory ms).  Returns dict(post, bits)."""
+    if H.layer_of_row is None:
+        raise ValueError("H must come from unwrap_qc")
+    y = np.ascontiguousarray(np.asarray(llr, dtype=np.float32))
+    if y.ndim != 2 or y.shape[1] != H.n:
+        raise ValueError("llr must be [gamma, n]")
+    g = y.shape[0]
+    post = np.empty((g, H.n), dtype=np.float64)
+    bits = np.empty((g, H.n), dtype=np.uint8)
+    rc = _lib().oracle_decode_pipeline(H.n, H.m, _ptr(H.row_ptr), _ptr(H.col_idx),
+                                       _ptr(H.layer_of_row), _ptr(H.pos_of_col), H.nlayers, H.npos, int(ms),
+                                       _ptr(y), g, int(I), float(lmax), int(nthreads), _ptr(post), _ptr(bits))
+    if rc != 0:
+        raise ValueError("oracle_decode_pipeline rejected its input")
     return dict(post=post, bits=bits)
 
 

@@ -31,7 +31,9 @@
  *
  * The window decoder for terminated LDPC convolutional codes (Sec. II-C/E)
  * runs the same two steps restricted to a sliding window of check layers and
- * code positions; see oracle_decode_window below.
+ * code positions; see oracle_decode_window below.  The pipelined decoder of
+ * Algorithm 2 runs them on a stream of code frames with I processors; see
+ * oracle_decode_pipeline.
  */
 #include <math.h>
 #include <stdint.h>
@@ -320,6 +322,115 @@ int oracle_decode_window(int n, int m, const int32_t* row_ptr, const int32_t* co
                             }
                             post[(size_t)g * n + v] = clipd(tot, lmax);
                             bits[(size_t)g * n + v] = (uint8_t)(tot < 0.0);
+                        }
+                    }
+                }
+            } else {
+                #pragma omp atomic write
+                status = -1;
+            }
+            free(beta); free(alpha); free(th);
+        }
+    }
+    free(lay_ptr); free(lay_row); free(pos_ptr); free(pos_col);
+    free_colview(&cv);
+    return status;
+}
+
+/*
+ * Pipelined decoder of Algorithm 2 (Sec. II-E, IV-B) on a terminated LDPC
+ * convolutional code: I processors, each spanning m_s + 1 code frames.
+ * At time slot t = 0, 1, ...:
+ *   - frame t enters processor 1 (if it exists): beta = clip(mu) on its edges;
+ *   - horizontal step: processor i (i = 1..I) updates check layer
+ *     t - (i-1)(m_s+1) (if it exists) from the current beta of its edges;
+ *   - vertical step: processor i updates frame t - (i-1)(m_s+1) - m_s (if it
+ *     exists) from the current alpha of all its edges;
+ *   - the frame leaving processor I is decided from its a-posteriori LLR.
+ * All horizontal steps of a slot precede all vertical steps.  Slots run until
+ * the last frame has left processor I.
+ */
+int oracle_decode_pipeline(int n, int m, const int32_t* row_ptr, const int32_t* col_idx,
+                           const int32_t* layer_of_row, const int32_t* pos_of_col,
+                           int nlayers, int npos, int ms, const float* llr, int gamma, int I,
+                           double lmax, int nthreads, double* post, uint8_t* bits) {
+    if (n < 0 || m < 0 || gamma < 0 || I < 1 || ms < 0 || npos < 0 || nlayers < 0) return -1;
+    colview cv;
+    if (build_colview(n, m, row_ptr, col_idx, &cv)) { free_colview(&cv); return -1; }
+    int ne = row_ptr[m];
+    int32_t* lay_ptr = (int32_t*)calloc((size_t)nlayers + 1, sizeof(int32_t));
+    int32_t* lay_row = (int32_t*)malloc(sizeof(int32_t) * (size_t)(m > 0 ? m : 1));
+    int32_t* pos_ptr = (int32_t*)calloc((size_t)npos + 1, sizeof(int32_t));
+    int32_t* pos_col = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    int status = 0;
+    if (!lay_ptr || !lay_row || !pos_ptr || !pos_col) status = -1;
+    for (int r = 0; r < m && !status; ++r) {
+        if (layer_of_row[r] < 0 || layer_of_row[r] >= nlayers) status = -1;
+        else lay_ptr[layer_of_row[r] + 1]++;
+    }
+    for (int v = 0; v < n && !status; ++v) {
+        if (pos_of_col[v] < 0 || pos_of_col[v] >= npos) status = -1;
+        else pos_ptr[pos_of_col[v] + 1]++;
+    }
+    if (!status) {
+        for (int t = 0; t < nlayers; ++t) lay_ptr[t + 1] += lay_ptr[t];
+        for (int t = 0; t < npos; ++t) pos_ptr[t + 1] += pos_ptr[t];
+        int32_t* fl = (int32_t*)calloc((size_t)nlayers + 1, sizeof(int32_t));
+        int32_t* fp = (int32_t*)calloc((size_t)npos + 1, sizeof(int32_t));
+        for (int r = 0; r < m; ++r) lay_row[lay_ptr[layer_of_row[r]] + fl[layer_of_row[r]]++] = r;
+        for (int v = 0; v < n; ++v) pos_col[pos_ptr[pos_of_col[v]] + fp[pos_of_col[v]]++] = v;
+        free(fl); free(fp);
+    }
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+    const int last_slot = npos - 1 + ms + (I - 1) * (ms + 1);
+    if (!status) {
+        #pragma omp parallel
+        {
+            double* beta = (double*)calloc((size_t)(ne > 0 ? ne : 1), sizeof(double));
+            double* alpha = (double*)calloc((size_t)(ne > 0 ? ne : 1), sizeof(double));
+            double* th = (double*)malloc(sizeof(double) * (size_t)max_row_weight(m, row_ptr));
+            if (beta && alpha && th) {
+                #pragma omp for schedule(dynamic, 1)
+                for (int g = 0; g < gamma; ++g) {
+                    const float* y = llr + (size_t)g * n;
+                    memset(beta, 0, sizeof(double) * (size_t)ne);
+                    memset(alpha, 0, sizeof(double) * (size_t)ne);
+                    for (int t = 0; t <= last_slot; ++t) {
+                        if (t < npos)
+                            for (int q = pos_ptr[t]; q < pos_ptr[t + 1]; ++q) {
+                                int v = pos_col[q];
+                                for (int k = cv.col_ptr[v]; k < cv.col_ptr[v + 1]; ++k)
+                                    beta[cv.col_edge[k]] = clipd((double)y[v], lmax);
+                            }
+                        for (int i = 1; i <= I; ++i) {
+                            int tau = t - (i - 1) * (ms + 1);
+                            if (tau < 0 || tau >= nlayers) continue;
+                            for (int q = lay_ptr[tau]; q < lay_ptr[tau + 1]; ++q)
+                                check_update(row_ptr, lay_row[q], beta, alpha, th);
+                        }
+                        for (int i = 1; i <= I; ++i) {
+                            int f = t - (i - 1) * (ms + 1) - ms;
+                            if (f < 0 || f >= npos) continue;
+                            for (int q = pos_ptr[f]; q < pos_ptr[f + 1]; ++q) {
+                                int v = pos_col[q];
+                                int k0 = cv.col_ptr[v], k1 = cv.col_ptr[v + 1];
+                                double tot = (double)y[v];
+                                for (int k = k0; k < k1; ++k) tot += alpha[cv.col_edge[k]];
+                                for (int k = k0; k < k1; ++k) {
+                                    double acc = (double)y[v];
+                                    for (int j = k0; j < k1; ++j)
+                                        if (j != k) acc += alpha[cv.col_edge[j]];
+                                    beta[cv.col_edge[k]] = clipd(acc, lmax);
+                                }
+                                if (i == I) {
+                                    post[(size_t)g * n + v] = clipd(tot, lmax);
+                                    bits[(size_t)g * n + v] = (uint8_t)(tot < 0.0);
+                                }
+                            }
                         }
                     }
                 }

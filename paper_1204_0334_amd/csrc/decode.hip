@@ -177,85 +177,106 @@ struct QCCol {
     }
 };
 
-// Window state of the convolutional decoder for one launch.
-struct WinState {
-    int s;        // target position
-    int lay_lo;   // first window layer (== s)
-    int lay_hi;   // last window layer
-    int R;        // ring slots
-    int eps;      // edge packages per ring slot = (ms+1)*Jb*Lb*p
+// Convolutional code.  A launch works on a list of "units": check layers
+// (check-node launches) or code positions (variable-node launches), with
+// everything that depends on the unit precomputed on the host: its ring slot,
+// its class (index mod T) and the range of positions / layers it exchanges
+// messages with.  The edges of position t live in ring slot t mod R, grouped
+// in blocks (d, rr, q) of p packages: package s of block (d, rr, q) is the
+// edge of check row s of circulant row rr of layer t + d and circulant column
+// q of position t.  The edge slots k of a check row (d = ms - k / Lb,
+// q = k % Lb, oldest position first) and of a variable (d = k / Jb,
+// rr = k % Jb) come from small tables, so no per-edge integer division is
+// done on the GPU.
+constexpr int kMaxUnits = 64;
+
+struct ConvUnits {
+    int n;                        // units in this launch
+    int ring;                     // R
+    int eps;                      // edge packages per ring slot: (ms+1) * Jb * Lb * p
+    int out_unit;                 // variable-node launch: unit whose posterior is returned, or -1
+    int32_t pos[kMaxUnits];       // check-node launch: layer tau; variable-node launch: position t
+    int32_t slot[kMaxUnits];      // ring slot of position pos[u]
+    int32_t cls[kMaxUnits];       // pos[u] mod T
+    int32_t lo[kMaxUnits];        // CN: alpha is written only on edges of positions >= lo
+                                  // VN: alphas of layers lo..hi are summed (others count as 0)
+    int32_t hi[kMaxUnits];
+};
+
+struct ConvSlots {
+    int8_t cn_dd[LDPC_MAX_ROW_WEIGHT], cn_q[LDPC_MAX_ROW_WEIGHT];
+    int8_t vn_dd[LDPC_MAX_COL_WEIGHT], vn_rr[LDPC_MAX_COL_WEIGHT];
 };
 
 __device__ __forceinline__ int sf_at(const ConvDesc& D, int cls, int dd, int rr, int q) {
     return D.sf[((cls * (D.ms + 1) + dd) * D.Jb + rr) * D.Lb + q];
 }
 
-// Window check row r: layer tau = lay_lo + r / (Jb p), circulant row rr,
-// offset s.  Edge k <-> (lag dd = ms - k / Lb, circulant column q = k % Lb):
-// position tau - dd, oldest position first.  Only edges of active positions
-// (>= s) receive alpha; edges of frozen positions keep their beta.
+// check row r of a launch: unit u, circulant row rr, offset s
 struct ConvRow {
-    int tau, rr, s, cls;
-    __device__ __forceinline__ ConvRow(const ConvDesc& D, const WinState& W, int r) {
+    int tau, rr, s, cls, slot0, lo;
+    __device__ __forceinline__ ConvRow(const ConvDesc& D, const ConvUnits& U, int r) {
         const int per = D.Jb * D.p;
-        const int l = r / per;
-        const int rem = r - l * per;
-        tau = W.lay_lo + l;
+        const int u = r / per;
+        const int rem = r - u * per;
         rr = rem / D.p;
         s = rem - rr * D.p;
-        cls = tau % D.T;
+        tau = U.pos[u];
+        cls = U.cls[u];
+        slot0 = U.slot[u];
+        lo = U.lo[u];
     }
-    __device__ __forceinline__ bool valid(const ConvDesc& D, int k) const {
+    __device__ __forceinline__ bool valid(const ConvDesc& D, const ConvSlots& S, int k) const {
         if (k >= (D.ms + 1) * D.Lb) return false;
-        const int dd = D.ms - k / D.Lb, q = k % D.Lb;
+        const int dd = S.cn_dd[k];
         const int t = tau - dd;
         if (t < 0 || t >= D.positions) return false;
-        return sf_at(D, cls, dd, rr, q) >= 0;
+        return sf_at(D, cls, dd, rr, S.cn_q[k]) >= 0;
     }
-    __device__ __forceinline__ int64_t pkg(const ConvDesc& D, const WinState& W, int k) const {
-        const int dd = D.ms - k / D.Lb, q = k % D.Lb;
-        const int slot = (tau - dd) % W.R;
-        return (int64_t)slot * W.eps + ((int64_t)((dd * D.Jb + rr) * D.Lb + q)) * D.p + s;
+    __device__ __forceinline__ int64_t pkg(const ConvDesc& D, const ConvSlots& S, const ConvUnits& U, int k) const {
+        const int dd = S.cn_dd[k];
+        int sl = slot0 - dd;
+        if (sl < 0) sl += U.ring;
+        return (int64_t)sl * U.eps + ((int64_t)((dd * D.Jb + rr) * D.Lb + S.cn_q[k])) * D.p + s;
     }
-    __device__ __forceinline__ bool writable(const ConvDesc& D, const WinState& W, int k) const {
-        return tau - (D.ms - k / D.Lb) >= W.s;
-    }
+    __device__ __forceinline__ bool writable(const ConvSlots& S, int k) const { return tau - S.cn_dd[k] >= lo; }
 };
 
-// Window variable r: position t = s + r / c, circulant column q, offset u.
-// Edge k <-> (lag dd = k / Jb, circulant row rr = k % Jb): layer t + dd.
+// variable column r of a launch: unit u, circulant column q, offset uu
 struct ConvCol {
-    int t, q, u, jc;
-    __device__ __forceinline__ ConvCol(const ConvDesc& D, const WinState& W, int r) {
-        const int pos = r / D.c;
-        const int rem = r - pos * D.c;
-        t = W.s + pos;
+    int t, q, uu, jc, slot, lo, hi, unit;
+    __device__ __forceinline__ ConvCol(const ConvDesc& D, const ConvUnits& U, int r) {
+        unit = r / D.c;
+        const int rem = r - unit * D.c;
         q = rem / D.p;
-        u = rem - q * D.p;
-        jc = t % D.T;
+        uu = rem - q * D.p;
+        t = U.pos[unit];
+        jc = U.cls[unit];
+        slot = U.slot[unit];
+        lo = U.lo[unit];
+        hi = U.hi[unit];
     }
-    __device__ __forceinline__ int shift(const ConvDesc& D, int k) const {
-        const int dd = k / D.Jb, rr = k % D.Jb;
-        return sf_at(D, (jc + dd) % D.T, dd, rr, q);
+    __device__ __forceinline__ int shift(const ConvDesc& D, const ConvSlots& S, int k) const {
+        const int dd = S.vn_dd[k];
+        int ic = jc + dd;
+        while (ic >= D.T) ic -= D.T;
+        return sf_at(D, ic, dd, S.vn_rr[k], q);
     }
-    __device__ __forceinline__ bool valid(const ConvDesc& D, int k) const {
+    __device__ __forceinline__ bool valid(const ConvDesc& D, const ConvSlots& S, int k) const {
         if (k >= (D.ms + 1) * D.Jb) return false;
-        if (t + k / D.Jb >= D.layers) return false;
-        return shift(D, k) >= 0;
+        if (t + S.vn_dd[k] >= D.layers) return false;
+        return shift(D, S, k) >= 0;
     }
-    __device__ __forceinline__ bool contributes(const WinState& W, const ConvDesc& D, int k) const {
-        return t + k / D.Jb <= W.lay_hi;
+    __device__ __forceinline__ bool contributes(const ConvSlots& S, int k) const {
+        const int tau = t + S.vn_dd[k];
+        return tau >= lo && tau <= hi;
     }
-    __device__ __forceinline__ int64_t pkg(const ConvDesc& D, const WinState& W, int k) const {
-        const int dd = k / D.Jb, rr = k % D.Jb;
-        int s = u - shift(D, k);
+    __device__ __forceinline__ int64_t pkg(const ConvDesc& D, const ConvSlots& S, const ConvUnits& U, int k) const {
+        int s = uu - shift(D, S, k);
         if (s < 0) s += D.p;
-        const int slot = t % W.R;
-        return (int64_t)slot * W.eps + ((int64_t)((dd * D.Jb + rr) * D.Lb + q)) * D.p + s;
+        return (int64_t)slot * U.eps + ((int64_t)((S.vn_dd[k] * D.Jb + S.vn_rr[k]) * D.Lb + q)) * D.p + s;
     }
-    __device__ __forceinline__ int64_t mu_index(const ConvDesc& D, const WinState& W) const {
-        return (int64_t)(t % W.R) * D.c + q * D.p + u;
-    }
+    __device__ __forceinline__ int64_t mu_index(const ConvDesc& D) const { return (int64_t)slot * D.c + q * D.p + uu; }
 };
 
 // ---------------------------------------------------------------------------
@@ -676,26 +697,26 @@ __global__ void __launch_bounds__(256) from_packages_kernel(const float* __restr
 }
 
 // ---------------------------------------------------------------------------
-// kernels: convolutional code, sliding window
+// kernels: convolutional code (window and pipelined schedules)
 // ---------------------------------------------------------------------------
 
-struct WinParams {
-    float* msg;       // [tiles][R*eps][Gt]
-    const float* mu;  // [tiles][R*c][Gt]
-    float* stage;     // [tiles][c][Gt] posterior of the decided position
-    int tiles, rows, decide;
+struct ConvParams {
+    float* msg;       // [tiles][R * eps][Gt]
+    float* mu;        // [tiles][R * c][Gt]
+    int tiles, rows, gamma;
 };
 
 template <int DCMAX, int FPL>
-__global__ void __launch_bounds__(kBlock) cn_window_kernel(const ConvDesc D, const WinState W, const WinParams P) {
+__global__ void __launch_bounds__(kBlock) conv_cn_kernel(const ConvDesc D, const ConvSlots S, const ConvUnits U,
+                                                         const ConvParams P) {
     constexpr int Gt = 64 * FPL;
     const int lane = threadIdx.x & 63;
     const int wave = blockIdx.x * kWavesPerBlock + wave_in_block();
     const int tile = wave / P.rows;
     const int row = wave - tile * P.rows;
     if (tile >= P.tiles) return;
-    const ConvRow R(D, W, row);
-    float* mt = P.msg + (size_t)tile * W.R * W.eps * Gt + (size_t)lane * FPL;
+    const ConvRow R(D, U, row);
+    float* mt = P.msg + (size_t)tile * U.ring * U.eps * Gt + (size_t)lane * FPL;
     float in[DCMAX][FPL];
     float t[FPL][DCMAX], q[FPL][DCMAX];
     uint32_t sgn[FPL];
@@ -703,8 +724,8 @@ __global__ void __launch_bounds__(kBlock) cn_window_kernel(const ConvDesc D, con
     for (int f = 0; f < FPL; ++f) sgn[f] = 0;
 #pragma unroll
     for (int k = 0; k < DCMAX; ++k) {
-        if (R.valid(D, k)) {
-            load_frames<FPL>(mt + (size_t)R.pkg(D, W, k) * Gt, in[k]);
+        if (R.valid(D, S, k)) {
+            load_frames<FPL>(mt + (size_t)R.pkg(D, S, U, k) * Gt, in[k]);
         } else {
 #pragma unroll
             for (int f = 0; f < FPL; ++f) in[k][f] = 0.0f;
@@ -712,7 +733,7 @@ __global__ void __launch_bounds__(kBlock) cn_window_kernel(const ConvDesc D, con
     }
 #pragma unroll
     for (int k = 0; k < DCMAX; ++k) {
-        const bool ok = R.valid(D, k);
+        const bool ok = R.valid(D, S, k);
 #pragma unroll
         for (int f = 0; f < FPL; ++f) {
             if (ok) {
@@ -731,48 +752,45 @@ __global__ void __launch_bounds__(kBlock) cn_window_kernel(const ConvDesc D, con
         boxplus_fb<DCMAX>(t[f], q[f], mag);
 #pragma unroll
         for (int k = 0; k < DCMAX; ++k) {
-            const uint32_t s = sgn[f] ^ (__float_as_uint(in[k][f]) & 0x80000000u);
-            outv[k][f] = __uint_as_float(__float_as_uint(mag[k]) | s);
+            const uint32_t sg = sgn[f] ^ (__float_as_uint(in[k][f]) & 0x80000000u);
+            outv[k][f] = __uint_as_float(__float_as_uint(mag[k]) | sg);
         }
     }
 #pragma unroll
     for (int k = 0; k < DCMAX; ++k)
-        if (R.valid(D, k) && R.writable(D, W, k)) store_frames<FPL>(mt + (size_t)R.pkg(D, W, k) * Gt, outv[k]);
+        if (R.valid(D, S, k) && R.writable(S, k)) store_frames<FPL>(mt + (size_t)R.pkg(D, S, U, k) * Gt, outv[k]);
 }
 
+// One variable column: betas on every existing edge, posterior from the
+// alphas of layers lo..hi.
 template <int DVMAX, int FPL>
-__global__ void __launch_bounds__(kBlock) vn_window_kernel(const ConvDesc D, const WinState W, const WinParams P) {
+__device__ __forceinline__ void conv_vn_column(const ConvDesc& D, const ConvSlots& S, const ConvUnits& U,
+                                               const ConvParams& P, const ConvCol& C, int tile, int lane,
+                                               float (&L)[FPL]) {
     constexpr int Gt = 64 * FPL;
-    const int lane = threadIdx.x & 63;
-    const int wave = blockIdx.x * kWavesPerBlock + wave_in_block();
-    const int tile = wave / P.rows;
-    const int col = wave - tile * P.rows;
-    if (tile >= P.tiles) return;
-    const ConvCol C(D, W, col);
     const size_t lane_off = (size_t)lane * FPL;
-    float* mt = P.msg + (size_t)tile * W.R * W.eps * Gt + lane_off;
+    float* mt = P.msg + (size_t)tile * U.ring * U.eps * Gt + lane_off;
     float mu[FPL];
-    load_frames<FPL>(P.mu + ((size_t)tile * W.R * D.c + C.mu_index(D, W)) * Gt + lane_off, mu);
+    load_frames<FPL>(P.mu + ((size_t)tile * U.ring * D.c + C.mu_index(D)) * Gt + lane_off, mu);
     float a[DVMAX][FPL];
 #pragma unroll
     for (int k = 0; k < DVMAX; ++k) {
-        if (C.valid(D, k) && C.contributes(W, D, k)) {
-            load_frames<FPL>(mt + (size_t)C.pkg(D, W, k) * Gt, a[k]);
+        if (C.valid(D, S, k) && C.contributes(S, k)) {
+            load_frames<FPL>(mt + (size_t)C.pkg(D, S, U, k) * Gt, a[k]);
         } else {
 #pragma unroll
             for (int f = 0; f < FPL; ++f) a[k][f] = 0.0f;
         }
     }
-    float L[FPL];
     float b[DVMAX][FPL];
 #pragma unroll
     for (int f = 0; f < FPL; ++f) {
         float suf[DVMAX];
-        float S = 0.0f;
+        float Ssum = 0.0f;
 #pragma unroll
         for (int k = DVMAX - 1; k >= 0; --k) {
-            suf[k] = S;
-            S += a[k][f];
+            suf[k] = Ssum;
+            Ssum += a[k][f];
         }
         float pre = 0.0f;
 #pragma unroll
@@ -784,30 +802,110 @@ __global__ void __launch_bounds__(kBlock) vn_window_kernel(const ConvDesc D, con
     }
 #pragma unroll
     for (int k = 0; k < DVMAX; ++k)
-        if (C.valid(D, k)) store_frames<FPL>(mt + (size_t)C.pkg(D, W, k) * Gt, b[k]);
-    if (P.decide && C.t == W.s)
-        store_frames<FPL>(P.stage + ((size_t)tile * D.c + C.q * D.p + C.u) * Gt + lane_off, L);
+        if (C.valid(D, S, k)) store_frames<FPL>(mt + (size_t)C.pkg(D, S, U, k) * Gt, b[k]);
 }
 
-// Positions entering the window: beta = clip(mu) on all their edges.
 template <int DVMAX, int FPL>
-__global__ void __launch_bounds__(kBlock) init_window_kernel(const ConvDesc D, const WinState W, const WinParams P) {
-    constexpr int Gt = 64 * FPL;
+__global__ void __launch_bounds__(kBlock) conv_vn_kernel(const ConvDesc D, const ConvSlots S, const ConvUnits U,
+                                                         const ConvParams P) {
     const int lane = threadIdx.x & 63;
     const int wave = blockIdx.x * kWavesPerBlock + wave_in_block();
     const int tile = wave / P.rows;
     const int col = wave - tile * P.rows;
     if (tile >= P.tiles) return;
-    const ConvCol C(D, W, col);
-    const size_t lane_off = (size_t)lane * FPL;
-    float* mt = P.msg + (size_t)tile * W.R * W.eps * Gt + lane_off;
-    float mu[FPL];
-    load_frames<FPL>(P.mu + ((size_t)tile * W.R * D.c + C.mu_index(D, W)) * Gt + lane_off, mu);
+    const ConvCol C(D, U, col);
+    float L[FPL];
+    conv_vn_column<DVMAX, FPL>(D, S, U, P, C, tile, lane, L);
+}
+
+// Variable-node launch that also returns the posterior and decisions of unit
+// U.out_unit in the caller's frame-major layout [gamma][positions * c], through
+// LDS as in the block decoder: 16 waves cover 64 consecutive columns.
+template <int DVMAX, int FPL>
+__global__ void __launch_bounds__(kOutBlock) conv_vn_out_kernel(const ConvDesc D, const ConvSlots S,
+                                                                const ConvUnits U, const ConvParams P, float* post,
+                                                                uint8_t* bits_out) {
+    constexpr int Gt = 64 * FPL;
+    __shared__ float Ls[kOutVars][Gt + 1];
+    const int lane = threadIdx.x & 63;
+    const int wv = wave_in_block();
+    const int nchunks = (P.rows + kOutVars - 1) / kOutVars;
+    const int tile = blockIdx.x / nchunks;
+    const int c0 = (blockIdx.x - tile * nchunks) * kOutVars;
+    constexpr int per_wave = kOutVars / (kOutBlock / 64);
+#pragma unroll 1
+    for (int i = 0; i < per_wave; ++i) {
+        const int vs = wv * per_wave + i;
+        const int col = c0 + vs;
+        if (col >= P.rows) break;
+        const ConvCol C(D, U, col);
+        float L[FPL];
+        conv_vn_column<DVMAX, FPL>(D, S, U, P, C, tile, lane, L);
 #pragma unroll
-    for (int f = 0; f < FPL; ++f) mu[f] = clip30(mu[f]);
-#pragma unroll
-    for (int k = 0; k < DVMAX; ++k)
-        if (C.valid(D, k)) store_frames<FPL>(mt + (size_t)C.pkg(D, W, k) * Gt, mu);
+        for (int f = 0; f < FPL; ++f) Ls[vs][lane * FPL + f] = L[f];
+    }
+    __syncthreads();
+    const int var = threadIdx.x & (kOutVars - 1);
+    const int col = c0 + var;
+    if (col >= P.rows || col / D.c != U.out_unit) return;
+    const int64_t ld = (int64_t)D.positions * D.c;
+    const int64_t oc = (int64_t)U.pos[U.out_unit] * D.c + (col - U.out_unit * D.c);
+    const int nvalid = min(P.gamma - tile * Gt, Gt);
+    for (int fr = threadIdx.x / kOutVars; fr < nvalid; fr += kOutBlock / kOutVars) {
+        const float L = Ls[var][fr];
+        const size_t o = (size_t)(tile * Gt + fr) * ld + oc;
+        post[o] = clip30(L);
+        bits_out[o] = (uint8_t)(L < 0.0f);
+    }
+}
+
+// Positions t0 .. t0+npos-1 enter the ring: channel LLRs go from the caller's
+// layout into the mu ring (through LDS), and every edge of the entering
+// positions starts with beta = clip(mu).  64 columns x 64 frames per block.
+__global__ void __launch_bounds__(256) conv_ingest_kernel(const ConvDesc D, const ConvSlots S, const ConvUnits U,
+                                                          const ConvParams P, const float* __restrict__ llr, int t0,
+                                                          int npos, int gpad, int Gt) {
+    __shared__ float tileS[64][65];
+    const int ncols = npos * D.c;
+    const int64_t ld = (int64_t)D.positions * D.c;
+    const int c0 = blockIdx.x * 64, f0 = blockIdx.y * 64;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+#pragma unroll 4
+    for (int r = ty; r < 64; r += 4) {
+        const int g = f0 + r, cc = c0 + tx;
+        float v = 0.0f;
+        if (g < P.gamma && cc < ncols) v = llr[(size_t)g * ld + (int64_t)t0 * D.c + cc];
+        tileS[r][tx] = v;
+    }
+    __syncthreads();
+    const int nslots = (D.ms + 1) * D.Jb;
+#pragma unroll 1
+    for (int r = ty; r < 64; r += 4) {
+        const int cc = c0 + r, g = f0 + tx;
+        if (cc >= ncols || g >= gpad) continue;
+        const int tile = g / Gt, fl = g - tile * Gt;
+        const int pu = cc / D.c;
+        const int rem = cc - pu * D.c;
+        const int t = t0 + pu;
+        const int q = rem / D.p, uu = rem - q * D.p;
+        const int slot = t % U.ring;
+        const float mu = tileS[tx][r];
+        P.mu[((size_t)tile * U.ring * D.c + (size_t)slot * D.c + rem) * Gt + fl] = mu;
+        const float b = clip30(mu);
+        const int jc = t % D.T;
+        for (int k = 0; k < nslots; ++k) {
+            const int dd = S.vn_dd[k], rr = S.vn_rr[k];
+            if (t + dd >= D.layers) continue;
+            int ic = jc + dd;
+            while (ic >= D.T) ic -= D.T;
+            const int a = sf_at(D, ic, dd, rr, q);
+            if (a < 0) continue;
+            int sidx = uu - a;
+            if (sidx < 0) sidx += D.p;
+            const int64_t pk = (int64_t)slot * U.eps + ((int64_t)((dd * D.Jb + rr) * D.Lb + q)) * D.p + sidx;
+            P.msg[((size_t)tile * U.ring * U.eps + pk) * Gt + fl] = b;
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -909,23 +1007,41 @@ static BlockLayout block_layout(const ldpc_graph* g, const Tiling& t, int max_it
     return L;
 }
 
-struct WinLayout {
+// Ring of code positions for the convolutional decoders (window: the W
+// active positions plus the ms frozen ones; pipeline: the I (ms+1) frames held
+// by the I processors).
+struct ConvLayout {
     int R, eps;
-    size_t mu, msg, stage, total;
+    size_t mu, msg, total;
 };
 
-static WinLayout win_layout(const ldpc_graph* g, const Tiling& t, int W) {
-    WinLayout L{};
-    L.R = std::min(W, g->positions) + g->ms;
+static ConvLayout conv_layout(const ldpc_graph* g, const Tiling& t, int ring) {
+    ConvLayout L{};
+    L.R = ring;
     L.eps = (g->ms + 1) * g->Jb * g->Lb * g->p;
     const int c = g->Lb * g->p;
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
     L.mu = take((size_t)t.gpad * L.R * c * sizeof(float));
     L.msg = take((size_t)t.gpad * L.R * L.eps * sizeof(float));
-    L.stage = take((size_t)t.gpad * c * sizeof(float));
     L.total = off;
     return L;
+}
+
+static int window_ring(const ldpc_graph* g, int W) { return std::min(W, g->positions) + g->ms; }
+static int pipeline_ring(const ldpc_graph* g, int I) { return I * (g->ms + 1); }
+
+static ConvSlots conv_slots(const ldpc_graph* g) {
+    ConvSlots S{};
+    for (int k = 0; k < (g->ms + 1) * g->Lb && k < LDPC_MAX_ROW_WEIGHT; ++k) {
+        S.cn_dd[k] = (int8_t)(g->ms - k / g->Lb);
+        S.cn_q[k] = (int8_t)(k % g->Lb);
+    }
+    for (int k = 0; k < (g->ms + 1) * g->Jb && k < LDPC_MAX_COL_WEIGHT; ++k) {
+        S.vn_dd[k] = (int8_t)(k / g->Jb);
+        S.vn_rr[k] = (int8_t)(k % g->Jb);
+    }
+    return S;
 }
 
 template <int FPL>
@@ -1024,73 +1140,145 @@ static void run_block(const ldpc_graph* g, const float* llr, int gamma, int max_
     }
 }
 
-template <int FPL>
-static void run_window(const ldpc_graph* g, const float* llr, int gamma, int Wlen, int K, float* post,
-                       uint8_t* bits, char* ws, const WinLayout& lay, const Tiling& tl, hipStream_t st) {
-    const ConvDesc& D = g->cv;
-    WinParams P{};
-    P.msg = reinterpret_cast<float*>(ws + lay.msg);
-    P.mu = reinterpret_cast<const float*>(ws + lay.mu);
-    P.stage = reinterpret_cast<float*>(ws + lay.stage);
-    P.tiles = tl.tiles;
-    const int c = D.c;
-    const int64_t ld = (int64_t)D.positions * c;
+// host-side helpers for the convolutional schedules
+struct ConvRun {
+    const ldpc_graph* g;
+    ConvDesc D;
+    ConvSlots S;
+    ConvParams P;
+    ConvLayout lay;
+    Tiling tl;
+    int dcc, dvc;
+    hipStream_t st;
+    const float* llr;
+    float* post;
+    uint8_t* bits;
+    int cls_ingest, cls_cn, cls_vn;
+
+    void unit(ConvUnits& U, int pos, int lo, int hi) const {
+        const int u = U.n++;
+        U.pos[u] = pos;
+        U.slot[u] = pos % lay.R;
+        U.cls[u] = pos % D.T;
+        U.lo[u] = lo;
+        U.hi[u] = hi;
+    }
+    ConvUnits units() const {
+        ConvUnits U{};
+        U.ring = lay.R;
+        U.eps = lay.eps;
+        U.out_unit = -1;
+        return U;
+    }
+
+    template <int FPL>
+    void ingest(int t0, int npos) const {
+        timing::Scope ts(cls_ingest, st);
+        ConvUnits U = units();
+        dim3 grid((npos * D.c + 63) / 64, tl.gpad / 64);
+        conv_ingest_kernel<<<grid, 256, 0, st>>>(D, S, U, P, llr, t0, npos, tl.gpad, tl.gt);
+    }
+
+    template <int FPL>
+    void check(const ConvUnits& U) const {
+        if (U.n == 0) return;
+        timing::Scope ts(cls_cn, st);
+        ConvParams Pc = P;
+        Pc.rows = U.n * D.Jb * D.p;
+        LDPC_DC_SWITCH(dcc, if constexpr (DC <= MaxDC<FPL>::value) {
+            conv_cn_kernel<DC, FPL><<<grid_for_waves((int64_t)Pc.rows * tl.tiles), kBlock, 0, st>>>(D, S, U, Pc);
+        });
+    }
+
+    template <int FPL>
+    void variable(const ConvUnits& U) const {
+        if (U.n == 0) return;
+        timing::Scope ts(cls_vn, st);
+        ConvParams Pv = P;
+        Pv.rows = U.n * D.c;
+        if (U.out_unit >= 0) {
+            const unsigned grid = (unsigned)(((Pv.rows + kOutVars - 1) / kOutVars) * tl.tiles);
+            LDPC_DV_SWITCH(dvc, (conv_vn_out_kernel<DV, FPL><<<grid, kOutBlock, 0, st>>>(D, S, U, Pv, post, bits)));
+        } else {
+            LDPC_DV_SWITCH(dvc, (conv_vn_kernel<DV, FPL>
+                                 <<<grid_for_waves((int64_t)Pv.rows * tl.tiles), kBlock, 0, st>>>(D, S, U, Pv)));
+        }
+    }
+};
+
+static ConvRun make_conv_run(const ldpc_graph* g, const float* llr, int gamma, float* post, uint8_t* bits, char* ws,
+                             const ConvLayout& lay, const Tiling& tl, hipStream_t st) {
+    ConvRun r{};
+    r.g = g;
+    r.D = g->cv;
+    r.S = conv_slots(g);
+    r.P.msg = reinterpret_cast<float*>(ws + lay.msg);
+    r.P.mu = reinterpret_cast<float*>(ws + lay.mu);
+    r.P.tiles = tl.tiles;
+    r.P.gamma = gamma;
+    r.lay = lay;
+    r.tl = tl;
     // edges are enumerated by syndrome-former slot, zero blocks included
-    const int dcc = dc_class((D.ms + 1) * D.Lb), dvc = dv_class((D.ms + 1) * D.Jb);
-    WinState W{};
-    W.R = lay.R;
-    W.eps = lay.eps;
+    r.dcc = dc_class((g->ms + 1) * g->Lb);
+    r.dvc = dv_class((g->ms + 1) * g->Jb);
+    r.st = st;
+    r.llr = llr;
+    r.post = post;
+    r.bits = bits;
+    return r;
+}
+
+// Sliding window (target position s = 0 .. positions-1): window layers
+// s..s+W-1, active positions s..s+W-1; entering positions start from
+// beta = clip(mu); K flooding iterations; position s decided at the end.
+template <int FPL>
+static void run_window(ConvRun& r, int Wlen, int K) {
+    const ConvDesc& D = r.D;
+    r.cls_ingest = 6;
+    r.cls_cn = 7;
+    r.cls_vn = 8;
     for (int s = 0; s < D.positions; ++s) {
-        W.s = s;
-        W.lay_lo = s;
-        W.lay_hi = std::min(s + Wlen - 1, D.layers - 1);
+        const int lay_hi = std::min(s + Wlen - 1, D.layers - 1);
         const int pos_hi = std::min(s + Wlen - 1, D.positions - 1);
         const int in_lo = (s == 0) ? 0 : s + Wlen - 1;
-        if (in_lo <= pos_hi) {
-            const int npos = pos_hi - in_lo + 1;
-            {
-                timing::Scope ts(6, st);
-                dim3 grid((npos * c + 63) / 64, tl.gpad / 64);
-                float* dst = reinterpret_cast<float*>(ws + lay.mu) + (size_t)(in_lo % lay.R) * c * tl.gt;
-                to_packages_kernel<<<grid, 256, 0, st>>>(llr, ld, (int64_t)in_lo * c, npos * c, gamma, tl.gpad,
-                                                         tl.gt, dst, (int64_t)lay.R * c * tl.gt, nullptr, 0);
-            }
-            {
-                timing::Scope ts(7, st);
-                WinState Wi = W;
-                Wi.s = in_lo;
-                WinParams Pi = P;
-                Pi.rows = npos * c;
-                LDPC_DV_SWITCH(dvc, (init_window_kernel<DV, FPL>
-                                     <<<grid_for_waves((int64_t)Pi.rows * tl.tiles), kBlock, 0, st>>>(D, Wi, Pi)));
-            }
-        }
-        const int nlay = W.lay_hi - W.lay_lo + 1;
-        const int ncol = (pos_hi - s + 1) * c;
+        if (in_lo <= pos_hi) r.ingest<FPL>(in_lo, pos_hi - in_lo + 1);
+        ConvUnits Uc = r.units();
+        for (int tau = s; tau <= lay_hi; ++tau) r.unit(Uc, tau, s, 0);
+        ConvUnits Uv = r.units();
+        for (int t = s; t <= pos_hi; ++t) r.unit(Uv, t, s, lay_hi);
         for (int k = 1; k <= K; ++k) {
-            {
-                timing::Scope ts(8, st);
-                WinParams Pc = P;
-                Pc.rows = nlay * D.Jb * D.p;
-                LDPC_DC_SWITCH(dcc, if constexpr (DC <= MaxDC<FPL>::value) {
-                    cn_window_kernel<DC, FPL><<<grid_for_waves((int64_t)Pc.rows * tl.tiles), kBlock, 0, st>>>(D, W, Pc);
-                });
-            }
-            {
-                timing::Scope ts(9, st);
-                WinParams Pv = P;
-                Pv.rows = ncol;
-                Pv.decide = (k == K);
-                LDPC_DV_SWITCH(dvc, (vn_window_kernel<DV, FPL>
-                                     <<<grid_for_waves((int64_t)Pv.rows * tl.tiles), kBlock, 0, st>>>(D, W, Pv)));
+            r.check<FPL>(Uc);
+            Uv.out_unit = (k == K) ? 0 : -1;
+            r.variable<FPL>(Uv);
+        }
+    }
+}
+
+// Pipelined decoder of Algorithm 2 with I processors: at slot t, frame t
+// enters; processor i updates check layer t - (i-1)(ms+1), then frame
+// t - (i-1)(ms+1) - ms; the frame leaving processor I is decided.
+template <int FPL>
+static void run_pipeline(ConvRun& r, int I) {
+    const ConvDesc& D = r.D;
+    r.cls_ingest = 9;
+    r.cls_cn = 10;
+    r.cls_vn = 11;
+    const int last_slot = D.positions - 1 + D.ms + (I - 1) * (D.ms + 1);
+    for (int t = 0; t <= last_slot; ++t) {
+        if (t < D.positions) r.ingest<FPL>(t, 1);
+        ConvUnits Uc = r.units();
+        ConvUnits Uv = r.units();
+        for (int i = 1; i <= I; ++i) {
+            const int tau = t - (i - 1) * (D.ms + 1);
+            if (tau >= 0 && tau < D.layers) r.unit(Uc, tau, 0, 0);
+            const int f = tau - D.ms;
+            if (f >= 0 && f < D.positions) {
+                if (i == I) Uv.out_unit = Uv.n;
+                r.unit(Uv, f, 0, D.layers - 1);
             }
         }
-        {
-            timing::Scope ts(10, st);
-            dim3 grid((c + 63) / 64, (gamma + 63) / 64);
-            from_packages_kernel<<<grid, 256, 0, st>>>(P.stage, (int64_t)c * tl.gt, c, gamma, tl.gt, post, bits, ld,
-                                                       (int64_t)s * c);
-        }
+        r.check<FPL>(Uc);
+        r.variable<FPL>(Uv);
     }
 }
 
@@ -1105,13 +1293,16 @@ ldpc_status ldpc_workspace_size(const ldpc_graph* g, int32_t gamma, int32_t max_
     if (!g || !bytes || gamma < 1 || max_iters < 1 || max_iters > LDPC_MAX_ITERS || window < 0)
         return LDPC_EINVAL;
     const Tiling tl = choose_tiling(gamma, g);
-    if (window == 0) {
-        if (g->kind != LDPC_GRAPH_QC) return LDPC_EUNSUPPORTED;
+    if (g->kind == LDPC_GRAPH_QC) {
+        if (window != 0) return LDPC_EUNSUPPORTED;
         *bytes = block_layout(g, tl, max_iters).total;
+    } else if (window == 0) {
+        if (max_iters > kMaxUnits) return LDPC_EUNSUPPORTED;
+        *bytes = conv_layout(g, tl, pipeline_ring(g, max_iters)).total;
     } else {
-        if (g->kind != LDPC_GRAPH_CONV) return LDPC_EUNSUPPORTED;
         if (window < g->ms + 1) return LDPC_EINVAL;
-        *bytes = win_layout(g, tl, window).total;
+        if (window > kMaxUnits) return LDPC_EUNSUPPORTED;
+        *bytes = conv_layout(g, tl, window_ring(g, window)).total;
     }
     return LDPC_OK;
 }
@@ -1139,25 +1330,54 @@ ldpc_status ldpc_decode(const ldpc_graph* g, const float* llr, int32_t gamma, in
     return hipGetLastError() == hipSuccess ? LDPC_OK : LDPC_EHIP;
 }
 
+static ldpc_status conv_checks(const ldpc_graph* g, const float* llr, int32_t gamma, const float* post,
+                               const uint8_t* bits) {
+    if (!g || !llr || !post || !bits) return LDPC_EINVAL;
+    if (g->kind != LDPC_GRAPH_CONV || gamma < 1) return LDPC_EINVAL;
+    if ((int64_t)gamma * g->n > ((int64_t)1 << 40)) return LDPC_EUNSUPPORTED;
+    if ((reinterpret_cast<uintptr_t>(llr) | reinterpret_cast<uintptr_t>(post)) & 3) return LDPC_EINVAL;
+    return LDPC_OK;
+}
+
 ldpc_status ldpc_decode_window(const ldpc_graph* g, const float* llr, int32_t gamma, int32_t W,
                                int32_t iters_per_window, float* post, uint8_t* bits, void* workspace,
                                size_t workspace_bytes, void* stream) {
-    if (!g || !llr || !post || !bits) return LDPC_EINVAL;
-    if (g->kind != LDPC_GRAPH_CONV) return LDPC_EINVAL;
-    if (gamma < 1 || iters_per_window < 1 || iters_per_window > LDPC_MAX_ITERS || W < g->ms + 1) return LDPC_EINVAL;
-    if ((int64_t)gamma * g->n > ((int64_t)1 << 40)) return LDPC_EUNSUPPORTED;
+    ldpc_status chk = conv_checks(g, llr, gamma, post, bits);
+    if (chk != LDPC_OK) return chk;
+    if (iters_per_window < 1 || iters_per_window > LDPC_MAX_ITERS || W < g->ms + 1) return LDPC_EINVAL;
+    if (W > kMaxUnits) return LDPC_EUNSUPPORTED;
     const Tiling tl = choose_tiling(gamma, g);
-    const WinLayout lay = win_layout(g, tl, W);
+    const ConvLayout lay = conv_layout(g, tl, window_ring(g, W));
     if (!workspace || workspace_bytes < lay.total) return LDPC_EWORKSPACE;
     if (reinterpret_cast<uintptr_t>(workspace) & 255) return LDPC_EINVAL;
-    if ((reinterpret_cast<uintptr_t>(llr) | reinterpret_cast<uintptr_t>(post)) & 3) return LDPC_EINVAL;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    char* ws = reinterpret_cast<char*>(workspace);
+    ConvRun r = make_conv_run(g, llr, gamma, post, bits, reinterpret_cast<char*>(workspace), lay, tl, st);
     (void)hipGetLastError();
     switch (tl.fpl) {
-        case 4: run_window<4>(g, llr, gamma, W, iters_per_window, post, bits, ws, lay, tl, st); break;
-        case 2: run_window<2>(g, llr, gamma, W, iters_per_window, post, bits, ws, lay, tl, st); break;
-        default: run_window<1>(g, llr, gamma, W, iters_per_window, post, bits, ws, lay, tl, st); break;
+        case 4: run_window<4>(r, W, iters_per_window); break;
+        case 2: run_window<2>(r, W, iters_per_window); break;
+        default: run_window<1>(r, W, iters_per_window); break;
+    }
+    return hipGetLastError() == hipSuccess ? LDPC_OK : LDPC_EHIP;
+}
+
+ldpc_status ldpc_decode_pipeline(const ldpc_graph* g, const float* llr, int32_t gamma, int32_t iters, float* post,
+                                 uint8_t* bits, void* workspace, size_t workspace_bytes, void* stream) {
+    ldpc_status chk = conv_checks(g, llr, gamma, post, bits);
+    if (chk != LDPC_OK) return chk;
+    if (iters < 1 || iters > LDPC_MAX_ITERS) return LDPC_EINVAL;
+    if (iters > kMaxUnits) return LDPC_EUNSUPPORTED;
+    const Tiling tl = choose_tiling(gamma, g);
+    const ConvLayout lay = conv_layout(g, tl, pipeline_ring(g, iters));
+    if (!workspace || workspace_bytes < lay.total) return LDPC_EWORKSPACE;
+    if (reinterpret_cast<uintptr_t>(workspace) & 255) return LDPC_EINVAL;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    ConvRun r = make_conv_run(g, llr, gamma, post, bits, reinterpret_cast<char*>(workspace), lay, tl, st);
+    (void)hipGetLastError();
+    switch (tl.fpl) {
+        case 4: run_pipeline<4>(r, iters); break;
+        case 2: run_pipeline<2>(r, iters); break;
+        default: run_pipeline<1>(r, iters); break;
     }
     return hipGetLastError() == hipSuccess ? LDPC_OK : LDPC_EHIP;
 }
@@ -1194,9 +1414,10 @@ ldpc_status ldpc_timing_read(int64_t* launches, double* total_ms, int32_t capaci
 }
 
 const char* ldpc_kernel_class_name(int32_t cls) {
-    static const char* names[LDPC_TIMING_CLASSES] = {"ingest",     "check_node",  "variable_node", "syndrome",
-                                                     "output",     "frame_status", "window_ingest", "window_init",
-                                                     "window_check_node", "window_variable_node", "window_output"};
+    static const char* names[LDPC_TIMING_CLASSES] = {
+        "ingest",          "check_node",        "variable_node",        "syndrome",
+        "output",          "frame_status",      "window_ingest",        "window_check_node",
+        "window_variable_node", "pipeline_ingest", "pipeline_check_node", "pipeline_variable_node"};
     if (cls < 0 || cls >= LDPC_TIMING_CLASSES) return "unknown";
     return names[cls];
 }

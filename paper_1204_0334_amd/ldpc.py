@@ -29,7 +29,7 @@ _vp, _i32, _i64, _sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c
 
 OK, EINVAL, EWORKSPACE, EHIP, EUNSUPPORTED, ENOMEM = 0, -1, -2, -3, -4, -5
 GRAPH_QC, GRAPH_CONV = 0, 1
-TIMING_CLASSES = 11
+TIMING_CLASSES = 12
 MAX_ITERS = 100000
 
 
@@ -56,6 +56,7 @@ _destroy = _sig("ldpc_graph_destroy", None, [_vp])
 _ws_size = _sig("ldpc_workspace_size", _i32, [_vp, _i32, _i32, _i32, ctypes.POINTER(_sz)])
 _decode = _sig("ldpc_decode", _i32, [_vp, _vp, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _sz, _vp])
 _decode_window = _sig("ldpc_decode_window", _i32, [_vp, _vp, _i32, _i32, _i32, _vp, _vp, _vp, _sz, _vp])
+_decode_pipeline = _sig("ldpc_decode_pipeline", _i32, [_vp, _vp, _i32, _i32, _vp, _vp, _vp, _sz, _vp])
 _status_str = _sig("ldpc_status_str", ctypes.c_char_p, [_i32])
 _timing_enable = _sig("ldpc_timing_enable", _i32, [_i32])
 _timing_read = _sig("ldpc_timing_read", _i32, [ctypes.POINTER(_i64), ctypes.POINTER(ctypes.c_double), _i32])
@@ -63,7 +64,7 @@ _class_name = _sig("ldpc_kernel_class_name", ctypes.c_char_p, [_i32])
 
 EXPORTED = ["ldpc_graph_create_qc", "ldpc_graph_create_ldpccc_from_qc", "ldpc_graph_create_ldpccc_sf",
             "ldpc_graph_get_info", "ldpc_graph_destroy", "ldpc_workspace_size", "ldpc_decode",
-            "ldpc_decode_window", "ldpc_status_str", "ldpc_timing_enable", "ldpc_timing_read",
+            "ldpc_decode_window", "ldpc_decode_pipeline", "ldpc_status_str", "ldpc_timing_enable", "ldpc_timing_read",
             "ldpc_kernel_class_name"]
 
 
@@ -218,6 +219,27 @@ def decode_window(g: Graph, llr, W: int, iters_per_window: int, out=None, ws=Non
     _check(_decode_window(g.handle, llr.data_ptr(), gamma, int(W), int(iters_per_window), post.data_ptr(),
                           bits.data_ptr(), ws.data_ptr(), ws.numel(), _stream_handle(stream)),
            "ldpc_decode_window")
+    return post, bits
+
+
+def decode_pipeline(g: Graph, llr, iters: int, out=None, ws=None, stream=None):
+    """Pipelined decoding (Algorithm 2) of llr [gamma, positions * c] with
+    `iters` processors.  Returns (post, bits)."""
+    if llr.dim() != 2:
+        raise ValueError("llr must be [gamma, n]")
+    gamma, n = llr.shape
+    _need(llr, torch.float32, (gamma, g.n), "llr")
+    dev = llr.device
+    if out is None:
+        out = (torch.empty((gamma, n), dtype=torch.float32, device=dev),
+               torch.empty((gamma, n), dtype=torch.uint8, device=dev))
+    post, bits = out
+    _need(post, torch.float32, (gamma, n), "post")
+    _need(bits, torch.uint8, (gamma, n), "bits")
+    if ws is None:
+        ws = workspace(g, gamma, iters, 0, dev)
+    _check(_decode_pipeline(g.handle, llr.data_ptr(), gamma, int(iters), post.data_ptr(), bits.data_ptr(),
+                            ws.data_ptr(), ws.numel(), _stream_handle(stream)), "ldpc_decode_pipeline")
     return post, bits
 
 

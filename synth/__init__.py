@@ -285,9 +285,10 @@ WORKLOADS = {
     "qc36_p3060": dict(J=3, L=6, p=3060, shift_seed=2, noise_seed=102, gamma=1024, ebn0_db=1.5,
                        codeword="random", max_iters=20, early_stop=0),
     # LDPC convolutional code unwrapped from the same 3x6 base at p = 512 (c = 1024),
-    # 128 positions, terminated; window 6, 10 iterations per window; 512 streams
+    # 128 positions, terminated; 512 streams; window 6 with 10 iterations per
+    # window, or the pipelined decoder with 20 processors
     "cc36_p512": dict(J=3, L=6, p=512, shift_seed=2, noise_seed=103, gamma=512, ebn0_db=1.5,
-                      positions=128, window=6, iters_per_window=10),
+                      positions=128, window=6, iters_per_window=10, pipeline_iters=20),
 }
 
 

@@ -122,7 +122,10 @@ def test_workspace_size_rules():
     assert cc.workspace_size(64, 1, window=6) > 0
     out = ctypes.c_size_t()
     assert ldpc._ws_size(qc.handle, 64, 20, 6, ctypes.byref(out)) == ldpc.EUNSUPPORTED
-    assert ldpc._ws_size(cc.handle, 64, 20, 0, ctypes.byref(out)) == ldpc.EUNSUPPORTED
+    assert ldpc._ws_size(cc.handle, 64, 20, 0, ctypes.byref(out)) == ldpc.OK        # pipeline, 20 processors
+    assert out.value == cc.workspace_size(64, 20, 0) > cc.workspace_size(64, 10, 0)
+    assert ldpc._ws_size(cc.handle, 64, 65, 0, ctypes.byref(out)) == ldpc.EUNSUPPORTED
+    assert ldpc._ws_size(cc.handle, 64, 1, 65, ctypes.byref(out)) == ldpc.EUNSUPPORTED
     assert ldpc._ws_size(cc.handle, 64, 20, 2, ctypes.byref(out)) == ldpc.EINVAL     # W < ms + 1
     assert ldpc._ws_size(qc.handle, 0, 20, 0, ctypes.byref(out)) == ldpc.EINVAL
     assert ldpc._ws_size(qc.handle, 64, 0, 0, ctypes.byref(out)) == ldpc.EINVAL
@@ -175,3 +178,17 @@ def test_library_shares_torch_hip_runtime():
     maps = open("/proc/self/maps").read()
     runtimes = {line.split()[-1] for line in maps.splitlines() if "libamdhip64" in line}
     assert len(runtimes) == 1, runtimes
+
+
+def test_decode_pipeline_validates_before_launching():
+    qc = ldpc.Graph.qc(synth.draw_qc_shifts(3, 6, 64, 1), 64)
+    cc = ldpc.Graph.ldpccc_from_qc(synth.draw_qc_shifts(3, 6, 32, 2), 32, 16)
+    ws = cc.workspace_size(64, 20, 0)
+    d = ldpc._decode_pipeline
+    assert d(qc.handle, FAKE, 64, 20, FAKE, FAKE, FAKE, ws, None) == ldpc.EINVAL
+    assert d(cc.handle, None, 64, 20, FAKE, FAKE, FAKE, ws, None) == ldpc.EINVAL
+    assert d(cc.handle, FAKE, 64, 0, FAKE, FAKE, FAKE, ws, None) == ldpc.EINVAL
+    assert d(cc.handle, FAKE, 64, 65, FAKE, FAKE, FAKE, ws, None) == ldpc.EUNSUPPORTED
+    assert d(cc.handle, FAKE, 0, 20, FAKE, FAKE, FAKE, ws, None) == ldpc.EINVAL
+    assert d(cc.handle, FAKE, 64, 20, FAKE, FAKE, FAKE, ws - 1, None) == ldpc.EWORKSPACE
+    assert d(cc.handle, FAKE, 64, 21, FAKE, FAKE, FAKE, ws, None) == ldpc.EWORKSPACE    # one more processor

@@ -320,3 +320,53 @@ def test_window_decoder_paper_scale_sampled_streams():
     # a 6-position window leaves residual errors at 1.5 dB (the full chain
     # decodes under flooding BP); the bit error rate stays low
     assert gpu["bits"].mean() < 1e-2
+
+
+# ----------------------------------------------------------------------------
+# convolutional code, pipelined decoder (Algorithm 2)
+# ----------------------------------------------------------------------------
+
+def gpu_pipeline(g, llr, I):
+    print(f"[gpu] pipeline n={g.n} gamma={llr.shape[0]} I={I}", flush=True)
+    x = torch.from_numpy(np.ascontiguousarray(llr)).to(DEV)
+    post, bits = ldpc.decode_pipeline(g, x, I)
+    torch.cuda.synchronize()
+    return dict(post=post.cpu().numpy(), bits=bits.cpu().numpy())
+
+
+@pytest.mark.parametrize("p,positions,I,gamma,terminate", [(32, 16, 1, 64, True), (32, 16, 3, 70, True),
+                                                           (17, 12, 8, 100, True), (24, 9, 20, 65, False),
+                                                           (16, 30, 12, 257, True)])
+def test_pipeline_decoder_small(p, positions, I, gamma, terminate):
+    a = synth.draw_qc_shifts(3, 6, p, 2)
+    Hc, info = oracle.unwrap_qc(a, p, positions, terminate=terminate)
+    llr = synth.bpsk_awgn_llr(None, synth.ebn0_to_sigma2(1.5, 0.5), 107, gamma=gamma, n=Hc.n)
+    ref = oracle.decode_pipeline(Hc, llr, I, info["ms"])
+    gpu = gpu_pipeline(ldpc.Graph.ldpccc_from_qc(a, p, positions, terminate), llr, I)
+    if I <= 3:
+        assert rel_err(gpu["post"], ref["post"]).max() <= TOL
+    window_parity(gpu, ref, f"pipeline p={p} I={I}")
+
+
+def test_pipeline_matches_flooding_reference_on_the_chain():
+    # the pipelined decoder computes I flooding iterations on the whole chain
+    a = synth.draw_qc_shifts(3, 6, 20, 2)
+    Hc, info = oracle.unwrap_qc(a, 20, 10)
+    llr = synth.bpsk_awgn_llr(None, synth.ebn0_to_sigma2(2.0, 0.5), 9, gamma=64, n=Hc.n)
+    ref = oracle.decode_block(Hc, llr, 6)
+    gpu = gpu_pipeline(ldpc.Graph.ldpccc_from_qc(a, 20, 10), llr, 6)
+    window_parity(gpu, ref, "pipeline vs flooding")
+
+
+def test_pipeline_paper_scale_sampled_streams():
+    w = synth.workload_inputs("cc36_p512")
+    spec = w["spec"]
+    a, llr = w["shifts"], w["llr"]
+    I = spec["pipeline_iters"]
+    g = ldpc.Graph.ldpccc_from_qc(a, spec["p"], spec["positions"], True)
+    gpu = gpu_pipeline(g, llr, I)
+    Hc, info = oracle.unwrap_qc(a, spec["p"], spec["positions"])
+    pick = np.array([0, 300, 511])
+    ref = oracle.decode_pipeline(Hc, llr[pick], I, info["ms"])
+    window_parity({k: v[pick] for k, v in gpu.items()}, ref, "pipeline p=512 sampled")
+    assert gpu["bits"].mean() < 1e-3

@@ -358,3 +358,47 @@ def test_window_single_layer_is_a_forward_recursion():
                     if lay[r] > s:
                         sent[(r, v)] = np.clip(mu[v] + sum(inc), -30, 30)
         np.testing.assert_allclose(win["post"][g], np.clip(post, -30, 30), rtol=1e-12, atol=1e-12)
+
+
+# ----------------------------------------------------------------------------
+# pipelined decoder (Algorithm 2) pins
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("I,positions,terminate", [(1, 9, True), (2, 9, True), (5, 12, True), (20, 12, True),
+                                                   (3, 10, False)])
+def test_pipeline_equals_flooding_on_the_chain(I, positions, terminate):
+    # each layer and each frame is updated I times, every check update seeing
+    # the previous round's variable messages: I flooding iterations on the
+    # terminated chain, bit for bit (same arithmetic, same summation order)
+    a = synth.draw_qc_shifts(3, 6, 16, 2)
+    Hc, info = oracle.unwrap_qc(a, 16, positions, terminate=terminate)
+    llr = synth.bpsk_awgn_llr(None, synth.ebn0_to_sigma2(1.0, 0.5), 11, gamma=4, n=Hc.n)
+    pipe = oracle.decode_pipeline(Hc, llr, I, info["ms"])
+    flood = oracle.decode_block(Hc, llr, I)
+    assert np.array_equal(pipe["post"], flood["post"])
+    assert np.array_equal(pipe["bits"], flood["bits"])
+
+
+def test_pipeline_on_decoupled_positions_is_block_bp():
+    # block-diagonal sub-blocks: every frame is its own code, decoded with I iterations
+    p, positions, I = 8, 7, 4
+    base = np.array([[0, 1, 3, -1, -1, -1], [2, 5, 0, -1, -1, -1],
+                     [-1, -1, -1, 3, 0, 4], [-1, -1, -1, 6, 2, 1]])
+    Hc, info = oracle.unwrap_qc(base, p, positions)
+    rng = np.random.default_rng(4)
+    llr = rng.normal(1.0, 1.6, size=(3, Hc.n)).astype(np.float32)
+    pipe = oracle.decode_pipeline(Hc, llr, I, info["ms"])
+    c = info["c"]
+    for s in range(positions):
+        cls = s % 2
+        sub = oracle.qc_parity_check(base[2 * cls:2 * cls + 2, 3 * cls:3 * cls + 3], p)
+        ref = oracle.decode_block(sub, llr[:, s * c:(s + 1) * c], I)
+        np.testing.assert_allclose(pipe["post"][:, s * c:(s + 1) * c], ref["post"], rtol=0, atol=1e-12)
+
+
+def test_pipeline_all_ones_symmetry():
+    a, Hc, info, llr = _conv_inputs(ebn0=1.0)
+    p0 = oracle.decode_pipeline(Hc, llr, 6, info["ms"])
+    p1 = oracle.decode_pipeline(Hc, -llr, 6, info["ms"])
+    assert np.array_equal(p1["post"], -p0["post"])
+    assert np.array_equal(p1["bits"], 1 - p0["bits"])
