@@ -861,8 +861,11 @@ __global__ void __launch_bounds__(kOutBlock) conv_vn_out_kernel(const ConvDesc D
 
 // Positions t0 .. t0+npos-1 enter the ring: channel LLRs go from the caller's
 // layout into the mu ring (through LDS), and every edge of the entering
-// positions starts with beta = clip(mu).  64 columns x 64 frames per block.
-__global__ void __launch_bounds__(256) conv_ingest_kernel(const ConvDesc D, const ConvSlots S, const ConvUnits U,
+// positions starts with beta = clip(mu).  64 columns x 64 frames per block of
+// 16 waves (one position is only 16 x Gt/64 blocks, so the block is wide).
+constexpr int kIngestBlock = 1024;
+
+__global__ void __launch_bounds__(kIngestBlock) conv_ingest_kernel(const ConvDesc D, const ConvSlots S, const ConvUnits U,
                                                           const ConvParams P, const float* __restrict__ llr, int t0,
                                                           int npos, int gpad, int Gt) {
     __shared__ float tileS[64][65];
@@ -871,7 +874,7 @@ __global__ void __launch_bounds__(256) conv_ingest_kernel(const ConvDesc D, cons
     const int c0 = blockIdx.x * 64, f0 = blockIdx.y * 64;
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
 #pragma unroll 4
-    for (int r = ty; r < 64; r += 4) {
+    for (int r = ty; r < 64; r += kIngestBlock / 64) {
         const int g = f0 + r, cc = c0 + tx;
         float v = 0.0f;
         if (g < P.gamma && cc < ncols) v = llr[(size_t)g * ld + (int64_t)t0 * D.c + cc];
@@ -880,7 +883,7 @@ __global__ void __launch_bounds__(256) conv_ingest_kernel(const ConvDesc D, cons
     __syncthreads();
     const int nslots = (D.ms + 1) * D.Jb;
 #pragma unroll 1
-    for (int r = ty; r < 64; r += 4) {
+    for (int r = ty; r < 64; r += kIngestBlock / 64) {
         const int cc = c0 + r, g = f0 + tx;
         if (cc >= ncols || g >= gpad) continue;
         const int tile = g / Gt, fl = g - tile * Gt;
@@ -1176,7 +1179,7 @@ struct ConvRun {
         timing::Scope ts(cls_ingest, st);
         ConvUnits U = units();
         dim3 grid((npos * D.c + 63) / 64, tl.gpad / 64);
-        conv_ingest_kernel<<<grid, 256, 0, st>>>(D, S, U, P, llr, t0, npos, tl.gpad, tl.gt);
+        conv_ingest_kernel<<<grid, kIngestBlock, 0, st>>>(D, S, U, P, llr, t0, npos, tl.gpad, tl.gt);
     }
 
     template <int FPL>
