@@ -194,6 +194,81 @@ def bench_window(args, pipeline: bool = False):
     print(json.dumps(line), flush=True)
 
 
+def paper_tables(args):
+    """Analogue of the paper's Tables III and V on one MI355X: the 4 x 24
+    (rate 5/6) code shapes A-D of Table II with seeded 4-cycle-free shifts
+    (the paper's shifts are not printed).  Table III: block decoding, 30
+    iterations, 3.2 dB, until 100 frame errors.  Table V: the convolutional
+    codes A'-D' unwrapped from them, pipelined decoder with 20 processors,
+    3.1 dB.  GPU times cover channel generation, decoding and error counting
+    (as the paper's do); CPU times are the FP64 reference decoder on the host."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import synth
+    from paper_1204_0334_amd import fer, ldpc
+    torch.cuda.set_device(0)
+    threads = max(1, min(int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)), os.cpu_count() or 1))
+    codes = [("A", 422), ("B", 632), ("C", 768), ("D", 1024)]
+    rows3, rows5 = [], []
+    for name, p in codes:
+        a = synth.draw_qc_shifts(4, 24, p, 40 + p)
+        g = ldpc.Graph.qc(a, p)
+        r = fer.simulate(g, 3.2, gamma=args.gamma, iters=30, seed=7, min_frame_errors=100,
+                         max_frames=args.max_frames)
+        H = oracle.qc_parity_check(a, p)
+        llr = synth.bpsk_awgn_llr(None, fer.ebn0_to_sigma2(3.2, 5 / 6), 7, gamma=2, n=H.n)
+        t0 = time.perf_counter()
+        oracle.decode_block(H, llr, 30, nthreads=1)
+        t_cpu = (time.perf_counter() - t0) / 2 * 1e3
+        rows3.append(dict(code=name, n=H.n, E=H.ne, frames=r["frames"], frame_errors=r["frame_errors"],
+                          fer=r["fer"], T_gpu_s=r["seconds"], t_gpu_ms=r["ms_per_frame"], t_cpu_ms=t_cpu,
+                          speedup=t_cpu / r["ms_per_frame"], coded_mbps=r["coded_mbps"]))
+        print(json.dumps({"table": "III", **rows3[-1]}), flush=True)
+    positions, I, streams = args.chain_positions, 20, args.streams
+    for name, p in codes:
+        a = synth.draw_qc_shifts(4, 24, p, 40 + p)
+        g = ldpc.Graph.ldpccc_from_qc(a, p, positions, True)
+        r = fer.simulate(g, 3.1, decoder="pipeline", gamma=streams, iters=I, seed=9, min_frame_errors=100,
+                         max_frames=args.max_streams)
+        Hc, info = oracle.unwrap_qc(a, p, positions)
+        llr = synth.bpsk_awgn_llr(None, fer.ebn0_to_sigma2(3.1, 5 / 6), 9, gamma=threads, n=Hc.n)
+        t0 = time.perf_counter()
+        oracle.decode_pipeline(Hc, llr[:1], I, info["ms"], nthreads=1)
+        t1 = (time.perf_counter() - t0) * 1e3 / positions
+        t0 = time.perf_counter()
+        oracle.decode_pipeline(Hc, llr, I, info["ms"], nthreads=threads)
+        tn = (time.perf_counter() - t0) * 1e3 / (positions * threads)
+        rows5.append(dict(code=name + "'", c=info["c"], streams=r["frames"], code_frames=r["frames"] * positions,
+                          stream_errors=r["frame_errors"], ber=r["ber"], T_gpu_s=r["seconds"],
+                          t_gpu_ms=r["ms_per_code_frame"], t_cpu1_ms=t1, t_cpun_ms=tn, cpu_threads=threads,
+                          speedup1=t1 / r["ms_per_code_frame"], speedupn=tn / r["ms_per_code_frame"],
+                          coded_mbps=r["coded_mbps"]))
+        print(json.dumps({"table": "V", **rows5[-1]}), flush=True)
+    print()
+    print(f"Table III analogue: 4x24 QC-LDPC (rate 5/6), 30 iterations, 3.2 dB, {args.gamma} frames per batch, "
+          f"stop after 100 frame errors")
+    print()
+    print("| code | N | edges | frames | frame errors | FER | T_GPU (s) | t_GPU (ms/codeword) | t_CPU 1 thread (ms) | speed-up | coded Mbit/s |")
+    print("|---|---|---|---|---|---|---|---|---|---|---|")
+    for r in rows3:
+        print(f"| {r['code']} | {r['n']} | {r['E']} | {r['frames']} | {r['frame_errors']} | {r['fer']:.2e} | "
+              f"{r['T_gpu_s']:.3f} | {r['t_gpu_ms']:.5f} | {r['t_cpu_ms']:.1f} | {r['speedup']:.0f} | "
+              f"{r['coded_mbps']:.0f} |")
+    print()
+    print(f"Table V analogue: LDPC-CC unwrapped from the same codes (Lambda = 4, m_s = 3), pipelined decoder with "
+          f"{I} processors, 3.1 dB, {positions} code frames per stream, {streams} streams per batch")
+    print()
+    print(f"| code | c | code frames | BER | T_GPU (s) | t_GPU (ms/frame) | t_CPU 1 thread (ms/frame) | "
+          f"t_CPU {threads} threads (ms/frame) | speed-up vs 1 | speed-up vs {threads} | coded Mbit/s |")
+    print("|---|---|---|---|---|---|---|---|---|---|---|")
+    for r in rows5:
+        print(f"| {r['code']} | {r['c']} | {r['code_frames']} | {r['ber']:.2e} | {r['T_gpu_s']:.3f} | "
+              f"{r['t_gpu_ms']:.5f} | {r['t_cpu1_ms']:.2f} | {r['t_cpun_ms']:.3f} | {r['speedup1']:.0f} | "
+              f"{r['speedupn']:.0f} | {r['coded_mbps']:.0f} |")
+
+
 def cpu_baseline(shifts, p, llr, iters, sample):
     import numpy as np
 
@@ -223,6 +298,12 @@ def main():
     ap.add_argument("--workload", default="qc36_p3060", choices=["qc36_p3060", "cc36_p512", "cc36_p512_pipeline"],
                     help="qc36_p3060: the block-code benchmark; cc36_p512: the convolutional-code window "
                          "decoder; cc36_p512_pipeline: the pipelined convolutional-code decoder")
+    ap.add_argument("--paper-tables", action="store_true",
+                    help="run the analogue of the paper's Tables III and V instead of the benchmark line")
+    ap.add_argument("--max-frames", type=int, default=1 << 19, help="--paper-tables: frame cap per code")
+    ap.add_argument("--chain-positions", type=int, default=64, help="--paper-tables: code frames per stream")
+    ap.add_argument("--streams", type=int, default=256, help="--paper-tables: streams per batch")
+    ap.add_argument("--max-streams", type=int, default=4096, help="--paper-tables: stream cap per code")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run 5 device-to-device copies of BYTES (counter calibration) and exit")
     args = ap.parse_args()
@@ -241,6 +322,9 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    if args.paper_tables:
+        paper_tables(args)
+        return
     if args.workload in ("cc36_p512", "cc36_p512_pipeline"):
         bench_window(args, pipeline=args.workload.endswith("pipeline"))
         return

@@ -209,6 +209,31 @@ ldpc_status ldpc_decode_pipeline(const ldpc_graph* conv, const float* llr, int32
                                  float* post, uint8_t* bits, void* workspace, size_t workspace_bytes,
                                  void* stream);
 
+/*
+ * Simulation on the GPU (Sec. V-B: codewords and noise are generated on the
+ * device, the host only reads error counts).  The codeword is all-zero (the
+ * decoders treat every codeword alike: flipping the signs of a codeword's
+ * LLRs flips the decisions and nothing else).
+ *
+ * ldpc_awgn_llr: llr (device, float [gamma][n]) = 2 y / sigma^2 with
+ * y = 1 + sigma z, z ~ N(0, 1), for frames frame0 .. frame0+gamma-1.  Sample
+ * (g, i) depends only on (seed, frame0 + g, i): Philox-4x32-10 with key =
+ * seed (low word first) and counter (i / 4, frame, 0x4E5A, frame >> 32) gives
+ * four uniforms (w + 0.5) / 2^32 and two Box-Muller pairs, in FP64.
+ * Errors: EINVAL (NULL, n < 1, gamma < 1, sigma2 <= 0, frame0 < 0).
+ *
+ * ldpc_count_errors: for decisions bits (device, uint8 [gamma][n]) against the
+ * all-zero codeword, writes each frame's bit-error count to frame_errors
+ * (device int32 [gamma], or NULL) and adds the batch's bit errors to totals[0]
+ * and its erroneous frames to totals[1] (device uint64 [2], or NULL; not
+ * cleared).  Errors: EINVAL (NULL bits, both outputs NULL, gamma or n < 1,
+ * misaligned totals).
+ */
+ldpc_status ldpc_awgn_llr(int64_t n, int32_t gamma, double sigma2, uint64_t seed, int64_t frame0, float* llr,
+                          void* stream);
+ldpc_status ldpc_count_errors(const uint8_t* bits, int32_t gamma, int64_t n, int32_t* frame_errors,
+                              uint64_t* totals, void* stream);
+
 /* Static description of a status code. */
 const char* ldpc_status_str(ldpc_status s);
 

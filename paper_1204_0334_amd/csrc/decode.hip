@@ -667,35 +667,6 @@ __global__ void __launch_bounds__(256) to_packages_kernel(const float* __restric
     }
 }
 
-// src[tile*sstride + col*Gt + frame]  ->  post [gamma][ld] = clip(L), bits = (L < 0)
-__global__ void __launch_bounds__(256) from_packages_kernel(const float* __restrict__ src, int64_t sstride, int ncols,
-                                                            int gamma, int Gt, float* __restrict__ post,
-                                                            uint8_t* __restrict__ bits, int64_t ld, int64_t col0) {
-    __shared__ float tileS[64][65];
-    const int c0 = blockIdx.x * 64, f0 = blockIdx.y * 64;
-    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-#pragma unroll 4
-    for (int r = ty; r < 64; r += 4) {
-        const int c = c0 + r, g = f0 + tx;
-        float v = 0.0f;
-        if (c < ncols && g < gamma) {
-            const int tile = g / Gt, fl = g - tile * Gt;
-            v = src[(size_t)tile * sstride + (size_t)c * Gt + fl];
-        }
-        tileS[tx][r] = v;
-    }
-    __syncthreads();
-#pragma unroll 4
-    for (int r = ty; r < 64; r += 4) {
-        const int g = f0 + r, c = c0 + tx;
-        if (g < gamma && c < ncols) {
-            const float L = tileS[r][tx];
-            post[(size_t)g * ld + col0 + c] = clip30(L);
-            bits[(size_t)g * ld + col0 + c] = (uint8_t)(L < 0.0f);
-        }
-    }
-}
-
 // ---------------------------------------------------------------------------
 // kernels: convolutional code (window and pipelined schedules)
 // ---------------------------------------------------------------------------
@@ -907,6 +878,81 @@ __global__ void __launch_bounds__(kIngestBlock) conv_ingest_kernel(const ConvDes
             if (sidx < 0) sidx += D.p;
             const int64_t pk = (int64_t)slot * U.eps + ((int64_t)((dd * D.Jb + rr) * D.Lb + q)) * D.p + sidx;
             P.msg[((size_t)tile * U.ring * U.eps + pk) * Gt + fl] = b;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// kernels: simulation (channel LLRs and error counts on the GPU, Sec. V-B)
+// ---------------------------------------------------------------------------
+
+// Philox-4x32-10 (Salmon, Moraes, Dror, Shaw, SC 2011): ten rounds of two
+// 32x32->64-bit products with the multipliers 0xD2511F53 / 0xCD9E8D57; the
+// key is bumped by 0x9E3779B9 / 0xBB67AE85 between rounds.
+__device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c[1] ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c[3] ^ k1;
+        c[1] = (uint32_t)p1;
+        c[3] = (uint32_t)p0;
+        c[0] = n0;
+        c[2] = n2;
+    }
+}
+
+// Channel LLRs of the all-zero codeword over BPSK/AWGN (Sec. II-B):
+// y = 1 + sigma z, mu = 2 y / sigma^2, for frames frame0 .. frame0+gamma-1.
+// Thread = (frame f, block b of 4 bits): the counter (b, f mod 2^32, tag,
+// f >> 32) gives four uniforms u = (w + 0.5) 2^-32 and two Box-Muller pairs
+// r0 (cos, sin)(2 pi u1), r1 (cos, sin)(2 pi u3), r = sqrt(-2 ln u), in FP64.
+__global__ void awgn_llr_kernel(float* __restrict__ llr, int64_t n, int gamma, uint64_t seed, int64_t frame0,
+                                uint32_t tag, double sigma2) {
+    const int64_t nblk = (n + 3) / 4;
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= nblk * gamma) return;
+    const int64_t g = id / nblk, b = id - g * nblk;
+    const uint64_t f = (uint64_t)(frame0 + g);
+    uint32_t c[4] = {(uint32_t)b, (uint32_t)f, tag, (uint32_t)(f >> 32)};
+    philox4x32_10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+    const double inv = 1.0 / 4294967296.0;
+    const double two_pi = 6.283185307179586476925286766559;
+    const double u0 = ((double)c[0] + 0.5) * inv, u1 = ((double)c[1] + 0.5) * inv;
+    const double u2 = ((double)c[2] + 0.5) * inv, u3 = ((double)c[3] + 0.5) * inv;
+    const double r0 = sqrt(-2.0 * log(u0)), r1 = sqrt(-2.0 * log(u2));
+    const double v[4] = {r0 * cos(two_pi * u1), r0 * sin(two_pi * u1), r1 * cos(two_pi * u3), r1 * sin(two_pi * u3)};
+    const double sigma = sqrt(sigma2);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int64_t i = 4 * b + q;
+        if (i < n) llr[g * n + i] = (float)(2.0 * (1.0 + sigma * v[q]) / sigma2);
+    }
+}
+
+// Bit errors against the all-zero codeword: per frame (one block per frame)
+// and accumulated into totals[0] (bit errors) and totals[1] (frame errors).
+__global__ void __launch_bounds__(256) count_errors_kernel(const uint8_t* __restrict__ bits, int64_t n,
+                                                           int32_t* frame_errors, unsigned long long* totals) {
+    __shared__ unsigned int part[4];
+    const int g = blockIdx.x;
+    const uint8_t* row = bits + (size_t)g * n;
+    unsigned int cnt = 0;
+    for (int64_t i = threadIdx.x; i < n; i += 256) cnt += row[i] != 0;
+    for (int off = 32; off >= 1; off >>= 1) cnt += __shfl_xor(cnt, off);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned int tot = part[0] + part[1] + part[2] + part[3];
+        if (frame_errors) frame_errors[g] = (int32_t)tot;
+        if (totals) {
+            atomicAdd(totals, (unsigned long long)tot);
+            if (tot) atomicAdd(totals + 1, 1ull);
         }
     }
 }
@@ -1382,6 +1428,27 @@ ldpc_status ldpc_decode_pipeline(const ldpc_graph* g, const float* llr, int32_t 
         case 2: run_pipeline<2>(r, iters); break;
         default: run_pipeline<1>(r, iters); break;
     }
+    return hipGetLastError() == hipSuccess ? LDPC_OK : LDPC_EHIP;
+}
+
+ldpc_status ldpc_awgn_llr(int64_t n, int32_t gamma, double sigma2, uint64_t seed, int64_t frame0, float* llr,
+                          void* stream) {
+    if (!llr || n < 1 || gamma < 1 || !(sigma2 > 0.0) || frame0 < 0) return LDPC_EINVAL;
+    if (n > ((int64_t)1 << 31) || (int64_t)gamma * n > ((int64_t)1 << 40)) return LDPC_EUNSUPPORTED;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const int64_t threads = (n + 3) / 4 * gamma;
+    (void)hipGetLastError();
+    awgn_llr_kernel<<<(unsigned)((threads + 255) / 256), 256, 0, st>>>(llr, n, gamma, seed, frame0, 0x4E5Au, sigma2);
+    return hipGetLastError() == hipSuccess ? LDPC_OK : LDPC_EHIP;
+}
+
+ldpc_status ldpc_count_errors(const uint8_t* bits, int32_t gamma, int64_t n, int32_t* frame_errors,
+                              uint64_t* totals, void* stream) {
+    if (!bits || gamma < 1 || n < 1 || (!frame_errors && !totals)) return LDPC_EINVAL;
+    if (reinterpret_cast<uintptr_t>(totals) & 7) return LDPC_EINVAL;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    (void)hipGetLastError();
+    count_errors_kernel<<<gamma, 256, 0, st>>>(bits, n, frame_errors, reinterpret_cast<unsigned long long*>(totals));
     return hipGetLastError() == hipSuccess ? LDPC_OK : LDPC_EHIP;
 }
 

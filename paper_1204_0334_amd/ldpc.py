@@ -57,6 +57,8 @@ _ws_size = _sig("ldpc_workspace_size", _i32, [_vp, _i32, _i32, _i32, ctypes.POIN
 _decode = _sig("ldpc_decode", _i32, [_vp, _vp, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _sz, _vp])
 _decode_window = _sig("ldpc_decode_window", _i32, [_vp, _vp, _i32, _i32, _i32, _vp, _vp, _vp, _sz, _vp])
 _decode_pipeline = _sig("ldpc_decode_pipeline", _i32, [_vp, _vp, _i32, _i32, _vp, _vp, _vp, _sz, _vp])
+_awgn_llr = _sig("ldpc_awgn_llr", _i32, [_i64, _i32, ctypes.c_double, ctypes.c_uint64, _i64, _vp, _vp])
+_count_errors = _sig("ldpc_count_errors", _i32, [_vp, _i32, _i64, _vp, _vp, _vp])
 _status_str = _sig("ldpc_status_str", ctypes.c_char_p, [_i32])
 _timing_enable = _sig("ldpc_timing_enable", _i32, [_i32])
 _timing_read = _sig("ldpc_timing_read", _i32, [ctypes.POINTER(_i64), ctypes.POINTER(ctypes.c_double), _i32])
@@ -64,7 +66,7 @@ _class_name = _sig("ldpc_kernel_class_name", ctypes.c_char_p, [_i32])
 
 EXPORTED = ["ldpc_graph_create_qc", "ldpc_graph_create_ldpccc_from_qc", "ldpc_graph_create_ldpccc_sf",
             "ldpc_graph_get_info", "ldpc_graph_destroy", "ldpc_workspace_size", "ldpc_decode",
-            "ldpc_decode_window", "ldpc_decode_pipeline", "ldpc_status_str", "ldpc_timing_enable", "ldpc_timing_read",
+            "ldpc_decode_window", "ldpc_decode_pipeline", "ldpc_awgn_llr", "ldpc_count_errors", "ldpc_status_str", "ldpc_timing_enable", "ldpc_timing_read",
             "ldpc_kernel_class_name"]
 
 
@@ -241,6 +243,32 @@ def decode_pipeline(g: Graph, llr, iters: int, out=None, ws=None, stream=None):
     _check(_decode_pipeline(g.handle, llr.data_ptr(), gamma, int(iters), post.data_ptr(), bits.data_ptr(),
                             ws.data_ptr(), ws.numel(), _stream_handle(stream)), "ldpc_decode_pipeline")
     return post, bits
+
+
+def awgn_llr(n: int, gamma: int, sigma2: float, seed: int, frame0: int = 0, out=None, device=None, stream=None):
+    """Channel LLRs of the all-zero codeword generated on the GPU: float32 [gamma, n]."""
+    if out is None:
+        out = torch.empty((gamma, n), dtype=torch.float32, device=device or "cuda")
+    _need(out, torch.float32, (gamma, n), "out")
+    _check(_awgn_llr(int(n), int(gamma), float(sigma2), int(seed) & 0xFFFFFFFFFFFFFFFF, int(frame0), out.data_ptr(),
+                     _stream_handle(stream)), "ldpc_awgn_llr")
+    return out
+
+
+def count_errors(bits, frame_errors=None, totals=None, stream=None):
+    """Bit errors per frame against the all-zero codeword; adds the batch's
+    bit and frame errors to `totals` (int64 [2]) when given."""
+    gamma, n = bits.shape
+    _need(bits, torch.uint8, (gamma, n), "bits")
+    if frame_errors is None:
+        frame_errors = torch.empty((gamma,), dtype=torch.int32, device=bits.device)
+    _need(frame_errors, torch.int32, (gamma,), "frame_errors")
+    if totals is not None:
+        _need(totals, torch.int64, (2,), "totals")
+    _check(_count_errors(bits.data_ptr(), gamma, n, frame_errors.data_ptr(),
+                         totals.data_ptr() if totals is not None else None, _stream_handle(stream)),
+           "ldpc_count_errors")
+    return frame_errors
 
 
 def timing_enable(on: bool = True):

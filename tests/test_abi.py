@@ -192,3 +192,15 @@ def test_decode_pipeline_validates_before_launching():
     assert d(cc.handle, FAKE, 0, 20, FAKE, FAKE, FAKE, ws, None) == ldpc.EINVAL
     assert d(cc.handle, FAKE, 64, 20, FAKE, FAKE, FAKE, ws - 1, None) == ldpc.EWORKSPACE
     assert d(cc.handle, FAKE, 64, 21, FAKE, FAKE, FAKE, ws, None) == ldpc.EWORKSPACE    # one more processor
+
+
+def test_simulation_helpers_validate_before_launching():
+    assert ldpc._awgn_llr(100, 4, 0.5, 1, 0, None, None) == ldpc.EINVAL
+    assert ldpc._awgn_llr(0, 4, 0.5, 1, 0, FAKE, None) == ldpc.EINVAL
+    assert ldpc._awgn_llr(100, 0, 0.5, 1, 0, FAKE, None) == ldpc.EINVAL
+    assert ldpc._awgn_llr(100, 4, 0.0, 1, 0, FAKE, None) == ldpc.EINVAL
+    assert ldpc._awgn_llr(100, 4, 0.5, 1, -1, FAKE, None) == ldpc.EINVAL
+    assert ldpc._count_errors(None, 4, 100, FAKE, FAKE, None) == ldpc.EINVAL
+    assert ldpc._count_errors(FAKE, 4, 100, None, None, None) == ldpc.EINVAL
+    assert ldpc._count_errors(FAKE, 0, 100, FAKE, None, None) == ldpc.EINVAL
+    assert ldpc._count_errors(FAKE, 4, 100, None, FAKE + 4, None) == ldpc.EINVAL

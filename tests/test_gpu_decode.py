@@ -370,3 +370,60 @@ def test_pipeline_paper_scale_sampled_streams():
     ref = oracle.decode_pipeline(Hc, llr[pick], I, info["ms"])
     window_parity({k: v[pick] for k, v in gpu.items()}, ref, "pipeline p=512 sampled")
     assert gpu["bits"].mean() < 1e-3
+
+
+# ----------------------------------------------------------------------------
+# simulation on the GPU: channel generator, error counting, FER loop
+# ----------------------------------------------------------------------------
+
+def test_gpu_channel_matches_the_cpu_generator():
+    n, gamma, s2, seed, f0 = 1001, 37, synth.ebn0_to_sigma2(1.3, 0.5), 0x1234_5678_9ABC, 77
+    gpu = ldpc.awgn_llr(n, gamma, s2, seed, f0, device=DEV).cpu().numpy()
+    cpu = synth.bpsk_awgn_llr(None, s2, seed, frame0=f0, gamma=gamma, n=n)
+    ulp = np.abs(gpu.view(np.int32).astype(np.int64) - cpu.view(np.int32).astype(np.int64))
+    assert ulp.max() <= 1
+    assert (ulp == 0).mean() > 0.999
+
+
+def test_gpu_error_counts():
+    rng = np.random.default_rng(3)
+    b = (rng.random((50, 333)) < 0.01).astype(np.uint8)
+    b[7] = 0
+    bits = torch.from_numpy(b).to(DEV)
+    totals = torch.zeros((2,), dtype=torch.int64, device=DEV)
+    pf = ldpc.count_errors(bits, totals=totals)
+    ldpc.count_errors(bits, totals=totals)
+    assert np.array_equal(pf.cpu().numpy(), b.sum(1))
+    assert totals.cpu().tolist() == [2 * int(b.sum()), 2 * int((b.sum(1) > 0).sum())]
+
+
+def test_fer_loop_counts_match_the_reference():
+    from paper_1204_0334_amd import fer
+    a = synth.draw_qc_shifts(3, 6, 37, 1)
+    g = ldpc.Graph.qc(a, 37)
+    r = fer.simulate(g, 0.5, gamma=64, iters=10, seed=5, min_frame_errors=10, max_frames=256)
+    assert r["frame_errors"] >= 10 and r["frames"] % 64 == 0
+    s2 = fer.ebn0_to_sigma2(0.5, 0.5)
+    llr = synth.bpsk_awgn_llr(None, s2, 5, frame0=0, gamma=r["frames"], n=g.n)
+    ref = oracle.decode_block(oracle.qc_parity_check(a, 37), llr, 10)
+    errs = ref["bits"].sum(1)
+    exempt = ref["min_abs"] < 1e-3
+    lo = int(((errs > 0) & ~exempt).sum())
+    hi = int(((errs > 0) | exempt).sum())
+    assert lo <= r["frame_errors"] <= hi
+    # high SNR: no errors in the frames simulated
+    r2 = fer.simulate(g, 8.0, gamma=64, iters=10, seed=5, max_frames=512)
+    assert r2["frames"] == 512 and r2["frame_errors"] == 0
+
+
+def test_fer_loop_pipeline_decoder():
+    from paper_1204_0334_amd import fer
+    a = synth.draw_qc_shifts(3, 6, 24, 2)
+    g = ldpc.Graph.ldpccc_from_qc(a, 24, 12)
+    r = fer.simulate(g, 0.0, decoder="pipeline", gamma=64, iters=5, seed=3, min_frame_errors=5, max_frames=128)
+    Hc, info = oracle.unwrap_qc(a, 24, 12)
+    llr = synth.bpsk_awgn_llr(None, fer.ebn0_to_sigma2(0.0, 0.5), 3, frame0=0, gamma=r["frames"], n=Hc.n)
+    ref = oracle.decode_pipeline(Hc, llr, 5, info["ms"])
+    close = (np.abs(ref["post"]) < 1e-3).any(1)
+    errs = ref["bits"].sum(1)
+    assert int(((errs > 0) & ~close).sum()) <= r["frame_errors"] <= int(((errs > 0) | close).sum())
