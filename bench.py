@@ -269,6 +269,76 @@ def paper_tables(args):
               f"{r['speedupn']:.0f} | {r['coded_mbps']:.0f} |")
 
 
+def learned_vs_plain(g, points, *, train_frames: int, eval_frames: int, T: int = 12, ckpt_every: int = 4,
+                     extra: bool = False, log=None):
+    """Train the learned min-sum decoder (T iterations, scale and offset per
+    iteration and base row, Adam on `train_frames` GPU-generated frames at
+    Eb/N0 uniform in 1.0-2.5 dB, BCE on every iteration's posterior,
+    checkpoints every `ckpt_every` iterations), then decode the same fresh
+    frames at each Eb/N0 with it and with plain sum-product (up to 30
+    iterations, early stop).  `extra` adds sum-product with T iterations and
+    the untrained normalised min-sum (scale 0.8) for context."""
+    import torch
+
+    from paper_1204_0334_amd import fer, nnms
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    W, hist = nnms.train(g, T=T, ckpt_every=ckpt_every, frames=train_frames, batch=1024, lr=0.01, seed=7,
+                         init=nnms.initial_weights(T, g.info["J"], 0.8, 0.0, device=dev), log_every=128)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    rows = []
+    for k, e in enumerate(points):
+        seed = 1_000_003 + 7919 * k
+
+        def run(decoder, **kw):
+            r = fer.simulate(g, e, decoder=decoder, gamma=1024, seed=seed, early_stop=True,
+                             min_frame_errors=1 << 62, max_frames=eval_frames, **kw)
+            return {"fer": r["fer"], "frame_errors": r["frame_errors"], "frames": r["frames"], "ber": r["ber"],
+                    "avg_iters": round(r["avg_iters"], 3), "coded_mbps": round(r["coded_mbps"], 1)}
+
+        row = {"ebn0_db": e, "learned_nms": run("nms", weights=W), "sp30": run("block", iters=30)}
+        if extra:
+            row["sp_T"] = run("block", iters=T)
+            row["nms_untrained"] = run("nms", weights=nnms.initial_weights(T, g.info["J"], 0.8, 0.0, device=dev))
+        rows.append(row)
+        if log:
+            log(row)
+    return {"T": T, "ckpt_every": ckpt_every, "train_frames": train_frames, "train_s": round(train_s, 2),
+            "train_frames_per_s": round(train_frames / train_s, 1),
+            "loss_first_last": [round(hist[0][1], 5), round(hist[-1][1], 5)],
+            "weights": {"scale": W[..., 0].cpu().numpy().round(4).tolist(),
+                        "offset": W[..., 1].cpu().numpy().round(4).tolist()},
+            "eval_frames_per_point": eval_frames, "points": rows}
+
+
+def nnms_report(args):
+    """Learned min-sum against plain sum-product on the paper-scale code:
+    training on 2^20 frames, 10^6 fresh frames per Eb/N0 point."""
+    import torch
+
+    import synth
+    from paper_1204_0334_amd import ldpc
+    torch.cuda.set_device(0)
+    spec = synth.WORKLOADS["qc36_p3060"]
+    g = ldpc.Graph.qc(synth.draw_qc_shifts(3, 6, spec["p"], spec["shift_seed"]), spec["p"])
+    points = [1.0, 1.25, 1.5, 1.75, 2.0, 2.25, 2.5]
+    res = learned_vs_plain(g, points, train_frames=args.train_frames, eval_frames=args.eval_frames, extra=True,
+                           log=lambda r: print(json.dumps(r), flush=True))
+    print(json.dumps({k: v for k, v in res.items() if k != "points"}), flush=True)
+    print()
+    print(f"Learned min-sum (T = {res['T']}, trained on {res['train_frames']} frames in {res['train_s']} s) "
+          f"against sum-product, n = 18360, {res['eval_frames_per_point']} frames per point, early stop")
+    print()
+    print("| Eb/N0 (dB) | SP-30 FER | SP-30 avg iters | learned NMS-12 FER | NMS-12 avg iters | SP-12 FER | "
+          "untrained NMS-12 FER |")
+    print("|---|---|---|---|---|---|---|")
+    for r in res["points"]:
+        print(f"| {r['ebn0_db']} | {r['sp30']['fer']:.3e} | {r['sp30']['avg_iters']:.2f} | "
+              f"{r['learned_nms']['fer']:.3e} | {r['learned_nms']['avg_iters']:.2f} | {r['sp_T']['fer']:.3e} | "
+              f"{r['nms_untrained']['fer']:.3e} |")
+
+
 def cpu_baseline(shifts, p, llr, iters, sample):
     import numpy as np
 
@@ -304,6 +374,12 @@ def main():
     ap.add_argument("--chain-positions", type=int, default=64, help="--paper-tables: code frames per stream")
     ap.add_argument("--streams", type=int, default=256, help="--paper-tables: streams per batch")
     ap.add_argument("--max-streams", type=int, default=4096, help="--paper-tables: stream cap per code")
+    ap.add_argument("--nnms", action="store_true",
+                    help="run the learned min-sum against sum-product FER comparison instead of the benchmark line")
+    ap.add_argument("--train-frames", type=int, default=1 << 20, help="learned min-sum: training frames")
+    ap.add_argument("--eval-frames", type=int, default=1_000_000, help="--nnms: frames per Eb/N0 point")
+    ap.add_argument("--fer-frames", type=int, default=1 << 17,
+                    help="benchmark line: frames per Eb/N0 point of its learned-vs-plain FER check (0: skip)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run 5 device-to-device copies of BYTES (counter calibration) and exit")
     args = ap.parse_args()
@@ -324,6 +400,9 @@ def main():
 
     if args.paper_tables:
         paper_tables(args)
+        return
+    if args.nnms:
+        nnms_report(args)
         return
     if args.workload in ("cc36_p512", "cc36_p512_pipeline"):
         bench_window(args, pipeline=args.workload.endswith("pipeline"))
@@ -390,6 +469,15 @@ def main():
     kernels = {k: {"launches": v[0], "avg_us": round(v[1] / v[0] * 1e3, 2)} for k, v in per_kernel.items() if v[0]}
 
     conv_rate = float(conv.float().mean().item())
+    learned = None
+    if args.fer_frames > 0:
+        learned = learned_vs_plain(g, [1.5, 1.75, 2.0, 2.25], train_frames=args.train_frames,
+                                   eval_frames=args.fer_frames)
+        learned = {"T": learned["T"], "train_frames": learned["train_frames"], "train_s": learned["train_s"],
+                   "frames_per_point": learned["eval_frames_per_point"],
+                   "points": [{"ebn0_db": r["ebn0_db"], "fer_learned_nms12": r["learned_nms"]["fer"],
+                               "fer_sp30": r["sp30"]["fer"], "avg_iters_learned": r["learned_nms"]["avg_iters"],
+                               "avg_iters_sp30": r["sp30"]["avg_iters"]} for r in learned["points"]]}
     cpu = None if args.no_cpu else cpu_baseline(shifts, p, llr_h, iters, min(args.cpu_sample, gamma))
     line = {
         "metric": METRIC, "value": round(value, 2), "unit": "coded Mbit/s", "n_gpus": 1, "steps": args.steps,
@@ -401,6 +489,7 @@ def main():
                    "n": n, "gamma": gamma, "iterations": iters, "early_stop": False,
                    "frames_converged": round(conv_rate, 4)},
         "roofline": roofline, "cpu_baseline": cpu, "kernels": kernels,
+        "fer_learned_vs_plain": learned,
     }
     print(json.dumps(line), flush=True)
 

@@ -168,6 +168,63 @@ ldpc_status ldpc_decode(const ldpc_graph* g, const float* llr, int32_t gamma, in
                         uint8_t* converged, void* workspace, size_t workspace_bytes, void* stream);
 
 /*
+ * Learned min-sum decoding (an addition to the paper: the neural normalized
+ * / offset min-sum of Nachmani et al. 2016/2018 and Lugosch & Gross 2017 on
+ * the flooding schedule of Algorithm 1).  The horizontal step (Eq. 3) is
+ * replaced, at iteration t for a check row of base row j, by
+ *   alpha_k = w[t][j] * s_k * max(m_k - b[t][j], 0),
+ * m_k = min(|beta_k'|) over the row's other edges (|beta| clipped at 30),
+ * s_k = product of their signs (negative iff beta < 0).  The vertical step
+ * (Eq. 4), the posterior (Eq. 5), the decision (Eq. 6), the clip of beta at
+ * +-30 and early stopping are those of ldpc_decode.
+ *   weights  device, float [iters][J][2]: (w, b) per iteration and base row
+ *   iters    iterations, 1..LDPC_MAX_ITERS (the weight rows used)
+ * Other arguments as for ldpc_decode (workspace from
+ * ldpc_workspace_size(g, gamma, iters, 0)).  Errors: those of ldpc_decode,
+ * and EINVAL for NULL weights.
+ */
+ldpc_status ldpc_nms_decode(const ldpc_graph* g, const float* llr, int32_t gamma, int32_t iters,
+                            const float* weights, int32_t early_stop, float* post, uint8_t* bits,
+                            int32_t* iters_out, uint8_t* converged, void* workspace, size_t workspace_bytes,
+                            void* stream);
+
+/*
+ * Training the learned min-sum weights: loss and gradient through T = iters
+ * unrolled iterations for frames of the all-zero codeword.  The loss of
+ * iteration t is the binary cross-entropy of its (unclipped) posterior
+ * against the transmitted bits, averaged over the gamma frames and n bits:
+ *   loss[t] = mean_{g, v} log(1 + exp(-L_gv^(t))).
+ *
+ * ldpc_nms_train_forward runs the T iterations, writes loss (device float
+ * [iters]) and keeps in the workspace the channel LLRs and the betas of
+ * iterations ckpt_every, 2 ckpt_every, ... (< iters).
+ *
+ * ldpc_nms_train_backward, called after ldpc_nms_train_forward on the same
+ * workspace with the same graph, gamma, iters, ckpt_every and weights,
+ * writes grad (device float [iters][J][2]) = d(sum_t dloss[t] loss[t]) /
+ * d weights, for dloss device float [iters] (the upstream gradient).  It
+ * recomputes each segment of ckpt_every iterations from its checkpoint
+ * and runs the hand-written backward of the vertical and horizontal steps
+ * through the segment, last iteration first.  The gradient of the minimum
+ * goes to the first edge holding it; the clips pass gradient inside
+ * [-30, 30] (inclusive), the offset's max(., 0) at >= 0; the gradient sums
+ * are reduced in a fixed order (deterministic for a given launch).
+ *
+ * ldpc_nms_train_workspace_size: bytes for (g, gamma, iters, ckpt_every).
+ * Errors: EINVAL (NULL pointers, convolutional graph, gamma < 1, iters
+ * outside [1, LDPC_MAX_ITERS], ckpt_every outside [1, iters], misaligned
+ * buffers), EWORKSPACE, EHIP.
+ */
+ldpc_status ldpc_nms_train_workspace_size(const ldpc_graph* g, int32_t gamma, int32_t iters, int32_t ckpt_every,
+                                          size_t* bytes);
+ldpc_status ldpc_nms_train_forward(const ldpc_graph* g, const float* llr, int32_t gamma, int32_t iters,
+                                   int32_t ckpt_every, const float* weights, float* loss, void* workspace,
+                                   size_t workspace_bytes, void* stream);
+ldpc_status ldpc_nms_train_backward(const ldpc_graph* g, int32_t gamma, int32_t iters, int32_t ckpt_every,
+                                    const float* weights, const float* dloss, float* grad, void* workspace,
+                                    size_t workspace_bytes, void* stream);
+
+/*
  * Sliding-window decoding of `gamma` independent streams of a terminated
  * convolutional graph (Sec. II-E: checks span at most ms+1 positions).  For
  * target position s = 0..positions-1: the window holds check layers
@@ -246,10 +303,12 @@ const char* ldpc_status_str(ldpc_status s);
  *   0 ingest, 1 check-node, 2 variable-node, 3 syndrome, 4 output,
  *   5 frame status, 6 window ingest, 7 window check-node,
  *   8 window variable-node, 9 pipeline ingest, 10 pipeline check-node,
- *   11 pipeline variable-node.
+ *   11 pipeline variable-node, 12 training check-node, 13 training
+ *   variable-node, 14 training variable-node backward, 15 training
+ *   check-node backward (with the gradient reduction).
  * ldpc_kernel_class_name returns a static name for a class index.
  */
-#define LDPC_TIMING_CLASSES 12
+#define LDPC_TIMING_CLASSES 16
 ldpc_status ldpc_timing_enable(int32_t enable);
 ldpc_status ldpc_timing_read(int64_t* launches, double* total_ms, int32_t capacity);
 const char* ldpc_kernel_class_name(int32_t cls);

@@ -138,9 +138,9 @@ __device__ __forceinline__ void tq_of(float b, float& t, float& q) {
 // b = rstart[j] + k (base columns ascending), package b*p + s, variable
 // ecol[b]*p + (s + a) mod p.
 struct QCRow {
-    int b0, d, s;
+    int b0, d, s, j;
     __device__ __forceinline__ QCRow(const QCDesc& D, int row) {
-        const int j = row / D.p;
+        j = row / D.p;
         s = row - j * D.p;
         b0 = D.rstart[j];
         d = D.rstart[j + 1] - b0;
@@ -290,32 +290,55 @@ struct BlockParams {
     uint64_t* unsat;         // [max_iters+1][tiles][FPL]
     uint64_t* frozen;        // [max_iters+1][tiles][FPL]
     int gamma, tiles, iter, last, early;
+    const float* nms_w;      // learned min-sum: device [iters][J][2] (scale, offset); NULL = sum-product
 };
 
-// Check-node pass of iteration P.iter.  With early stopping, also ORs the
-// syndrome of iteration iter-1's decisions into unsat[iter-1] and skips tiles
-// whose frames were all frozen by iteration iter-2.
-template <int DCMAX, int FPL>
-__global__ void __launch_bounds__(kBlock) cn_block_kernel(const QCDesc D, const BlockParams P) {
-    constexpr int Gt = 64 * FPL;
-    const int lane = threadIdx.x & 63;
-    const int wave = blockIdx.x * kWavesPerBlock + wave_in_block();
-    const int tile = wave / D.m;
-    const int row = wave - tile * D.m;
-    if (tile >= P.tiles) return;
-    const int nvalid = min(P.gamma - tile * Gt, Gt);
+// Learned min-sum check rule for one frame (neural normalized-offset
+// min-sum): alpha_k = w * s_k * max(m_k - b, 0), m_k the smallest |beta| of
+// the other edges, s_k the product of their signs (negative iff beta < 0).
+// Unused slots carry |beta| = +inf.  Also returns the first index of the
+// minimum and the second minimum (for the backward pass).
+struct MinInfo {
+    float min1, min2;
+    int idx1, idx2;
+    uint32_t parity;
+};
 
+template <int DC>
+__device__ __forceinline__ MinInfo row_minima(const float (&mag)[DC], const uint32_t (&neg)[DC]) {
+    MinInfo r{__builtin_inff(), __builtin_inff(), -1, -1, 0u};
+#pragma unroll
+    for (int k = 0; k < DC; ++k) {
+        const float m = mag[k];
+        if (m < r.min1) {
+            r.min2 = r.min1;
+            r.idx2 = r.idx1;
+            r.min1 = m;
+            r.idx1 = k;
+        } else if (m < r.min2) {
+            r.min2 = m;
+            r.idx2 = k;
+        }
+        r.parity ^= neg[k];
+    }
+    return r;
+}
+
+// Check-node pass, prologue shared by both check rules: with early stopping,
+// skip tiles whose frames were all frozen by iteration iter-2, and OR the
+// syndrome of iteration iter-1's decisions into unsat[iter-1].  Returns false
+// when the wave has nothing to do.
+template <int DCMAX, int FPL>
+__device__ __forceinline__ bool cn_prologue(const QCDesc& D, const BlockParams& P, const QCRow& R, int tile,
+                                            int lane, int nvalid) {
     if (P.early && P.iter >= 3) {
         const uint64_t* fz = P.frozen + ((size_t)(P.iter - 2) * P.tiles + tile) * FPL;
         bool all = true;
 #pragma unroll
         for (int f = 0; f < FPL; ++f) all = all && (fz[f] == ~0ull);
-        if (all) return;
+        if (all) return false;
     }
-    const QCRow R(D, row);
-
     if (P.early && P.iter >= 2) {
-        // syndrome of the previous iteration's decisions for this row
         uint64_t par[FPL];
 #pragma unroll
         for (int f = 0; f < FPL; ++f) par[f] = 0;
@@ -340,54 +363,104 @@ __global__ void __launch_bounds__(kBlock) cn_block_kernel(const QCDesc D, const 
             }
         }
     }
+    return true;
+}
 
-    // gather the row's messages (iteration 1 reads the channel LLRs)
+// Horizontal step of iteration P.iter for the check row R and the 64*FPL
+// frames of the wave, reading beta from `src` (iteration 1: the channel LLRs
+// gathered from `mu`) and writing alpha to `dst` (which may be `src`: each
+// package belongs to one row).  RULE 0: sum-product (Eq. 3); RULE 1: learned
+// min-sum with the weights of P.nms_w.
+template <int DCMAX, int FPL, int RULE>
+__device__ __forceinline__ void cn_row(const QCDesc& D, const BlockParams& P, const QCRow& R, int tile, int lane,
+                                       const float* src, const float* mu, float* dst, bool from_mu) {
+    constexpr int Gt = 64 * FPL;
     const size_t lane_off = (size_t)lane * FPL;
-    float t[FPL][DCMAX], q[FPL][DCMAX];
-    uint32_t sgn[FPL];
-#pragma unroll
-    for (int f = 0; f < FPL; ++f) sgn[f] = 0;
-    float* mt = P.msg + (size_t)tile * D.E * Gt + lane_off;
-    const float* ut = P.mu + (size_t)tile * D.n * Gt + lane_off;
+    const float* st = src + (size_t)tile * D.E * Gt + lane_off;
+    const float* ut = mu + (size_t)tile * D.n * Gt + lane_off;
+    float* dt = dst + (size_t)tile * D.E * Gt + lane_off;
     float in[DCMAX][FPL];
 #pragma unroll
     for (int k = 0; k < DCMAX; ++k) {
         if (R.valid(D, k)) {
-            const float* src = (P.iter == 1) ? ut + (size_t)R.var(D, k) * Gt : mt + (size_t)R.pkg(D, k) * Gt;
-            load_frames<FPL>(src, in[k]);
+            const float* s = from_mu ? ut + (size_t)R.var(D, k) * Gt : st + (size_t)R.pkg(D, k) * Gt;
+            load_frames<FPL>(s, in[k]);
         } else {
 #pragma unroll
             for (int f = 0; f < FPL; ++f) in[k][f] = 0.0f;
         }
     }
-#pragma unroll
-    for (int k = 0; k < DCMAX; ++k) {
-        const bool ok = R.valid(D, k);
-#pragma unroll
-        for (int f = 0; f < FPL; ++f) {
-            if (ok) {
-                tq_of(in[k][f], t[f][k], q[f][k]);
-                sgn[f] ^= __float_as_uint(in[k][f]) & 0x80000000u;
-            } else {
-                t[f][k] = 1.0f;
-                q[f][k] = 0.0f;
-            }
-        }
-    }
     float outv[DCMAX][FPL];
+    if constexpr (RULE == 0) {
+        float t[FPL][DCMAX], q[FPL][DCMAX];
+        uint32_t sgn[FPL];
 #pragma unroll
-    for (int f = 0; f < FPL; ++f) {
-        float mag[DCMAX];
-        boxplus_fb<DCMAX>(t[f], q[f], mag);
+        for (int f = 0; f < FPL; ++f) sgn[f] = 0;
 #pragma unroll
         for (int k = 0; k < DCMAX; ++k) {
-            const uint32_t s = sgn[f] ^ (__float_as_uint(in[k][f]) & 0x80000000u);
-            outv[k][f] = __uint_as_float(__float_as_uint(mag[k]) | s);
+            const bool ok = R.valid(D, k);
+#pragma unroll
+            for (int f = 0; f < FPL; ++f) {
+                if (ok) {
+                    tq_of(in[k][f], t[f][k], q[f][k]);
+                    sgn[f] ^= __float_as_uint(in[k][f]) & 0x80000000u;
+                } else {
+                    t[f][k] = 1.0f;
+                    q[f][k] = 0.0f;
+                }
+            }
+        }
+#pragma unroll
+        for (int f = 0; f < FPL; ++f) {
+            float mag[DCMAX];
+            boxplus_fb<DCMAX>(t[f], q[f], mag);
+#pragma unroll
+            for (int k = 0; k < DCMAX; ++k) {
+                const uint32_t sg = sgn[f] ^ (__float_as_uint(in[k][f]) & 0x80000000u);
+                outv[k][f] = __uint_as_float(__float_as_uint(mag[k]) | sg);
+            }
+        }
+    } else {
+        const float* wp = P.nms_w + ((size_t)(P.iter - 1) * D.J + R.j) * 2;
+        const float w = wp[0], b = wp[1];
+#pragma unroll
+        for (int f = 0; f < FPL; ++f) {
+            float mag[DCMAX];
+            uint32_t neg[DCMAX];
+#pragma unroll
+            for (int k = 0; k < DCMAX; ++k) {
+                const bool ok = R.valid(D, k);
+                mag[k] = ok ? fminf(fabsf(in[k][f]), kClip) : __builtin_inff();
+                neg[k] = ok ? (uint32_t)(in[k][f] < 0.0f) : 0u;
+            }
+            const MinInfo mi = row_minima<DCMAX>(mag, neg);
+#pragma unroll
+            for (int k = 0; k < DCMAX; ++k) {
+                const float m = (k == mi.idx1) ? mi.min2 : mi.min1;
+                const float a = w * fmaxf(m - b, 0.0f);
+                outv[k][f] = (mi.parity ^ neg[k]) ? -a : a;
+            }
         }
     }
 #pragma unroll
     for (int k = 0; k < DCMAX; ++k)
-        if (R.valid(D, k)) store_frames<FPL>(mt + (size_t)R.pkg(D, k) * Gt, outv[k]);
+        if (R.valid(D, k)) store_frames<FPL>(dt + (size_t)R.pkg(D, k) * Gt, outv[k]);
+}
+
+// Check-node pass of iteration P.iter (in place in P.msg; iteration 1 reads
+// the channel LLRs).
+template <int DCMAX, int FPL, int RULE>
+__global__ void __launch_bounds__(kBlock) cn_block_kernel(const QCDesc D, const BlockParams P) {
+    constexpr int Gt = 64 * FPL;
+    const int lane = threadIdx.x & 63;
+    const int wave = blockIdx.x * kWavesPerBlock + wave_in_block();
+    const int tile = wave / D.m;
+    const int row = wave - tile * D.m;
+    if (tile >= P.tiles) return;
+    const int nvalid = min(P.gamma - tile * Gt, Gt);
+    const QCRow R(D, row);
+    if (!cn_prologue<DCMAX, FPL>(D, P, R, tile, lane, nvalid)) return;
+    cn_row<DCMAX, FPL, RULE>(D, P, R, tile, lane, P.msg, P.mu, P.msg, P.iter == 1);
 }
 
 // Frames of a tile frozen before iteration P.iter (bit set = frozen; padding
@@ -632,6 +705,309 @@ __global__ void frame_status_kernel(const BlockParams P, int max_iters, int32_t*
     if (iters) iters[g] = it;
     if (converged) converged[g] = (uint8_t)ok;
 }
+
+// ---------------------------------------------------------------------------
+// kernels: training the learned min-sum decoder (forward with checkpoints,
+// backward through the unrolled iterations).  The transmitted codeword is
+// all-zero, so the loss of a posterior L is softplus(-L).
+// ---------------------------------------------------------------------------
+
+// Forward check-node pass of a training step: beta from `src` (NULL: the
+// channel LLRs), alpha to `dst`, learned rule.
+template <int DCMAX, int FPL>
+__global__ void __launch_bounds__(kBlock) nms_train_cn_kernel(const QCDesc D, const BlockParams P, const float* src,
+                                                              float* dst) {
+    const int lane = threadIdx.x & 63;
+    const int wave = blockIdx.x * kWavesPerBlock + wave_in_block();
+    const int tile = wave / D.m;
+    const int row = wave - tile * D.m;
+    if (tile >= P.tiles) return;
+    const QCRow R(D, row);
+    cn_row<DCMAX, FPL, 1>(D, P, R, tile, lane, src ? src : P.mu, P.mu, dst, src == nullptr);
+}
+
+__device__ __forceinline__ float softplus_neg(float L) {   // log(1 + exp(-L))
+    return fmaxf(-L, 0.0f) + log1pf(__expf(-fabsf(L)));
+}
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+// Forward variable-node pass of a training step: alpha from A, beta to dst
+// (NULL: not needed), and, when `lpart` is not NULL, the wave's share of the
+// iteration's mean loss (sum of softplus(-L) over its valid frames, times
+// inv_count = 1 / (gamma n)) written to lpart[wave].
+template <int DVMAX, int FPL>
+__global__ void __launch_bounds__(kBlock) nms_train_vn_kernel(const QCDesc D, const BlockParams P, const float* A,
+                                                              float* dst, float* lpart, float inv_count) {
+    constexpr int Gt = 64 * FPL;
+    const int lane = threadIdx.x & 63;
+    const int wave = blockIdx.x * kWavesPerBlock + wave_in_block();
+    const int tile = wave / D.n;
+    const int col = wave - tile * D.n;
+    if (tile >= P.tiles) return;
+    const int nvalid = min(P.gamma - tile * Gt, Gt);
+    const QCCol C(D, col);
+    const size_t lane_off = (size_t)lane * FPL;
+    const size_t base = (size_t)tile * D.E * Gt + lane_off;
+    float mu[FPL];
+    load_frames<FPL>(P.mu + ((size_t)tile * D.n + C.v) * Gt + lane_off, mu);
+    float a[DVMAX][FPL];
+#pragma unroll
+    for (int k = 0; k < DVMAX; ++k) {
+        if (C.valid(D, k)) {
+            load_frames<FPL>(A + base + (size_t)C.pkg(D, k) * Gt, a[k]);
+        } else {
+#pragma unroll
+            for (int f = 0; f < FPL; ++f) a[k][f] = 0.0f;
+        }
+    }
+    float b[DVMAX][FPL];
+    float lsum = 0.0f;
+#pragma unroll
+    for (int f = 0; f < FPL; ++f) {
+        float suf[DVMAX];
+        float S = 0.0f;
+#pragma unroll
+        for (int k = DVMAX - 1; k >= 0; --k) {
+            suf[k] = S;
+            S += a[k][f];
+        }
+        float pre = 0.0f;
+#pragma unroll
+        for (int k = 0; k < DVMAX; ++k) {
+            b[k][f] = clip30(mu[f] + (pre + suf[k]));
+            pre += a[k][f];
+        }
+        const float L = mu[f] + pre;
+        if (lane * FPL + f < nvalid) lsum += softplus_neg(L);
+    }
+#pragma unroll
+    for (int k = 0; k < DVMAX; ++k) {
+        if (!C.valid(D, k)) continue;
+        if (dst) store_frames<FPL>(dst + base + (size_t)C.pkg(D, k) * Gt, b[k]);
+    }
+    if (lpart) {
+        lsum = wave_sum(lsum);
+        if (lane == 0) lpart[wave] = lsum * inv_count;
+    }
+}
+
+// Backward of the variable-node pass of iteration P.iter.  Inputs: alpha of
+// the iteration (A), the gradient with respect to its betas (dB; NULL at the
+// last iteration, whose betas are not used).  The iteration's mean loss, with
+// upstream gradient dloss[iter-1], contributes dloss/dL = -dloss[iter-1] *
+// inv_count / (1 + exp(L)) on valid frames.  Output: the gradient with
+// respect to the iteration's alphas, dA_k = dL + sum_{k' != k} dB_k' [beta_k'
+// not clipped].
+template <int DVMAX, int FPL>
+__global__ void __launch_bounds__(kBlock) nms_vn_backward_kernel(const QCDesc D, const BlockParams P, const float* A,
+                                                                 const float* dB, float* dA, const float* dloss,
+                                                                 float inv_count) {
+    constexpr int Gt = 64 * FPL;
+    const int lane = threadIdx.x & 63;
+    const int wave = blockIdx.x * kWavesPerBlock + wave_in_block();
+    const int tile = wave / D.n;
+    const int col = wave - tile * D.n;
+    if (tile >= P.tiles) return;
+    const int nvalid = min(P.gamma - tile * Gt, Gt);
+    const QCCol C(D, col);
+    const size_t lane_off = (size_t)lane * FPL;
+    const size_t base = (size_t)tile * D.E * Gt + lane_off;
+    const float scale = dloss[P.iter - 1] * inv_count;
+    float mu[FPL];
+    load_frames<FPL>(P.mu + ((size_t)tile * D.n + C.v) * Gt + lane_off, mu);
+    float a[DVMAX][FPL], gb[DVMAX][FPL];
+#pragma unroll
+    for (int k = 0; k < DVMAX; ++k) {
+        const bool ok = C.valid(D, k);
+        if (ok) {
+            load_frames<FPL>(A + base + (size_t)C.pkg(D, k) * Gt, a[k]);
+        } else {
+#pragma unroll
+            for (int f = 0; f < FPL; ++f) a[k][f] = 0.0f;
+        }
+        if (ok && dB) {
+            load_frames<FPL>(dB + base + (size_t)C.pkg(D, k) * Gt, gb[k]);
+        } else {
+#pragma unroll
+            for (int f = 0; f < FPL; ++f) gb[k][f] = 0.0f;
+        }
+    }
+    float out[DVMAX][FPL];
+#pragma unroll
+    for (int f = 0; f < FPL; ++f) {
+        float suf[DVMAX];
+        float S = 0.0f;
+#pragma unroll
+        for (int k = DVMAX - 1; k >= 0; --k) {
+            suf[k] = S;
+            S += a[k][f];
+        }
+        float pre = 0.0f, g[DVMAX];
+#pragma unroll
+        for (int k = 0; k < DVMAX; ++k) {
+            const float beta = mu[f] + (pre + suf[k]);          // before the clip
+            g[k] = (fabsf(beta) <= kClip) ? gb[k][f] : 0.0f;
+            pre += a[k][f];
+        }
+        const float L = mu[f] + pre;
+        const float dL = (lane * FPL + f < nvalid) ? -scale / (1.0f + __expf(L)) : 0.0f;
+        float gs[DVMAX];
+        float G = 0.0f;
+#pragma unroll
+        for (int k = DVMAX - 1; k >= 0; --k) {
+            gs[k] = G;
+            G += g[k];
+        }
+        float gp = 0.0f;
+#pragma unroll
+        for (int k = 0; k < DVMAX; ++k) {
+            out[k][f] = dL + (gp + gs[k]);
+            gp += g[k];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < DVMAX; ++k)
+        if (C.valid(D, k)) store_frames<FPL>(dA + base + (size_t)C.pkg(D, k) * Gt, out[k]);
+}
+
+__device__ __forceinline__ float abs_grad(float x) { return x > 0.0f ? 1.0f : (x < 0.0f ? -1.0f : 0.0f); }
+
+// Backward of the check-node pass of iteration P.iter.  Inputs: the betas the
+// pass read (src; NULL at iteration 1: the channel LLRs, whose gradient is not
+// needed) and the gradient with respect to its alphas (dA).  With
+// m_k = min over the other edges, s_k their sign product, a_k = m_k - b:
+//   dw += dA_k s_k max(a_k, 0),  db -= dA_k w s_k [a_k > 0],
+//   the gradient w s_k [a_k > 0] dA_k reaches |beta| of the edge holding m_k
+// (the row minimum for k != argmin, the second minimum for k = argmin).
+// Writes dB (gradient with respect to the betas read; NULL at iteration 1) and
+// the wave's (dw, db) partial sums.
+template <int DCMAX, int FPL>
+__global__ void __launch_bounds__(kBlock) nms_cn_backward_kernel(const QCDesc D, const BlockParams P,
+                                                                 const float* src, const float* dA, float* dB,
+                                                                 float2* partial) {
+    constexpr int Gt = 64 * FPL;
+    const int lane = threadIdx.x & 63;
+    const int wave = blockIdx.x * kWavesPerBlock + wave_in_block();
+    const int tile = wave / D.m;
+    const int row = wave - tile * D.m;
+    if (tile >= P.tiles) return;
+    const QCRow R(D, row);
+    const size_t lane_off = (size_t)lane * FPL;
+    const size_t base = (size_t)tile * D.E * Gt + lane_off;
+    const float* ut = P.mu + (size_t)tile * D.n * Gt + lane_off;
+    float in[DCMAX][FPL], da[DCMAX][FPL];
+#pragma unroll
+    for (int k = 0; k < DCMAX; ++k) {
+        if (R.valid(D, k)) {
+            load_frames<FPL>(src ? src + base + (size_t)R.pkg(D, k) * Gt : ut + (size_t)R.var(D, k) * Gt, in[k]);
+            load_frames<FPL>(dA + base + (size_t)R.pkg(D, k) * Gt, da[k]);
+        } else {
+#pragma unroll
+            for (int f = 0; f < FPL; ++f) {
+                in[k][f] = 0.0f;
+                da[k][f] = 0.0f;
+            }
+        }
+    }
+    const float* wp = P.nms_w + ((size_t)(P.iter - 1) * D.J + R.j) * 2;
+    const float w = wp[0], b = wp[1];
+    float dw = 0.0f, db = 0.0f;
+    float out[DCMAX][FPL];
+#pragma unroll
+    for (int f = 0; f < FPL; ++f) {
+        float mag[DCMAX];
+        uint32_t neg[DCMAX];
+#pragma unroll
+        for (int k = 0; k < DCMAX; ++k) {
+            const bool ok = R.valid(D, k);
+            mag[k] = ok ? fminf(fabsf(in[k][f]), kClip) : __builtin_inff();
+            neg[k] = ok ? (uint32_t)(in[k][f] < 0.0f) : 0u;
+        }
+        const MinInfo mi = row_minima<DCMAX>(mag, neg);
+        float G1 = 0.0f, G2 = 0.0f;
+#pragma unroll
+        for (int k = 0; k < DCMAX; ++k) {
+            if (!R.valid(D, k)) continue;
+            const float m = (k == mi.idx1) ? mi.min2 : mi.min1;
+            const float sg = (mi.parity ^ neg[k]) ? -1.0f : 1.0f;
+            const float a = m - b;
+            const float act = a >= 0.0f ? 1.0f : 0.0f;
+            dw += da[k][f] * sg * fmaxf(a, 0.0f);
+            db -= da[k][f] * w * sg * act;
+            const float gk = da[k][f] * w * sg * act;
+            if (k == mi.idx1) G2 = gk;
+            else G1 += gk;
+        }
+#pragma unroll
+        for (int k = 0; k < DCMAX; ++k) {
+            float v = 0.0f;
+            if (k == mi.idx1) v = G1 * abs_grad(in[k][f]);
+            if (k == mi.idx2) v = G2 * abs_grad(in[k][f]);
+            out[k][f] = v;
+        }
+    }
+    if (dB) {
+#pragma unroll
+        for (int k = 0; k < DCMAX; ++k)
+            if (R.valid(D, k)) store_frames<FPL>(dB + base + (size_t)R.pkg(D, k) * Gt, out[k]);
+    }
+    dw = wave_sum(dw);
+    db = wave_sum(db);
+    if (lane == 0) partial[wave] = make_float2(dw, db);
+}
+
+// grad[t][j] = sum of the check-node backward partials of iteration t + 1
+// over the rows of base row j, in a fixed order; grid (J, T), partial
+// [T][tiles * m].
+__global__ void __launch_bounds__(256) nms_grad_reduce_kernel(const QCDesc D, const float2* partial, int tiles,
+                                                              float* grad) {
+    __shared__ float sw[256], sb[256];
+    const int j = blockIdx.x, t = blockIdx.y;
+    const float2* pt = partial + (size_t)t * tiles * D.m;
+    float aw = 0.0f, ab = 0.0f;
+    for (int i = threadIdx.x; i < tiles * D.p; i += 256) {
+        const int tile = i / D.p, s = i - tile * D.p;
+        const float2 v = pt[(size_t)tile * D.m + (size_t)j * D.p + s];
+        aw += v.x;
+        ab += v.y;
+    }
+    sw[threadIdx.x] = aw;
+    sb[threadIdx.x] = ab;
+    __syncthreads();
+    for (int h = 128; h >= 1; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            sw[threadIdx.x] += sw[threadIdx.x + h];
+            sb[threadIdx.x] += sb[threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        grad[((size_t)t * D.J + j) * 2 + 0] = sw[0];
+        grad[((size_t)t * D.J + j) * 2 + 1] = sb[0];
+    }
+}
+
+// loss[t] = sum of the count wave partials of iteration t + 1, in a fixed
+// order; one block per iteration.
+__global__ void __launch_bounds__(256) nms_loss_reduce_kernel(const float* lpart, int64_t count, float* loss) {
+    __shared__ float sl[256];
+    const float* pt = lpart + (size_t)blockIdx.x * count;
+    float a = 0.0f;
+    for (int64_t i = threadIdx.x; i < count; i += 256) a += pt[i];
+    sl[threadIdx.x] = a;
+    __syncthreads();
+    for (int h = 128; h >= 1; h >>= 1) {
+        if ((int)threadIdx.x < h) sl[threadIdx.x] += sl[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) loss[blockIdx.x] = sl[0];
+}
+
 
 // ---------------------------------------------------------------------------
 // kernels: layout changes (frame-major <-> packages), through LDS
@@ -1136,7 +1512,7 @@ static unsigned grid_for_waves(int64_t waves) {
 template <int FPL>
 static void run_block(const ldpc_graph* g, const float* llr, int gamma, int max_iters, int early, float* post,
                       uint8_t* bits, int32_t* iters, uint8_t* converged, char* ws, const BlockLayout& lay,
-                      const Tiling& tl, hipStream_t st) {
+                      const Tiling& tl, hipStream_t st, const float* nms_w) {
     const QCDesc& D = g->qc;
     BlockParams P{};
     P.msg = reinterpret_cast<float*>(ws + lay.msg);
@@ -1147,6 +1523,7 @@ static void run_block(const ldpc_graph* g, const float* llr, int gamma, int max_
     P.gamma = gamma;
     P.tiles = tl.tiles;
     P.early = early;
+    P.nms_w = nms_w;
 
     {
         timing::Scope ts(0, st);
@@ -1165,7 +1542,10 @@ static void run_block(const ldpc_graph* g, const float* llr, int gamma, int max_
         {
             timing::Scope ts(1, st);
             LDPC_DC_SWITCH(dcc, if constexpr (DC <= MaxDC<FPL>::value) {
-                cn_block_kernel<DC, FPL><<<cn_grid, kBlock, 0, st>>>(D, P);
+                if (nms_w)
+                    cn_block_kernel<DC, FPL, 1><<<cn_grid, kBlock, 0, st>>>(D, P);
+                else
+                    cn_block_kernel<DC, FPL, 0><<<cn_grid, kBlock, 0, st>>>(D, P);
             });
         }
         {
@@ -1187,6 +1567,156 @@ static void run_block(const ldpc_graph* g, const float* llr, int gamma, int max_
         timing::Scope ts(5, st);
         frame_status_kernel<FPL><<<(gamma + 255) / 256, 256, 0, st>>>(P, max_iters, iters, converged);
     }
+}
+
+// Learned min-sum training: workspace holds the packaged channel LLRs, the
+// betas at the checkpoints k, 2k, ... (< T), one segment of recomputed alphas
+// (k) and betas (k - 1), the gradient buffers, and the per-wave partial sums
+// of the loss ([T][tiles n]) and of the gradient ([T][tiles m] pairs).
+struct TrainLayout {
+    int k, nck, seg_b;
+    size_t arr, mu, ckpt, A, B, dA, dB, lpart, gpart, total;
+};
+
+static TrainLayout train_layout(const ldpc_graph* g, const Tiling& t, int T, int k) {
+    TrainLayout L{};
+    L.k = k;
+    L.nck = (T + k - 1) / k - 1;
+    L.seg_b = std::max(k - 1, 1);
+    L.arr = align256((size_t)t.gpad * g->E * sizeof(float));
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
+    L.mu = take((size_t)t.gpad * g->n * sizeof(float));
+    L.ckpt = take(L.arr * L.nck);
+    L.A = take(L.arr * k);
+    L.B = take(L.arr * L.seg_b);
+    L.dA = take(L.arr);
+    L.dB = take(L.arr);
+    L.lpart = take((size_t)T * t.tiles * g->n * sizeof(float));
+    L.gpart = take((size_t)T * t.tiles * g->m * sizeof(float2));
+    L.total = off;
+    return L;
+}
+
+struct TrainRun {
+    const ldpc_graph* g;
+    QCDesc D;
+    BlockParams P;
+    TrainLayout L;
+    Tiling tl;
+    char* ws;
+    hipStream_t st;
+    int T;
+    float inv_count;
+    float* arr(size_t base, int i) const { return reinterpret_cast<float*>(ws + base + L.arr * (size_t)i); }
+    // beta at checkpoint iteration c (c = 0: the channel LLRs, read from mu)
+    float* ckpt(int c) const { return c == 0 ? nullptr : arr(L.ckpt, c / L.k - 1); }
+};
+
+static TrainRun make_train_run(const ldpc_graph* g, int gamma, int T, int k, const float* w, char* ws,
+                               const Tiling& tl, hipStream_t st) {
+    TrainRun r{};
+    r.g = g;
+    r.D = g->qc;
+    r.L = train_layout(g, tl, T, k);
+    r.tl = tl;
+    r.ws = ws;
+    r.st = st;
+    r.T = T;
+    r.inv_count = (float)(1.0 / ((double)gamma * g->n));
+    r.P.mu = reinterpret_cast<const float*>(ws + r.L.mu);
+    r.P.gamma = gamma;
+    r.P.tiles = tl.tiles;
+    r.P.nms_w = w;
+    return r;
+}
+
+template <int FPL>
+static void train_cn(TrainRun& r, int t, const float* src, float* dst) {
+    r.P.iter = t;
+    const unsigned grid = grid_for_waves((int64_t)r.D.m * r.tl.tiles);
+    timing::Scope ts(12, r.st);
+    LDPC_DC_SWITCH(dc_class(r.D.dc_max), if constexpr (DC <= MaxDC<FPL>::value) {
+        nms_train_cn_kernel<DC, FPL><<<grid, kBlock, 0, r.st>>>(r.D, r.P, src, dst);
+    });
+}
+
+template <int FPL>
+static void train_vn(TrainRun& r, int t, const float* A, float* dst, bool with_loss) {
+    r.P.iter = t;
+    const int64_t waves = (int64_t)r.D.n * r.tl.tiles;
+    float* lpart = with_loss ? reinterpret_cast<float*>(r.ws + r.L.lpart) + (size_t)(t - 1) * waves : nullptr;
+    timing::Scope ts(13, r.st);
+    LDPC_DV_SWITCH(dv_class(r.D.dv_max), (nms_train_vn_kernel<DV, FPL><<<grid_for_waves(waves), kBlock, 0, r.st>>>(
+                                             r.D, r.P, A, dst, lpart, r.inv_count)));
+}
+
+template <int FPL>
+static void train_forward(TrainRun& r, const float* llr, float* loss) {
+    {
+        timing::Scope ts(0, r.st);
+        dim3 grid((r.g->n + 63) / 64, r.tl.gpad / 64);
+        to_packages_kernel<<<grid, 256, 0, r.st>>>(llr, r.g->n, 0, r.g->n, r.P.gamma, r.tl.gpad, r.tl.gt,
+                                                   reinterpret_cast<float*>(r.ws + r.L.mu),
+                                                   (int64_t)r.g->n * r.tl.gt, nullptr, 0);
+    }
+    const float* src = nullptr;
+    for (int t = 1; t <= r.T; ++t) {
+        float* A = r.arr(r.L.A, 0);
+        train_cn<FPL>(r, t, src, A);
+        float* dst = nullptr;
+        if (t < r.T) dst = (t % r.L.k == 0) ? r.ckpt(t) : r.arr(r.L.B, 0);
+        train_vn<FPL>(r, t, A, dst, true);
+        src = dst;
+    }
+    timing::Scope ts(13, r.st);
+    nms_loss_reduce_kernel<<<r.T, 256, 0, r.st>>>(reinterpret_cast<const float*>(r.ws + r.L.lpart),
+                                                  (int64_t)r.D.n * r.tl.tiles, loss);
+}
+
+template <int FPL>
+static void train_backward(TrainRun& r, const float* dloss, float* grad) {
+    const QCDesc& D = r.D;
+    const int k = r.L.k;
+    float* dA = r.arr(r.L.dA, 0);
+    float* dB = r.arr(r.L.dB, 0);
+    float2* gpart = reinterpret_cast<float2*>(r.ws + r.L.gpart);
+    const unsigned cn_grid = grid_for_waves((int64_t)D.m * r.tl.tiles);
+    const unsigned vn_grid = grid_for_waves((int64_t)D.n * r.tl.tiles);
+    const int dcc = dc_class(D.dc_max), dvc = dv_class(D.dv_max);
+    for (int c = (r.T - 1) / k * k; c >= 0; c -= k) {
+        const int e = std::min(c + k, r.T);
+        // recompute alphas c+1..e and betas c+1..e-1 from the checkpoint at c
+        const float* src = r.ckpt(c);
+        for (int t = c + 1; t <= e; ++t) {
+            float* A = r.arr(r.L.A, t - c - 1);
+            train_cn<FPL>(r, t, src, A);
+            float* dst = t < e ? r.arr(r.L.B, t - c - 1) : nullptr;
+            train_vn<FPL>(r, t, A, dst, false);
+            src = dst;
+        }
+        for (int t = e; t > c; --t) {
+            r.P.iter = t;
+            {
+                timing::Scope ts(14, r.st);
+                const float* A = r.arr(r.L.A, t - c - 1);
+                const float* dBin = t == r.T ? nullptr : dB;
+                LDPC_DV_SWITCH(dvc, (nms_vn_backward_kernel<DV, FPL><<<vn_grid, kBlock, 0, r.st>>>(
+                                        D, r.P, A, dBin, dA, dloss, r.inv_count)));
+            }
+            {
+                timing::Scope ts(15, r.st);
+                const float* bsrc = t == c + 1 ? r.ckpt(c) : r.arr(r.L.B, t - c - 2);
+                float* dBout = t == 1 ? nullptr : dB;
+                float2* part = gpart + (size_t)(t - 1) * r.tl.tiles * D.m;
+                LDPC_DC_SWITCH(dcc, if constexpr (DC <= MaxDC<FPL>::value) {
+                    nms_cn_backward_kernel<DC, FPL><<<cn_grid, kBlock, 0, r.st>>>(D, r.P, bsrc, dA, dBout, part);
+                });
+            }
+        }
+    }
+    timing::Scope ts(15, r.st);
+    nms_grad_reduce_kernel<<<dim3(D.J, r.T), 256, 0, r.st>>>(D, gpart, r.tl.tiles, grad);
 }
 
 // host-side helpers for the convolutional schedules
@@ -1356,9 +1886,9 @@ ldpc_status ldpc_workspace_size(const ldpc_graph* g, int32_t gamma, int32_t max_
     return LDPC_OK;
 }
 
-ldpc_status ldpc_decode(const ldpc_graph* g, const float* llr, int32_t gamma, int32_t max_iters, int32_t early_stop,
-                        float* post, uint8_t* bits, int32_t* iters, uint8_t* converged, void* workspace,
-                        size_t workspace_bytes, void* stream) {
+static ldpc_status decode_block(const ldpc_graph* g, const float* llr, int32_t gamma, int32_t max_iters,
+                                int32_t early_stop, float* post, uint8_t* bits, int32_t* iters, uint8_t* converged,
+                                void* workspace, size_t workspace_bytes, void* stream, const float* nms_w) {
     if (!g || !llr || !post || !bits) return LDPC_EINVAL;
     if (g->kind != LDPC_GRAPH_QC) return LDPC_EINVAL;
     if (gamma < 1 || max_iters < 1 || max_iters > LDPC_MAX_ITERS) return LDPC_EINVAL;
@@ -1372,9 +1902,9 @@ ldpc_status ldpc_decode(const ldpc_graph* g, const float* llr, int32_t gamma, in
     char* ws = reinterpret_cast<char*>(workspace);
     (void)hipGetLastError();
     switch (tl.fpl) {
-        case 4: run_block<4>(g, llr, gamma, max_iters, early_stop ? 1 : 0, post, bits, iters, converged, ws, lay, tl, st); break;
-        case 2: run_block<2>(g, llr, gamma, max_iters, early_stop ? 1 : 0, post, bits, iters, converged, ws, lay, tl, st); break;
-        default: run_block<1>(g, llr, gamma, max_iters, early_stop ? 1 : 0, post, bits, iters, converged, ws, lay, tl, st); break;
+        case 4: run_block<4>(g, llr, gamma, max_iters, early_stop ? 1 : 0, post, bits, iters, converged, ws, lay, tl, st, nms_w); break;
+        case 2: run_block<2>(g, llr, gamma, max_iters, early_stop ? 1 : 0, post, bits, iters, converged, ws, lay, tl, st, nms_w); break;
+        default: run_block<1>(g, llr, gamma, max_iters, early_stop ? 1 : 0, post, bits, iters, converged, ws, lay, tl, st, nms_w); break;
     }
     return hipGetLastError() == hipSuccess ? LDPC_OK : LDPC_EHIP;
 }
@@ -1386,6 +1916,85 @@ static ldpc_status conv_checks(const ldpc_graph* g, const float* llr, int32_t ga
     if ((int64_t)gamma * g->n > ((int64_t)1 << 40)) return LDPC_EUNSUPPORTED;
     if ((reinterpret_cast<uintptr_t>(llr) | reinterpret_cast<uintptr_t>(post)) & 3) return LDPC_EINVAL;
     return LDPC_OK;
+}
+
+ldpc_status ldpc_decode(const ldpc_graph* g, const float* llr, int32_t gamma, int32_t max_iters, int32_t early_stop,
+                        float* post, uint8_t* bits, int32_t* iters, uint8_t* converged, void* workspace,
+                        size_t workspace_bytes, void* stream) {
+    return decode_block(g, llr, gamma, max_iters, early_stop, post, bits, iters, converged, workspace, workspace_bytes,
+                        stream, nullptr);
+}
+
+ldpc_status ldpc_nms_decode(const ldpc_graph* g, const float* llr, int32_t gamma, int32_t iters, const float* weights,
+                            int32_t early_stop, float* post, uint8_t* bits, int32_t* iters_out, uint8_t* converged,
+                            void* workspace, size_t workspace_bytes, void* stream) {
+    if (!weights) return LDPC_EINVAL;
+    return decode_block(g, llr, gamma, iters, early_stop, post, bits, iters_out, converged, workspace,
+                        workspace_bytes, stream, weights);
+}
+
+static ldpc_status train_checks(const ldpc_graph* g, int32_t gamma, int32_t iters, int32_t ckpt_every) {
+    if (!g || g->kind != LDPC_GRAPH_QC) return LDPC_EINVAL;
+    if (gamma < 1 || iters < 1 || iters > LDPC_MAX_ITERS || ckpt_every < 1 || ckpt_every > iters) return LDPC_EINVAL;
+    if ((int64_t)gamma * g->n > ((int64_t)1 << 40)) return LDPC_EUNSUPPORTED;
+    return LDPC_OK;
+}
+
+ldpc_status ldpc_nms_train_workspace_size(const ldpc_graph* g, int32_t gamma, int32_t iters, int32_t ckpt_every,
+                                          size_t* bytes) {
+    ldpc_status chk = train_checks(g, gamma, iters, ckpt_every);
+    if (chk != LDPC_OK) return chk;
+    if (!bytes) return LDPC_EINVAL;
+    *bytes = train_layout(g, choose_tiling(gamma, g), iters, ckpt_every).total;
+    return LDPC_OK;
+}
+
+ldpc_status ldpc_nms_train_forward(const ldpc_graph* g, const float* llr, int32_t gamma, int32_t iters,
+                                   int32_t ckpt_every, const float* weights, float* loss, void* workspace,
+                                   size_t workspace_bytes, void* stream) {
+    ldpc_status chk = train_checks(g, gamma, iters, ckpt_every);
+    if (chk != LDPC_OK) return chk;
+    if (!llr || !weights || !loss) return LDPC_EINVAL;
+    if ((reinterpret_cast<uintptr_t>(llr) | reinterpret_cast<uintptr_t>(weights) |
+         reinterpret_cast<uintptr_t>(loss)) & 3)
+        return LDPC_EINVAL;
+    const Tiling tl = choose_tiling(gamma, g);
+    const TrainLayout lay = train_layout(g, tl, iters, ckpt_every);
+    if (!workspace || workspace_bytes < lay.total) return LDPC_EWORKSPACE;
+    if (reinterpret_cast<uintptr_t>(workspace) & 255) return LDPC_EINVAL;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    TrainRun r = make_train_run(g, gamma, iters, ckpt_every, weights, reinterpret_cast<char*>(workspace), tl, st);
+    (void)hipGetLastError();
+    switch (tl.fpl) {
+        case 4: train_forward<4>(r, llr, loss); break;
+        case 2: train_forward<2>(r, llr, loss); break;
+        default: train_forward<1>(r, llr, loss); break;
+    }
+    return hipGetLastError() == hipSuccess ? LDPC_OK : LDPC_EHIP;
+}
+
+ldpc_status ldpc_nms_train_backward(const ldpc_graph* g, int32_t gamma, int32_t iters, int32_t ckpt_every,
+                                    const float* weights, const float* dloss, float* grad, void* workspace,
+                                    size_t workspace_bytes, void* stream) {
+    ldpc_status chk = train_checks(g, gamma, iters, ckpt_every);
+    if (chk != LDPC_OK) return chk;
+    if (!weights || !dloss || !grad) return LDPC_EINVAL;
+    if ((reinterpret_cast<uintptr_t>(weights) | reinterpret_cast<uintptr_t>(dloss) |
+         reinterpret_cast<uintptr_t>(grad)) & 3)
+        return LDPC_EINVAL;
+    const Tiling tl = choose_tiling(gamma, g);
+    const TrainLayout lay = train_layout(g, tl, iters, ckpt_every);
+    if (!workspace || workspace_bytes < lay.total) return LDPC_EWORKSPACE;
+    if (reinterpret_cast<uintptr_t>(workspace) & 255) return LDPC_EINVAL;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    TrainRun r = make_train_run(g, gamma, iters, ckpt_every, weights, reinterpret_cast<char*>(workspace), tl, st);
+    (void)hipGetLastError();
+    switch (tl.fpl) {
+        case 4: train_backward<4>(r, dloss, grad); break;
+        case 2: train_backward<2>(r, dloss, grad); break;
+        default: train_backward<1>(r, dloss, grad); break;
+    }
+    return hipGetLastError() == hipSuccess ? LDPC_OK : LDPC_EHIP;
 }
 
 ldpc_status ldpc_decode_window(const ldpc_graph* g, const float* llr, int32_t gamma, int32_t W,
@@ -1487,7 +2096,8 @@ const char* ldpc_kernel_class_name(int32_t cls) {
     static const char* names[LDPC_TIMING_CLASSES] = {
         "ingest",          "check_node",        "variable_node",        "syndrome",
         "output",          "frame_status",      "window_ingest",        "window_check_node",
-        "window_variable_node", "pipeline_ingest", "pipeline_check_node", "pipeline_variable_node"};
+        "window_variable_node", "pipeline_ingest", "pipeline_check_node", "pipeline_variable_node",
+        "train_check_node", "train_variable_node", "train_variable_node_backward", "train_check_node_backward"};
     if (cls < 0 || cls >= LDPC_TIMING_CLASSES) return "unknown";
     return names[cls];
 }

@@ -5,7 +5,8 @@ come back to the host; the run stops after a fixed number of frame errors.
 
 The transmitted codeword is all-zero (the decoders treat every codeword
 alike).  Every step runs in the HIP library: `ldpc_awgn_llr` (channel),
-`ldpc_decode` / `ldpc_decode_pipeline` / `ldpc_decode_window` (decoder) and
+`ldpc_decode` / `ldpc_nms_decode` / `ldpc_decode_pipeline` /
+`ldpc_decode_window` (decoder) and
 `ldpc_count_errors` (error counting); this module only loops and keeps time.
 """
 from __future__ import annotations
@@ -24,10 +25,11 @@ def ebn0_to_sigma2(ebn0_db: float, rate: float) -> float:
 
 def simulate(g: ldpc.Graph, ebn0_db: float, *, decoder: str = "block", gamma: int = 1024, iters: int = 30,
              early_stop: bool = False, window: int = 6, seed: int = 1, min_frame_errors: int = 100,
-             max_frames: int = 1 << 20, device=None) -> dict:
+             max_frames: int = 1 << 20, weights=None, device=None) -> dict:
     """Simulate until `min_frame_errors` frame errors or `max_frames` frames.
 
-    decoder: "block" (QC graph, `iters` flooding iterations), "pipeline"
+    decoder: "block" (QC graph, `iters` flooding iterations), "nms" (QC
+    graph, learned min-sum with `weights` [T, J, 2], T iterations), "pipeline"
     (convolutional graph, `iters` processors) or "window" (convolutional
     graph, window `window`, `iters` iterations per window).  A frame is one
     codeword of the block code, or one stream of the convolutional chain.
@@ -46,7 +48,11 @@ def simulate(g: ldpc.Graph, ebn0_db: float, *, decoder: str = "block", gamma: in
     per_frame = torch.empty((gamma,), dtype=torch.int32, device=dev)
     totals = torch.zeros((2,), dtype=torch.int64, device=dev)
     iter_sum = torch.zeros((), dtype=torch.int64, device=dev)
-    if decoder == "block":
+    if decoder == "nms":
+        if weights is None:
+            raise ValueError("the learned decoder needs weights")
+        iters = int(weights.shape[0])
+    if decoder in ("block", "nms"):
         ws = ldpc.workspace(g, gamma, iters, 0, dev)
     elif decoder == "pipeline":
         ws = ldpc.workspace(g, gamma, iters, 0, dev)
@@ -61,6 +67,9 @@ def simulate(g: ldpc.Graph, ebn0_db: float, *, decoder: str = "block", gamma: in
         ldpc.awgn_llr(n, gamma, sigma2, seed, frames, out=llr)
         if decoder == "block":
             ldpc.decode(g, llr, iters, early_stop, out=(post, bits, it, conv), ws=ws)
+            iter_sum += it.sum()
+        elif decoder == "nms":
+            ldpc.nms_decode(g, llr, weights, early_stop, out=(post, bits, it, conv), ws=ws)
             iter_sum += it.sum()
         elif decoder == "pipeline":
             ldpc.decode_pipeline(g, llr, iters, out=(post, bits), ws=ws)
@@ -78,9 +87,9 @@ def simulate(g: ldpc.Graph, ebn0_db: float, *, decoder: str = "block", gamma: in
                ber=bit_err / (frames * n), seconds=seconds, ms_per_frame=seconds * 1e3 / frames,
                coded_mbps=frames * n / seconds / 1e6, ebn0_db=ebn0_db, sigma2=sigma2, n=n, gamma=gamma,
                decoder=decoder, iters=iters)
-    if decoder == "block":
+    if decoder in ("block", "nms"):
         out["avg_iters"] = int(iter_sum.item()) / frames
-    if decoder != "block":
+    else:
         out["ms_per_code_frame"] = seconds * 1e3 / (frames * info["positions"])
     return out
 

@@ -29,7 +29,7 @@ _vp, _i32, _i64, _sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c
 
 OK, EINVAL, EWORKSPACE, EHIP, EUNSUPPORTED, ENOMEM = 0, -1, -2, -3, -4, -5
 GRAPH_QC, GRAPH_CONV = 0, 1
-TIMING_CLASSES = 12
+TIMING_CLASSES = 16
 MAX_ITERS = 100000
 
 
@@ -55,6 +55,10 @@ _get_info = _sig("ldpc_graph_get_info", _i32, [_vp, ctypes.POINTER(GraphInfo)])
 _destroy = _sig("ldpc_graph_destroy", None, [_vp])
 _ws_size = _sig("ldpc_workspace_size", _i32, [_vp, _i32, _i32, _i32, ctypes.POINTER(_sz)])
 _decode = _sig("ldpc_decode", _i32, [_vp, _vp, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _sz, _vp])
+_nms_decode = _sig("ldpc_nms_decode", _i32, [_vp, _vp, _i32, _i32, _vp, _i32, _vp, _vp, _vp, _vp, _vp, _sz, _vp])
+_nms_ws_size = _sig("ldpc_nms_train_workspace_size", _i32, [_vp, _i32, _i32, _i32, ctypes.POINTER(_sz)])
+_nms_forward = _sig("ldpc_nms_train_forward", _i32, [_vp, _vp, _i32, _i32, _i32, _vp, _vp, _vp, _sz, _vp])
+_nms_backward = _sig("ldpc_nms_train_backward", _i32, [_vp, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _sz, _vp])
 _decode_window = _sig("ldpc_decode_window", _i32, [_vp, _vp, _i32, _i32, _i32, _vp, _vp, _vp, _sz, _vp])
 _decode_pipeline = _sig("ldpc_decode_pipeline", _i32, [_vp, _vp, _i32, _i32, _vp, _vp, _vp, _sz, _vp])
 _awgn_llr = _sig("ldpc_awgn_llr", _i32, [_i64, _i32, ctypes.c_double, ctypes.c_uint64, _i64, _vp, _vp])
@@ -66,7 +70,9 @@ _class_name = _sig("ldpc_kernel_class_name", ctypes.c_char_p, [_i32])
 
 EXPORTED = ["ldpc_graph_create_qc", "ldpc_graph_create_ldpccc_from_qc", "ldpc_graph_create_ldpccc_sf",
             "ldpc_graph_get_info", "ldpc_graph_destroy", "ldpc_workspace_size", "ldpc_decode",
-            "ldpc_decode_window", "ldpc_decode_pipeline", "ldpc_awgn_llr", "ldpc_count_errors", "ldpc_status_str", "ldpc_timing_enable", "ldpc_timing_read",
+            "ldpc_nms_decode", "ldpc_nms_train_workspace_size", "ldpc_nms_train_forward",
+            "ldpc_nms_train_backward", "ldpc_decode_window", "ldpc_decode_pipeline", "ldpc_awgn_llr",
+            "ldpc_count_errors", "ldpc_status_str", "ldpc_timing_enable", "ldpc_timing_read",
             "ldpc_kernel_class_name"]
 
 
@@ -200,6 +206,78 @@ def decode(g: Graph, llr, max_iters: int, early_stop: bool = False, out=None, ws
                    bits.data_ptr(), iters.data_ptr(), conv.data_ptr(), ws.data_ptr(), ws.numel(),
                    _stream_handle(stream)), "ldpc_decode")
     return post, bits, iters, conv
+
+
+def _decode_outputs(llr, gamma, n, out):
+    dev = llr.device
+    if out is None:
+        out = (torch.empty((gamma, n), dtype=torch.float32, device=dev),
+               torch.empty((gamma, n), dtype=torch.uint8, device=dev),
+               torch.empty((gamma,), dtype=torch.int32, device=dev),
+               torch.empty((gamma,), dtype=torch.uint8, device=dev))
+    post, bits, iters, conv = out
+    _need(post, torch.float32, (gamma, n), "post")
+    _need(bits, torch.uint8, (gamma, n), "bits")
+    _need(iters, torch.int32, (gamma,), "iters")
+    _need(conv, torch.uint8, (gamma,), "converged")
+    return out
+
+
+def nms_decode(g: Graph, llr, weights, early_stop: bool = False, out=None, ws=None, stream=None):
+    """Learned min-sum decoding of llr [gamma, n] with weights float32
+    [iters, J, 2] (scale, offset) on the device; iters = weights.shape[0].
+    Returns (post, bits, iters, converged)."""
+    if llr.dim() != 2:
+        raise ValueError("llr must be [gamma, n]")
+    gamma, n = llr.shape
+    _need(llr, torch.float32, (gamma, g.n), "llr")
+    T = int(weights.shape[0]) if weights.dim() == 3 else -1
+    _need(weights, torch.float32, (T, g.info["J"], 2), "weights")
+    post, bits, iters, conv = _decode_outputs(llr, gamma, n, out)
+    if ws is None:
+        ws = workspace(g, gamma, T, 0, llr.device)
+    _check(_nms_decode(g.handle, llr.data_ptr(), gamma, T, weights.data_ptr(), int(bool(early_stop)),
+                       post.data_ptr(), bits.data_ptr(), iters.data_ptr(), conv.data_ptr(), ws.data_ptr(),
+                       ws.numel(), _stream_handle(stream)), "ldpc_nms_decode")
+    return post, bits, iters, conv
+
+
+def nms_train_workspace(g: Graph, gamma: int, iters: int, ckpt_every: int, device=None):
+    out = _sz()
+    _check(_nms_ws_size(g.handle, int(gamma), int(iters), int(ckpt_every), ctypes.byref(out)),
+           "ldpc_nms_train_workspace_size")
+    return torch.empty(max(int(out.value), 1), dtype=torch.uint8, device=device or "cuda")
+
+
+def nms_train_forward(g: Graph, llr, weights, ckpt_every: int, ws, loss=None, stream=None):
+    """Per-iteration losses float32 [iters] of the learned min-sum decoder on
+    llr [gamma, n] (all-zero codeword); keeps checkpoints in `ws` for
+    nms_train_backward."""
+    gamma, n = llr.shape
+    _need(llr, torch.float32, (gamma, g.n), "llr")
+    T = int(weights.shape[0]) if weights.dim() == 3 else -1
+    _need(weights, torch.float32, (T, g.info["J"], 2), "weights")
+    if loss is None:
+        loss = torch.empty((T,), dtype=torch.float32, device=llr.device)
+    _need(loss, torch.float32, (T,), "loss")
+    _check(_nms_forward(g.handle, llr.data_ptr(), gamma, T, int(ckpt_every), weights.data_ptr(), loss.data_ptr(),
+                        ws.data_ptr(), ws.numel(), _stream_handle(stream)), "ldpc_nms_train_forward")
+    return loss
+
+
+def nms_train_backward(g: Graph, gamma: int, weights, ckpt_every: int, dloss, ws, grad=None, stream=None):
+    """Gradient float32 [iters, J, 2] of sum_t dloss[t] loss[t] with respect to
+    the weights, after nms_train_forward on the same workspace."""
+    T = int(weights.shape[0]) if weights.dim() == 3 else -1
+    _need(weights, torch.float32, (T, g.info["J"], 2), "weights")
+    _need(dloss, torch.float32, (T,), "dloss")
+    if grad is None:
+        grad = torch.empty_like(weights)
+    _need(grad, torch.float32, tuple(weights.shape), "grad")
+    _check(_nms_backward(g.handle, int(gamma), T, int(ckpt_every), weights.data_ptr(), dloss.data_ptr(),
+                         grad.data_ptr(), ws.data_ptr(), ws.numel(), _stream_handle(stream)),
+           "ldpc_nms_train_backward")
+    return grad
 
 
 def decode_window(g: Graph, llr, W: int, iters_per_window: int, out=None, ws=None, stream=None):

@@ -204,3 +204,48 @@ def test_simulation_helpers_validate_before_launching():
     assert ldpc._count_errors(FAKE, 4, 100, None, None, None) == ldpc.EINVAL
     assert ldpc._count_errors(FAKE, 0, 100, FAKE, None, None) == ldpc.EINVAL
     assert ldpc._count_errors(FAKE, 4, 100, None, FAKE + 4, None) == ldpc.EINVAL
+
+
+def test_learned_decoder_validates_before_launching():
+    qc = ldpc.Graph.qc(synth.draw_qc_shifts(3, 6, 64, 1), 64)
+    cc = ldpc.Graph.ldpccc_from_qc(synth.draw_qc_shifts(3, 6, 32, 2), 32, 16)
+    ws = qc.workspace_size(64, 12)
+    d = ldpc._nms_decode
+    assert d(qc.handle, FAKE, 64, 12, None, 0, FAKE, FAKE, FAKE, FAKE, FAKE, ws, None) == ldpc.EINVAL
+    assert d(cc.handle, FAKE, 64, 12, FAKE, 0, FAKE, FAKE, FAKE, FAKE, FAKE, ws, None) == ldpc.EINVAL
+    assert d(qc.handle, FAKE, 64, 0, FAKE, 0, FAKE, FAKE, FAKE, FAKE, FAKE, ws, None) == ldpc.EINVAL
+    assert d(qc.handle, FAKE, 64, 12, FAKE, 0, FAKE, FAKE, FAKE, FAKE, FAKE, ws - 1, None) == ldpc.EWORKSPACE
+
+
+def test_training_workspace_and_validation():
+    qc = ldpc.Graph.qc(synth.draw_qc_shifts(3, 6, 64, 1), 64)
+    cc = ldpc.Graph.ldpccc_from_qc(synth.draw_qc_shifts(3, 6, 32, 2), 32, 16)
+    out = ctypes.c_size_t()
+    size = ldpc._nms_ws_size
+    assert size(qc.handle, 1024, 12, 4, ctypes.byref(out)) == ldpc.OK
+    with_ckpt = out.value
+    # checkpoints every 4 of 12 iterations keep 2 checkpoints + 4 + 3 segment
+    # arrays + 2 gradient arrays; without checkpoints (every 12): 12 + 11 + 2
+    assert size(qc.handle, 1024, 12, 12, ctypes.byref(out)) == ldpc.OK
+    arr = 1024 * qc.info["E"] * 4
+    assert out.value - with_ckpt == (25 - 11) * arr
+    assert size(cc.handle, 1024, 12, 4, ctypes.byref(out)) == ldpc.EINVAL
+    assert size(qc.handle, 0, 12, 4, ctypes.byref(out)) == ldpc.EINVAL
+    assert size(qc.handle, 64, 12, 0, ctypes.byref(out)) == ldpc.EINVAL
+    assert size(qc.handle, 64, 12, 13, ctypes.byref(out)) == ldpc.EINVAL
+    assert size(qc.handle, 64, 12, 4, None) == ldpc.EINVAL
+    assert size(qc.handle, 64, 12, 4, ctypes.byref(out)) == ldpc.OK
+    ws = out.value
+    f, b = ldpc._nms_forward, ldpc._nms_backward
+    assert f(qc.handle, None, 64, 12, 4, FAKE, FAKE, FAKE, ws, None) == ldpc.EINVAL
+    assert f(qc.handle, FAKE, 64, 12, 4, None, FAKE, FAKE, ws, None) == ldpc.EINVAL
+    assert f(qc.handle, FAKE, 64, 12, 4, FAKE, None, FAKE, ws, None) == ldpc.EINVAL
+    assert f(qc.handle, FAKE, 64, 12, 4, FAKE, FAKE, FAKE, ws - 1, None) == ldpc.EWORKSPACE
+    assert f(qc.handle, FAKE, 64, 12, 4, FAKE, FAKE, FAKE + 4, ws, None) == ldpc.EINVAL
+    assert f(qc.handle, FAKE, 64, 12, 4, FAKE + 2, FAKE, FAKE, ws, None) == ldpc.EINVAL
+    assert b(qc.handle, 64, 12, 4, None, FAKE, FAKE, FAKE, ws, None) == ldpc.EINVAL
+    assert b(qc.handle, 64, 12, 4, FAKE, None, FAKE, FAKE, ws, None) == ldpc.EINVAL
+    assert b(qc.handle, 64, 12, 4, FAKE, FAKE, None, FAKE, ws, None) == ldpc.EINVAL
+    assert b(qc.handle, 64, 12, 4, FAKE, FAKE, FAKE, FAKE, ws - 1, None) == ldpc.EWORKSPACE
+    assert b(cc.handle, 64, 12, 4, FAKE, FAKE, FAKE, FAKE, ws, None) == ldpc.EINVAL
+    assert b(qc.handle, 64, 12, 0, FAKE, FAKE, FAKE, FAKE, ws, None) == ldpc.EINVAL
