@@ -269,6 +269,88 @@ def paper_tables(args):
               f"{r['speedupn']:.0f} | {r['coded_mbps']:.0f} |")
 
 
+def train_algorithmic_bytes(n: int, E: int, gamma: int, T: int):
+    """Average bytes per launch of the training kernels with their state in
+    HBM (per frame): check node 8 E (read beta or gather mu, write alpha);
+    variable node 8 E + 4 n when it writes beta, 4 E + 4 n when it does not
+    (the last iteration, and the end of a recomputed segment); variable-node
+    backward 12 E + 4 n (alpha, dbeta, mu in; dalpha out), 8 E + 4 n at
+    iteration T (no dbeta); check-node backward 12 E (beta, dalpha in; dbeta
+    out), 8 E at iteration 1 (gathers mu, writes no dbeta)."""
+    return {"train_variable_node_backward": ((T - 1) * (12 * E + 4 * n) + 8 * E + 4 * n) * gamma / T,
+            "train_check_node_backward": ((T - 1) * 12 * E + 8 * E) * gamma / T,
+            "train_check_node": 8 * E * gamma}
+
+
+def bench_train(args):
+    """Training throughput of the learned min-sum decoder on the paper-scale
+    code: one step = forward (T = 12 iterations, checkpoints every 4), the
+    hand-written backward, and an Adam update, on 1024 resident frames."""
+    import torch
+
+    import synth
+    from paper_1204_0334_amd import fer, ldpc, nnms
+    spec = synth.WORKLOADS["qc36_p3060"]
+    g = ldpc.Graph.qc(synth.draw_qc_shifts(3, 6, spec["p"], spec["shift_seed"]), spec["p"])
+    n, E, J = g.info["n"], g.info["E"], g.info["J"]
+    gamma, T, k = args.gamma, 12, 4
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    llr = ldpc.awgn_llr(n, gamma, fer.ebn0_to_sigma2(1.75, 0.5), 11, 0, device=dev)
+    W = nnms.initial_weights(T, J, 0.8, 0.0, device=dev).requires_grad_(True)
+    opt = torch.optim.Adam([W], lr=0.01)
+    ws = ldpc.nms_train_workspace(g, gamma, T, k, dev)
+
+    def step():
+        per = nnms.iteration_losses(W, g, llr, k, ws)
+        loss = per.mean()
+        opt.zero_grad(set_to_none=True)
+        loss.backward()
+        opt.step()
+        with torch.no_grad():
+            W.clamp_(min=0.0)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(args.steps):
+        step()
+    stop.record()
+    torch.cuda.synchronize()
+    ms_per_step = start.elapsed_time(stop) / args.steps
+    ldpc.timing_read()
+    ldpc.timing_enable(True)
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    ldpc.timing_enable(False)
+    per_kernel = ldpc.timing_read()
+    algo = train_algorithmic_bytes(n, E, gamma, T)
+    dom = max(algo, key=lambda c: per_kernel[c][1])
+    launches, ms = per_kernel[dom]
+    avg_s = ms / launches * 1e-3
+    achieved = algo[dom] / avg_s / 1e9
+    line = {
+        "metric": "learned min-sum training frames/s (forward + backward + Adam)",
+        "value": round(gamma / (ms_per_step * 1e-3), 1), "unit": "frames/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"learned normalized/offset min-sum on the (3,6)-regular QC-LDPC code p=3060 "
+                               f"(n={n}, E={E}); {gamma} frames at 1.75 dB; T={T} unrolled iterations, "
+                               f"checkpoints every {k}; BCE on every iteration's posterior",
+                   "n": n, "gamma": gamma, "T": T, "ckpt_every": k},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
+                     "avg_launch_us": round(avg_s * 1e6, 2), "algorithmic_bytes_per_launch": round(algo[dom])},
+        "cpu_baseline": None,
+        "kernels": {c: {"launches": v[0], "avg_us": round(v[1] / v[0] * 1e3, 2)} for c, v in per_kernel.items()
+                    if v[0]},
+    }
+    print(json.dumps(line), flush=True)
+
+
 def learned_vs_plain(g, points, *, train_frames: int, eval_frames: int, T: int = 12, ckpt_every: int = 4,
                      extra: bool = False, log=None):
     """Train the learned min-sum decoder (T iterations, scale and offset per
@@ -365,9 +447,11 @@ def main():
     ap.add_argument("--iters", type=int, default=20)
     ap.add_argument("--cpu-sample", type=int, default=96, help="frames decoded by the FP64 reference")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--workload", default="qc36_p3060", choices=["qc36_p3060", "cc36_p512", "cc36_p512_pipeline"],
+    ap.add_argument("--workload", default="qc36_p3060",
+                    choices=["qc36_p3060", "cc36_p512", "cc36_p512_pipeline", "nnms_train_p3060"],
                     help="qc36_p3060: the block-code benchmark; cc36_p512: the convolutional-code window "
-                         "decoder; cc36_p512_pipeline: the pipelined convolutional-code decoder")
+                         "decoder; cc36_p512_pipeline: the pipelined convolutional-code decoder; "
+                         "nnms_train_p3060: training steps of the learned min-sum decoder")
     ap.add_argument("--paper-tables", action="store_true",
                     help="run the analogue of the paper's Tables III and V instead of the benchmark line")
     ap.add_argument("--max-frames", type=int, default=1 << 19, help="--paper-tables: frame cap per code")
@@ -403,6 +487,9 @@ def main():
         return
     if args.nnms:
         nnms_report(args)
+        return
+    if args.workload == "nnms_train_p3060":
+        bench_train(args)
         return
     if args.workload in ("cc36_p512", "cc36_p512_pipeline"):
         bench_window(args, pipeline=args.workload.endswith("pipeline"))

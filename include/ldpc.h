@@ -305,10 +305,10 @@ const char* ldpc_status_str(ldpc_status s);
  *   8 window variable-node, 9 pipeline ingest, 10 pipeline check-node,
  *   11 pipeline variable-node, 12 training check-node, 13 training
  *   variable-node, 14 training variable-node backward, 15 training
- *   check-node backward (with the gradient reduction).
+ *   check-node backward, 16 training loss and gradient reductions.
  * ldpc_kernel_class_name returns a static name for a class index.
  */
-#define LDPC_TIMING_CLASSES 16
+#define LDPC_TIMING_CLASSES 17
 ldpc_status ldpc_timing_enable(int32_t enable);
 ldpc_status ldpc_timing_read(int64_t* launches, double* total_ms, int32_t capacity);
 const char* ldpc_kernel_class_name(int32_t cls);

@@ -1569,27 +1569,34 @@ static void run_block(const ldpc_graph* g, const float* llr, int gamma, int max_
     }
 }
 
-// Learned min-sum training: workspace holds the packaged channel LLRs, the
-// betas at the checkpoints k, 2k, ... (< T), one segment of recomputed alphas
-// (k) and betas (k - 1), the gradient buffers, and the per-wave partial sums
-// of the loss ([T][tiles n]) and of the gradient ([T][tiles m] pairs).
+// Learned min-sum training.  The T iterations form segments of k
+// (ckpt_every); the last one may be shorter.  The workspace holds the
+// packaged channel LLRs, the betas at the checkpoints k, 2k, ... (< T), the
+// alphas and betas of the last segment (written by the forward pass, so the
+// backward pass starts without recomputing), buffers for recomputing one
+// other segment (k alphas, k - 1 betas), the gradient buffers, and the
+// per-wave partial sums of the loss ([T][tiles n]) and of the gradient
+// ([T][tiles m] pairs).
 struct TrainLayout {
-    int k, nck, seg_b;
-    size_t arr, mu, ckpt, A, B, dA, dB, lpart, gpart, total;
+    int k, nseg, nck, last;
+    size_t arr, mu, ckpt, A, B, Al, Bl, dA, dB, lpart, gpart, total;
 };
 
 static TrainLayout train_layout(const ldpc_graph* g, const Tiling& t, int T, int k) {
     TrainLayout L{};
     L.k = k;
-    L.nck = (T + k - 1) / k - 1;
-    L.seg_b = std::max(k - 1, 1);
+    L.nseg = (T + k - 1) / k;
+    L.nck = L.nseg - 1;
+    L.last = T - L.nck * k;
     L.arr = align256((size_t)t.gpad * g->E * sizeof(float));
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
     L.mu = take((size_t)t.gpad * g->n * sizeof(float));
     L.ckpt = take(L.arr * L.nck);
-    L.A = take(L.arr * k);
-    L.B = take(L.arr * L.seg_b);
+    L.A = take(L.nseg > 1 ? L.arr * k : 0);
+    L.B = take(L.nseg > 1 ? L.arr * (k - 1) : 0);
+    L.Al = take(L.arr * L.last);
+    L.Bl = take(L.arr * (L.last - 1));
     L.dA = take(L.arr);
     L.dB = take(L.arr);
     L.lpart = take((size_t)T * t.tiles * g->n * sizeof(float));
@@ -1660,16 +1667,23 @@ static void train_forward(TrainRun& r, const float* llr, float* loss) {
                                                    reinterpret_cast<float*>(r.ws + r.L.mu),
                                                    (int64_t)r.g->n * r.tl.gt, nullptr, 0);
     }
+    const int cl = r.L.nck * r.L.k;     // the last segment holds iterations cl+1 .. T
     const float* src = nullptr;
     for (int t = 1; t <= r.T; ++t) {
-        float* A = r.arr(r.L.A, 0);
-        train_cn<FPL>(r, t, src, A);
+        float* A;
         float* dst = nullptr;
-        if (t < r.T) dst = (t % r.L.k == 0) ? r.ckpt(t) : r.arr(r.L.B, 0);
+        if (t > cl) {
+            A = r.arr(r.L.Al, t - cl - 1);
+            if (t < r.T) dst = r.arr(r.L.Bl, t - cl - 1);
+        } else {
+            A = r.arr(r.L.A, 0);
+            dst = (t % r.L.k == 0) ? r.ckpt(t) : r.arr(r.L.B, 0);
+        }
+        train_cn<FPL>(r, t, src, A);
         train_vn<FPL>(r, t, A, dst, true);
         src = dst;
     }
-    timing::Scope ts(13, r.st);
+    timing::Scope ts(16, r.st);
     nms_loss_reduce_kernel<<<r.T, 256, 0, r.st>>>(reinterpret_cast<const float*>(r.ws + r.L.lpart),
                                                   (int64_t)r.D.n * r.tl.tiles, loss);
 }
@@ -1684,29 +1698,35 @@ static void train_backward(TrainRun& r, const float* dloss, float* grad) {
     const unsigned cn_grid = grid_for_waves((int64_t)D.m * r.tl.tiles);
     const unsigned vn_grid = grid_for_waves((int64_t)D.n * r.tl.tiles);
     const int dcc = dc_class(D.dc_max), dvc = dv_class(D.dv_max);
-    for (int c = (r.T - 1) / k * k; c >= 0; c -= k) {
+    const int cl = r.L.nck * k;
+    for (int c = cl; c >= 0; c -= k) {
         const int e = std::min(c + k, r.T);
-        // recompute alphas c+1..e and betas c+1..e-1 from the checkpoint at c
-        const float* src = r.ckpt(c);
-        for (int t = c + 1; t <= e; ++t) {
-            float* A = r.arr(r.L.A, t - c - 1);
-            train_cn<FPL>(r, t, src, A);
-            float* dst = t < e ? r.arr(r.L.B, t - c - 1) : nullptr;
-            train_vn<FPL>(r, t, A, dst, false);
-            src = dst;
+        // the last segment's alphas and betas are the forward pass's; any other
+        // segment's are recomputed from its checkpoint (alphas c+1..e, betas
+        // c+1..e-1)
+        const size_t Abuf = c == cl ? r.L.Al : r.L.A, Bbuf = c == cl ? r.L.Bl : r.L.B;
+        if (c != cl) {
+            const float* src = r.ckpt(c);
+            for (int t = c + 1; t <= e; ++t) {
+                float* A = r.arr(Abuf, t - c - 1);
+                train_cn<FPL>(r, t, src, A);
+                float* dst = t < e ? r.arr(Bbuf, t - c - 1) : nullptr;
+                train_vn<FPL>(r, t, A, dst, false);
+                src = dst;
+            }
         }
         for (int t = e; t > c; --t) {
             r.P.iter = t;
             {
                 timing::Scope ts(14, r.st);
-                const float* A = r.arr(r.L.A, t - c - 1);
+                const float* A = r.arr(Abuf, t - c - 1);
                 const float* dBin = t == r.T ? nullptr : dB;
                 LDPC_DV_SWITCH(dvc, (nms_vn_backward_kernel<DV, FPL><<<vn_grid, kBlock, 0, r.st>>>(
                                         D, r.P, A, dBin, dA, dloss, r.inv_count)));
             }
             {
                 timing::Scope ts(15, r.st);
-                const float* bsrc = t == c + 1 ? r.ckpt(c) : r.arr(r.L.B, t - c - 2);
+                const float* bsrc = t == c + 1 ? r.ckpt(c) : r.arr(Bbuf, t - c - 2);
                 float* dBout = t == 1 ? nullptr : dB;
                 float2* part = gpart + (size_t)(t - 1) * r.tl.tiles * D.m;
                 LDPC_DC_SWITCH(dcc, if constexpr (DC <= MaxDC<FPL>::value) {
@@ -1715,7 +1735,7 @@ static void train_backward(TrainRun& r, const float* dloss, float* grad) {
             }
         }
     }
-    timing::Scope ts(15, r.st);
+    timing::Scope ts(16, r.st);
     nms_grad_reduce_kernel<<<dim3(D.J, r.T), 256, 0, r.st>>>(D, gpart, r.tl.tiles, grad);
 }
 
@@ -2097,7 +2117,8 @@ const char* ldpc_kernel_class_name(int32_t cls) {
         "ingest",          "check_node",        "variable_node",        "syndrome",
         "output",          "frame_status",      "window_ingest",        "window_check_node",
         "window_variable_node", "pipeline_ingest", "pipeline_check_node", "pipeline_variable_node",
-        "train_check_node", "train_variable_node", "train_variable_node_backward", "train_check_node_backward"};
+        "train_check_node", "train_variable_node", "train_variable_node_backward", "train_check_node_backward",
+        "train_reduce"};
     if (cls < 0 || cls >= LDPC_TIMING_CLASSES) return "unknown";
     return names[cls];
 }

@@ -224,11 +224,12 @@ def test_training_workspace_and_validation():
     size = ldpc._nms_ws_size
     assert size(qc.handle, 1024, 12, 4, ctypes.byref(out)) == ldpc.OK
     with_ckpt = out.value
-    # checkpoints every 4 of 12 iterations keep 2 checkpoints + 4 + 3 segment
-    # arrays + 2 gradient arrays; without checkpoints (every 12): 12 + 11 + 2
+    # checkpoints every 4 of 12 iterations keep 2 checkpoints, the last
+    # segment (4 + 3 arrays), one recomputed segment (4 + 3) and 2 gradient
+    # arrays; without checkpoints (every 12): 12 + 11 + 2
     assert size(qc.handle, 1024, 12, 12, ctypes.byref(out)) == ldpc.OK
     arr = 1024 * qc.info["E"] * 4
-    assert out.value - with_ckpt == (25 - 11) * arr
+    assert out.value - with_ckpt == (25 - 18) * arr
     assert size(cc.handle, 1024, 12, 4, ctypes.byref(out)) == ldpc.EINVAL
     assert size(qc.handle, 0, 12, 4, ctypes.byref(out)) == ldpc.EINVAL
     assert size(qc.handle, 64, 12, 0, ctypes.byref(out)) == ldpc.EINVAL
