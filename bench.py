@@ -29,8 +29,8 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 METRIC = "coded Mbit/s at 20 BP iters (n=18360, Γ=1024) + %HBM peak; FER learned vs plain"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_qc36_p3060.json")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_1204_0334_amd", "csrc", "decode.hip"),
-                  os.path.join(ROOT, "paper_1204_0334_amd", "csrc", "internal.h")]
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1204_0334_amd", "csrc", f)
+                  for f in ("decode.hip", "device.h", "internal.h")]
 
 
 def kernel_source_hash() -> str:
@@ -49,11 +49,11 @@ def algorithmic_bytes(n: int, E: int, gamma: int):
     return {"check_node": 8 * E * gamma, "variable_node": (8 * E + 4 * n) * gamma}
 
 
-def measured_traffic(kernel: str):
+def measured_traffic(kernel: str, path: str = TRAFFIC_FILE):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
     was taken on the current kernel sources."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(path) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
@@ -185,7 +185,9 @@ def bench_window(args, pipeline: bool = False):
                    "window": None if pipeline else W, "iters_per_window": None if pipeline else K,
                    "processors": I if pipeline else None, "bit_error_rate": ber},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic(dom, os.path.join(ROOT, "profiles", "traffic_nnms_train_p3060.json")),
+                     "kernel": dom,
                      "avg_launch_us": round(avg_s * 1e6, 2), "algorithmic_bytes_per_launch": round(algo[dom]),
                      "note": "fraction of HBM peak; the window ring (~67 MB) is cache-resident"},
         "cpu_baseline": None,
@@ -342,7 +344,9 @@ def bench_train(args):
                                f"checkpoints every {k}; BCE on every iteration's posterior",
                    "n": n, "gamma": gamma, "T": T, "ckpt_every": k},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic(dom, os.path.join(ROOT, "profiles", "traffic_nnms_train_p3060.json")),
+                     "kernel": dom,
                      "avg_launch_us": round(avg_s * 1e6, 2), "algorithmic_bytes_per_launch": round(algo[dom])},
         "cpu_baseline": None,
         "kernels": {c: {"launches": v[0], "avg_us": round(v[1] / v[0] * 1e3, 2)} for c, v in per_kernel.items()

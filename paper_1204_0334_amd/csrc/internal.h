@@ -7,6 +7,7 @@
 // no per-edge index table is read from memory.
 #pragma once
 
+#include <hip/hip_runtime_api.h>
 #include <stdint.h>
 #include <vector>
 
@@ -38,6 +39,19 @@ struct ConvDesc {
     int32_t dc_max, dv_max;
     int32_t sf[LDPC_MAX_BLOCKS];              // [T][ms+1][Jb][Lb], -1 = zero block
 };
+
+// Kernel timing (ldpc_timing_enable / ldpc_timing_read): while enabled, a
+// Scope records a pair of events around the launches it brackets.
+namespace timing {
+struct Scope {
+    int idx = -1;
+    hipStream_t st;
+    Scope(int cls, hipStream_t s);
+    ~Scope();
+};
+// turns recording off (for stream capture) and returns the previous state
+bool set_enabled(bool on);
+}  // namespace timing
 
 }  // namespace ldpc
 
