@@ -225,6 +225,78 @@ ldpc_status ldpc_nms_train_backward(const ldpc_graph* g, int32_t gamma, int32_t 
                                     size_t workspace_bytes, void* stream);
 
 /*
+ * Multi-code plan: frames of several QC graphs, each with its own batch size,
+ * decoded together by the flooding sum-product decoder of ldpc_decode
+ * (Algorithm 1, Eq. 3-6; same arithmetic, so each code's outputs equal
+ * ldpc_decode's bit for bit).  One check-node launch and one variable-node
+ * launch per iteration cover all codes; the whole decode can be captured
+ * once into a HIP graph and replayed.
+ *
+ * Layout of a code (frames per tile and rows per wavefront):
+ *   LDPC_LAYOUT_G8, _G16, _G32: tiles of 8, 16 or 32 frames, a wavefront
+ *     working on 8, 4 or 2 consecutive rows (variables) at once;
+ *   LDPC_LAYOUT_G64: tiles of 64 frames, one row per wavefront;
+ *   LDPC_LAYOUT_G64F4: tiles of 256 frames, 4 frames per lane (row weight
+ *     <= 6 and column weight <= 8 only).
+ * Graphs in a plan have row weight <= 24 (EUNSUPPORTED otherwise): one
+ * kernel serves all codes and carries the registers of its heaviest case.
+ * The default is the smallest tile >= gamma (G64F4 for large batches when
+ * allowed); ldpc_plan_autotune times every candidate per code and keeps the
+ * fastest; ldpc_plan_set_layout sets one (-1 = the default).
+ *
+ * ldpc_plan_create: graphs (host array of ncodes QC graphs, which must
+ * outlive the plan), gammas (host int32 [ncodes], >= 1), 1 <= ncodes <=
+ * LDPC_PLAN_MAX_CODES, max_iters, early_stop as for ldpc_decode.
+ * ldpc_plan_workspace_size: bytes for any choice of layouts; the workspace
+ * (device, 256-byte aligned) starts with the plan's table of per-code
+ * descriptors, written by the first call that uses new buffers or layouts
+ * (that call synchronises `stream`).
+ *
+ * ldpc_plan_decode: per code c (host arrays of device pointers, ncodes
+ * entries): llr[c] float [gamma_c][n_c], post[c] float [gamma_c][n_c],
+ * bits[c] uint8 [gamma_c][n_c], iters[c] int32 [gamma_c] and converged[c]
+ * uint8 [gamma_c] (the arrays `iters` and `converged`, or their entries, may
+ * be NULL).  Outputs as for ldpc_decode.  Asynchronous on `stream`.
+ *
+ * ldpc_plan_capture: records the same decode for these buffers into a HIP
+ * graph (on a stream of the plan's own; nothing runs); ldpc_plan_replay
+ * launches it on `stream`.  Replay fails with EINVAL once another call has
+ * bound other buffers or layouts (capture again).  The workspace must not be
+ * used by anything else between capture and replay.
+ *
+ * ldpc_plan_autotune: one pass of coordinate descent over the codes: each
+ * code in turn tries every other allowed layout (tiles no larger than the
+ * next power of two above its batch) while the others stay fixed; each
+ * candidate is timed over `trials` whole decodes of the plan (after one
+ * warm-up) on the given buffers (outputs are overwritten); the fastest is
+ * kept.  Writes the final time per decode in ms to *best_ms (host, may be
+ * NULL).  Synchronises `stream`.
+ *
+ * Errors: EINVAL (NULL pointers, bad counts, convolutional graphs, layout not
+ * allowed, misaligned buffers), EWORKSPACE, EUNSUPPORTED, EHIP, ENOMEM.
+ */
+typedef struct ldpc_plan ldpc_plan;
+#define LDPC_PLAN_MAX_CODES 16
+enum { LDPC_LAYOUT_G8 = 0, LDPC_LAYOUT_G16 = 1, LDPC_LAYOUT_G32 = 2, LDPC_LAYOUT_G64 = 3, LDPC_LAYOUT_G64F4 = 4 };
+
+ldpc_status ldpc_plan_create(const ldpc_graph* const* graphs, const int32_t* gammas, int32_t ncodes,
+                             int32_t max_iters, int32_t early_stop, ldpc_plan** out);
+void        ldpc_plan_destroy(ldpc_plan* plan);
+ldpc_status ldpc_plan_workspace_size(const ldpc_plan* plan, size_t* bytes);
+ldpc_status ldpc_plan_set_layout(ldpc_plan* plan, int32_t code, int32_t layout);
+ldpc_status ldpc_plan_get_layout(const ldpc_plan* plan, int32_t code, int32_t* layout);
+ldpc_status ldpc_plan_decode(ldpc_plan* plan, const float* const* llr, float* const* post, uint8_t* const* bits,
+                             int32_t* const* iters, uint8_t* const* converged, void* workspace,
+                             size_t workspace_bytes, void* stream);
+ldpc_status ldpc_plan_capture(ldpc_plan* plan, const float* const* llr, float* const* post, uint8_t* const* bits,
+                              int32_t* const* iters, uint8_t* const* converged, void* workspace,
+                              size_t workspace_bytes, void* stream);
+ldpc_status ldpc_plan_replay(ldpc_plan* plan, void* stream);
+ldpc_status ldpc_plan_autotune(ldpc_plan* plan, const float* const* llr, float* const* post, uint8_t* const* bits,
+                               int32_t* const* iters, uint8_t* const* converged, void* workspace,
+                               size_t workspace_bytes, int32_t trials, void* stream, double* best_ms);
+
+/*
  * Sliding-window decoding of `gamma` independent streams of a terminated
  * convolutional graph (Sec. II-E: checks span at most ms+1 positions).  For
  * target position s = 0..positions-1: the window holds check layers
@@ -305,10 +377,12 @@ const char* ldpc_status_str(ldpc_status s);
  *   8 window variable-node, 9 pipeline ingest, 10 pipeline check-node,
  *   11 pipeline variable-node, 12 training check-node, 13 training
  *   variable-node, 14 training variable-node backward, 15 training
- *   check-node backward, 16 training loss and gradient reductions.
+ *   check-node backward, 16 training loss and gradient reductions,
+ *   17 plan ingest, 18 plan check-node, 19 plan variable-node, 20 plan
+ *   final syndrome, frame status and output.
  * ldpc_kernel_class_name returns a static name for a class index.
  */
-#define LDPC_TIMING_CLASSES 17
+#define LDPC_TIMING_CLASSES 21
 ldpc_status ldpc_timing_enable(int32_t enable);
 ldpc_status ldpc_timing_read(int64_t* launches, double* total_ms, int32_t capacity);
 const char* ldpc_kernel_class_name(int32_t cls);

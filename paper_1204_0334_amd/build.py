@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libldpc_hip.so")
-SOURCES = [os.path.join(HERE, "csrc", "graph.cpp"), os.path.join(HERE, "csrc", "decode.hip")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("graph.cpp", "decode.hip", "plan.hip")]
 ARCH = os.environ.get("LDPC_OFFLOAD_ARCH", "gfx950")
 
 

@@ -1950,7 +1950,7 @@ const char* ldpc_kernel_class_name(int32_t cls) {
         "output",          "frame_status",      "window_ingest",        "window_check_node",
         "window_variable_node", "pipeline_ingest", "pipeline_check_node", "pipeline_variable_node",
         "train_check_node", "train_variable_node", "train_variable_node_backward", "train_check_node_backward",
-        "train_reduce"};
+        "train_reduce", "plan_ingest", "plan_check_node", "plan_variable_node", "plan_finish"};
     if (cls < 0 || cls >= LDPC_TIMING_CLASSES) return "unknown";
     return names[cls];
 }

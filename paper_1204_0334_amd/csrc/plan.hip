@@ -1,0 +1,874 @@
+// Multi-code plan: frames of several QC-LDPC codes, each with its own batch
+// size, decoded together by flooding sum-product (Algorithm 1, Eq. 3-6).
+//
+// One launch per phase covers every code of the plan: the check-node launch
+// of iteration i runs the rows of all codes, the variable-node launch all
+// their variables, so small codes ride along with large ones instead of each
+// paying for its own 2 * I_max launches.  The whole sequence (ingest,
+// 2 * I_max phase launches, final syndrome, frame status, output) can be
+// captured once into a HIP graph and replayed.
+//
+// Lane layouts.  A code's frames are tiled by Gt = G * FPL frames.  A wave
+// holds R = 64 / G rows (or variables) x G frames: lane = r * G + f works on
+// row (variable) r of the wave and frame f of the tile (G = 64: one row per
+// wave, FPL frames per lane as in the single-code decoder).  Message packages
+// stay [tile][package][Gt]; the R rows of a wave are consecutive rows of a
+// circulant block, so their packages are consecutive and the wave's access
+// to an edge slot is one contiguous 64 * FPL * 4-byte run whatever G is.
+// Small batches (Gamma < 64) therefore use G = 8, 16 or 32 instead of
+// padding every tile to 64 frames.  The layout of each code is chosen by
+// the caller or by ldpc_plan_autotune (which times the candidates).
+//
+// Per-code descriptors (the QC description, buffer addresses, tiling and the
+// code's first wave in each launch) live in a table at the start of the
+// caller's workspace; a launch's waves find their code by scanning that
+// table (a handful of entries).  The arithmetic per frame is the single-code
+// decoder's (shared helpers sp_check / sp_variable, same edge order), so a
+// plan returns bit for bit what ldpc_decode returns for each code.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "device.h"
+#include "internal.h"
+
+namespace ldpc {
+
+constexpr int kPlanLayouts = 5;   // G8, G16, G32, G64, G64 with 4 frames per lane
+
+__host__ __device__ constexpr int layout_g(int l) { return l == 0 ? 8 : l == 1 ? 16 : l == 2 ? 32 : 64; }
+__host__ __device__ constexpr int layout_fpl(int l) { return l == 4 ? 4 : 1; }
+
+struct PlanCode {
+    QCDesc D;
+    float* mu;            // [tiles][n][Gt]
+    float* msg;           // [tiles][E][Gt]
+    float* postw;         // [tiles][n][Gt]: posterior of the returned iteration
+    uint64_t* bits;       // [tiles][n][FPL] packed decisions
+    uint64_t* unsat;      // [max_iters+1][tiles][FPL]
+    uint64_t* frozen;     // [max_iters+1][tiles][FPL]
+    const float* llr;     // caller, [gamma][n]
+    float* post;          // caller, [gamma][n]
+    uint8_t* bits_out;    // caller, [gamma][n]
+    int32_t* iters;       // caller, [gamma] or NULL
+    uint8_t* converged;   // caller, [gamma] or NULL
+    int64_t flag_words;   // (max_iters+1) * tiles * FPL
+    int gamma, tiles, layout, Gt, fpl, dcc, dvc;
+    int cn_wpt, vn_wpt;   // waves per tile in the check / variable launches
+    int io_vchunks, io_fchunks;
+    int64_t cn0, vn0;     // first wave of the code in the check / variable launches
+    int64_t syn0, st0;    // first thread in the syndrome / frame-status launches (multiples of 64)
+    int64_t io0;          // first block in the ingest / output launches
+};
+
+struct PlanStep {
+    int iter, last, early, max_iters;
+};
+
+__device__ __forceinline__ int plan_find(const PlanCode* __restrict__ codes, int ncodes, int64_t x,
+                                         int64_t PlanCode::*first) {
+    int c = 0;
+    for (int i = 1; i < ncodes; ++i)
+        if (x >= codes[i].*first) c = i;
+    return c;
+}
+
+// a[i] of a register array by mask blending (a dynamic index would move the
+// array to private memory)
+template <int FPL>
+__device__ __forceinline__ uint64_t plan_pick(const uint64_t (&a)[FPL], int i) {
+    uint64_t r = a[0];
+#pragma unroll
+    for (int f = 1; f < FPL; ++f) {
+        const uint64_t m = 0ull - (uint64_t)(i == f);
+        r = (a[f] & m) | (r & ~m);
+    }
+    return r;
+}
+
+#define PLAN_LAYOUT_SWITCH(LV, ...)                                           \
+    switch (LV) {                                                             \
+        case 0: { constexpr int G = 8, FPL = 1; __VA_ARGS__; } break;         \
+        case 1: { constexpr int G = 16, FPL = 1; __VA_ARGS__; } break;        \
+        case 2: { constexpr int G = 32, FPL = 1; __VA_ARGS__; } break;        \
+        case 3: { constexpr int G = 64, FPL = 1; __VA_ARGS__; } break;        \
+        default: { constexpr int G = 64, FPL = 4; __VA_ARGS__; } break;       \
+    }
+// row-weight classes of a plan (at most 24: one kernel serves every code, and
+// its register budget is that of the heaviest variant it contains)
+#define PLAN_DC_SWITCH(DCV, ...)                                    \
+    switch (DCV) {                                                  \
+        case 4: { constexpr int DC = 4; __VA_ARGS__; } break;       \
+        case 6: { constexpr int DC = 6; __VA_ARGS__; } break;       \
+        case 8: { constexpr int DC = 8; __VA_ARGS__; } break;       \
+        case 12: { constexpr int DC = 12; __VA_ARGS__; } break;     \
+        case 16: { constexpr int DC = 16; __VA_ARGS__; } break;     \
+        default: { constexpr int DC = 24; __VA_ARGS__; } break;     \
+    }
+#define PLAN_DV_SWITCH(DVV, ...)                                    \
+    switch (DVV) {                                                  \
+        case 2: { constexpr int DV = 2; __VA_ARGS__; } break;       \
+        case 3: { constexpr int DV = 3; __VA_ARGS__; } break;       \
+        case 4: { constexpr int DV = 4; __VA_ARGS__; } break;       \
+        case 6: { constexpr int DV = 6; __VA_ARGS__; } break;       \
+        case 8: { constexpr int DV = 8; __VA_ARGS__; } break;       \
+        default: { constexpr int DV = 16; __VA_ARGS__; } break;     \
+    }
+
+// Check-node pass of iteration S.iter for wave lw of code C (in place; the
+// first iteration gathers the channel LLRs).  With early stopping it first
+// skips tiles frozen by iteration iter-2 and ORs the syndrome of iteration
+// iter-1's decisions into unsat[iter-1].
+template <int DCMAX, int G, int FPL>
+__device__ __forceinline__ void plan_cn_body(const PlanCode& C, const PlanStep& S, int64_t lw, int lane) {
+    constexpr int R = 64 / G;
+    constexpr int Gt = G * FPL;
+    const QCDesc& D = C.D;
+    const int tile = (int)(lw / C.cn_wpt);
+    const int rw = (int)(lw - (int64_t)tile * C.cn_wpt);
+    const int r = lane / G, f = lane % G;
+    const int row = rw * R + r;
+    const bool active = row < D.m;
+    const int nvalid = min(C.gamma - tile * Gt, Gt);
+    if (S.early && S.iter >= 3) {
+        const uint64_t* fz = C.frozen + ((size_t)(S.iter - 2) * C.tiles + tile) * FPL;
+        bool all = true;
+#pragma unroll
+        for (int i = 0; i < FPL; ++i) all = all && (fz[i] == ~0ull);
+        if (all) return;
+    }
+    const QCRow Rw(D, active ? row : 0);
+    const int d = active ? Rw.d : 0;
+    if (S.early && S.iter >= 2) {
+        uint64_t par[FPL];
+#pragma unroll
+        for (int i = 0; i < FPL; ++i) par[i] = 0;
+        const uint64_t* bt = C.bits + (size_t)tile * D.n * FPL;
+#pragma unroll
+        for (int k = 0; k < DCMAX; ++k) {
+            if (k >= d) continue;
+            const uint64_t* w = bt + (size_t)Rw.var(D, k) * FPL;
+#pragma unroll
+            for (int i = 0; i < FPL; ++i) par[i] ^= w[i];
+        }
+        uint64_t* un = C.unsat + ((size_t)(S.iter - 1) * C.tiles + tile) * FPL;
+        if constexpr (G == 64) {
+#pragma unroll
+            for (int i = 0; i < FPL; ++i) {
+                const uint64_t bad = par[i] & valid_word<FPL>(nvalid, i);
+                if (bad && lane == i) {
+                    // a stale read can only miss bits: a redundant atomic at worst
+                    if ((__atomic_load_n(un + i, __ATOMIC_RELAXED) & bad) != bad)
+                        atomicOr((unsigned long long*)(un + i), (unsigned long long)bad);
+                }
+            }
+        } else {
+            uint64_t v = par[0] & valid_word<1>(nvalid, 0);
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) v |= __shfl_xor(v, off);
+            if (lane == 0 && v) {
+                if ((__atomic_load_n(un, __ATOMIC_RELAXED) & v) != v)
+                    atomicOr((unsigned long long*)un, (unsigned long long)v);
+            }
+        }
+    }
+    const size_t lane_off = (G == 64) ? (size_t)lane * FPL : (size_t)f;
+    float* mt = C.msg + (size_t)tile * D.E * Gt + lane_off;
+    const float* ut = C.mu + (size_t)tile * D.n * Gt + lane_off;
+    float in[DCMAX][FPL];
+#pragma unroll
+    for (int k = 0; k < DCMAX; ++k) {
+        if (k < d) {
+            const float* s = S.iter == 1 ? ut + (size_t)Rw.var(D, k) * Gt : mt + (size_t)Rw.pkg(D, k) * Gt;
+            load_frames<FPL>(s, in[k]);
+        } else {
+#pragma unroll
+            for (int i = 0; i < FPL; ++i) in[k][i] = 0.0f;
+        }
+    }
+    float out[DCMAX][FPL];
+    sp_check<DCMAX, FPL>(in, d, out);
+#pragma unroll
+    for (int k = 0; k < DCMAX; ++k)
+        if (k < d) store_frames<FPL>(mt + (size_t)Rw.pkg(D, k) * Gt, out[k]);
+}
+
+// Variable-node pass of iteration S.iter for wave lw of code C: betas (not
+// after the last iteration), and with early stopping or at the last
+// iteration the packed decisions and the posterior of the frames still
+// running (frozen frames keep theirs).
+template <int DVMAX, int G, int FPL>
+__device__ __forceinline__ void plan_vn_body(const PlanCode& C, const PlanStep& S, int64_t lw, int lane) {
+    constexpr int R = 64 / G;
+    constexpr int Gt = G * FPL;
+    const QCDesc& D = C.D;
+    const int tile = (int)(lw / C.vn_wpt);
+    const int rw = (int)(lw - (int64_t)tile * C.vn_wpt);
+    const int r = lane / G, f = lane % G;
+    const int var = rw * R + r;
+    const bool active = var < D.n;
+    const int nvalid = min(C.gamma - tile * Gt, Gt);
+    // frames frozen before this iteration (padding frames count as frozen)
+    uint64_t frz[FPL];
+    bool any = false, all = true;
+#pragma unroll
+    for (int i = 0; i < FPL; ++i) {
+        uint64_t z = ~valid_word<FPL>(nvalid, i);
+        if (S.early && S.iter >= 2) {
+            z |= C.frozen[((size_t)(S.iter - 2) * C.tiles + tile) * FPL + i] |
+                 ~C.unsat[((size_t)(S.iter - 1) * C.tiles + tile) * FPL + i];
+        }
+        frz[i] = z;
+        any = any || (z & valid_word<FPL>(nvalid, i)) != 0;
+        all = all && (z == ~0ull);
+    }
+    if (S.early && rw == 0 && lane < FPL)
+        C.frozen[((size_t)(S.iter - 1) * C.tiles + tile) * FPL + lane] = plan_pick<FPL>(frz, lane);
+    if (S.early && all) return;
+    const QCCol Cc(D, active ? var : 0);
+    const int dv = active ? Cc.d : 0;
+    const size_t lane_off = (G == 64) ? (size_t)lane * FPL : (size_t)f;
+    float* mt = C.msg + (size_t)tile * D.E * Gt + lane_off;
+    float mu[FPL];
+    if (active) {
+        load_frames<FPL>(C.mu + ((size_t)tile * D.n + var) * Gt + lane_off, mu);
+    } else {
+#pragma unroll
+        for (int i = 0; i < FPL; ++i) mu[i] = 0.0f;
+    }
+    float a[DVMAX][FPL];
+#pragma unroll
+    for (int k = 0; k < DVMAX; ++k) {
+        if (k < dv) {
+            load_frames<FPL>(mt + (size_t)Cc.pkg(D, k) * Gt, a[k]);
+        } else {
+#pragma unroll
+            for (int i = 0; i < FPL; ++i) a[k][i] = 0.0f;
+        }
+    }
+    float b[DVMAX][FPL], L[FPL];
+    sp_variable<DVMAX, FPL>(mu, a, b, L);
+    if (!S.last) {
+#pragma unroll
+        for (int k = 0; k < DVMAX; ++k)
+            if (k < dv) store_frames<FPL>(mt + (size_t)Cc.pkg(D, k) * Gt, b[k]);
+    }
+    if (S.early || S.last) {
+        uint64_t* bw = C.bits + ((size_t)tile * D.n + var) * FPL;
+        if constexpr (G == 64) {
+            // word i, bit j <-> frame FPL * j + i
+            uint64_t mine = 0;
+#pragma unroll
+            for (int i = 0; i < FPL; ++i) {
+                uint64_t w = __ballot(L[i] < 0.0f);
+                if (any) w = (w & ~frz[i]) | (bw[i] & frz[i]);
+                if (lane == i) mine = w;
+            }
+            if (lane < FPL) bw[lane] = mine;
+        } else {
+            // bits r*G .. r*G+G-1 of the ballot are the G frames of variable r
+            const uint64_t gmask = (1ull << G) - 1ull;
+            uint64_t w = (__ballot(active && L[0] < 0.0f) >> (r * G)) & gmask;
+            if (active && f == 0) {
+                if (any) w = (w & ~frz[0]) | (bw[0] & frz[0]);
+                bw[0] = w;
+            }
+        }
+        if (active) {
+            float* pw = C.postw + ((size_t)tile * D.n + var) * Gt + lane_off;
+#pragma unroll
+            for (int i = 0; i < FPL; ++i) {
+                const int bit = (G == 64) ? lane : f;   // frame lane_off + i: word i, bit `bit`
+                if (!((frz[i] >> bit) & 1ull)) pw[i] = clip30(L[i]);
+            }
+        }
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) plan_cn_kernel(const PlanCode* __restrict__ codes, int ncodes,
+                                                         PlanStep S) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = (int64_t)blockIdx.x * kWavesPerBlock + wave_in_block();
+    const PlanCode& C = codes[plan_find(codes, ncodes, wave, &PlanCode::cn0)];
+    const int64_t lw = wave - C.cn0;
+    if (lw >= (int64_t)C.tiles * C.cn_wpt) return;
+    PLAN_LAYOUT_SWITCH(C.layout, PLAN_DC_SWITCH(C.dcc, if constexpr (FPL == 1 || DC <= 6) {
+        plan_cn_body<DC, G, FPL>(C, S, lw, lane);
+    }));
+}
+
+__global__ void __launch_bounds__(kBlock) plan_vn_kernel(const PlanCode* __restrict__ codes, int ncodes,
+                                                         PlanStep S) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = (int64_t)blockIdx.x * kWavesPerBlock + wave_in_block();
+    const PlanCode& C = codes[plan_find(codes, ncodes, wave, &PlanCode::vn0)];
+    const int64_t lw = wave - C.vn0;
+    if (lw >= (int64_t)C.tiles * C.vn_wpt) return;
+    PLAN_LAYOUT_SWITCH(C.layout, PLAN_DV_SWITCH(C.dvc, if constexpr (FPL == 1 || DV <= 8) {
+        plan_vn_body<DV, G, FPL>(C, S, lw, lane);
+    }));
+}
+
+// Syndrome of the final decisions into unsat[max_iters]: one thread per
+// (code, tile, row); each code's threads start at a multiple of 64, so a
+// wave belongs to one code; its rows may straddle two tiles.
+template <int FPL>
+__device__ __forceinline__ void plan_syndrome_body(const PlanCode& C, const PlanStep& S, int64_t t, int lane) {
+    const QCDesc& D = C.D;
+    const int Gt = C.Gt;
+    const int tile = (int)(t / D.m);
+    const int row = (int)(t - (int64_t)tile * D.m);
+    const bool live = tile < C.tiles;
+    uint64_t par[FPL];
+#pragma unroll
+    for (int i = 0; i < FPL; ++i) par[i] = 0;
+    if (live) {
+        const QCRow Rw(D, row);
+        const uint64_t* bt = C.bits + (size_t)tile * D.n * FPL;
+        for (int k = 0; k < Rw.d; ++k) {
+            const uint64_t* w = bt + (size_t)Rw.var(D, k) * FPL;
+#pragma unroll
+            for (int i = 0; i < FPL; ++i) par[i] ^= w[i];
+        }
+        const int nvalid = min(C.gamma - tile * Gt, Gt);
+#pragma unroll
+        for (int i = 0; i < FPL; ++i) par[i] &= valid_word<FPL>(nvalid, i);
+    }
+    const int tile0 = __shfl(tile, 0);
+    const bool same = tile == tile0;
+#pragma unroll
+    for (int i = 0; i < FPL; ++i) {
+        uint64_t v = same ? par[i] : 0;
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) v |= __shfl_xor(v, off);
+        if (live) {
+            uint64_t* un = C.unsat + ((size_t)S.max_iters * C.tiles + tile) * FPL + i;
+            if (same) {
+                if (lane == 0 && v) atomicOr((unsigned long long*)un, (unsigned long long)v);
+            } else if (par[i]) {
+                atomicOr((unsigned long long*)un, (unsigned long long)par[i]);
+            }
+        }
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) plan_syndrome_kernel(const PlanCode* __restrict__ codes, int ncodes,
+                                                               PlanStep S) {
+    const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t wave0 = (int64_t)blockIdx.x * kBlock + wave_in_block() * 64;
+    const PlanCode& C = codes[plan_find(codes, ncodes, wave0, &PlanCode::syn0)];
+    const int64_t t = gid - C.syn0;
+    if (C.fpl == 4) {
+        plan_syndrome_body<4>(C, S, t, threadIdx.x & 63);
+    } else {
+        plan_syndrome_body<1>(C, S, t, threadIdx.x & 63);
+    }
+}
+
+// Per-frame iteration count and convergence flag from the flag words.
+__global__ void __launch_bounds__(kBlock) plan_status_kernel(const PlanCode* __restrict__ codes, int ncodes,
+                                                             PlanStep S) {
+    const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t wave0 = (int64_t)blockIdx.x * kBlock + wave_in_block() * 64;
+    const PlanCode& C = codes[plan_find(codes, ncodes, wave0, &PlanCode::st0)];
+    const int64_t g = gid - C.st0;
+    if (g >= C.gamma || (!C.iters && !C.converged)) return;
+    const int tile = (int)(g / C.Gt), fl = (int)(g - (int64_t)tile * C.Gt);
+    const int w = fl % C.fpl, bit = fl / C.fpl;
+    int it = S.max_iters, ok = 0;
+    if (S.early) {
+        for (int i = 1; i <= S.max_iters; ++i) {
+            if (!((C.unsat[((size_t)i * C.tiles + tile) * C.fpl + w] >> bit) & 1ull)) {
+                it = i;
+                ok = 1;
+                break;
+            }
+        }
+    } else {
+        ok = !((C.unsat[((size_t)S.max_iters * C.tiles + tile) * C.fpl + w] >> bit) & 1ull);
+    }
+    if (C.iters) C.iters[g] = it;
+    if (C.converged) C.converged[g] = (uint8_t)ok;
+}
+
+// Ingest: llr [gamma][n] -> mu [tile][n][Gt] (padding frames 0), through LDS,
+// 64 variables x 64 frames per block; block 0 of a code clears its flags.
+__global__ void __launch_bounds__(256) plan_ingest_kernel(const PlanCode* __restrict__ codes, int ncodes) {
+    __shared__ float tileS[64][65];
+    const PlanCode& C = codes[plan_find(codes, ncodes, blockIdx.x, &PlanCode::io0)];
+    const int64_t b = blockIdx.x - C.io0;
+    if (b >= (int64_t)C.io_vchunks * C.io_fchunks) return;
+    if (b == 0)
+        for (int64_t i = threadIdx.x; i < 2 * C.flag_words; i += 256) C.unsat[i] = 0ull;
+    const int n = C.D.n, Gt = C.Gt, gpad = C.tiles * C.Gt;
+    const int c0 = (int)(b % C.io_vchunks) * 64, f0 = (int)(b / C.io_vchunks) * 64;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    for (int r = ty; r < 64; r += 4) {
+        const int g = f0 + r, c = c0 + tx;
+        float v = 0.0f;
+        if (g < C.gamma && c < n) v = C.llr[(size_t)g * n + c];
+        tileS[r][tx] = v;
+    }
+    __syncthreads();
+    for (int r = ty; r < 64; r += 4) {
+        const int c = c0 + r, g = f0 + tx;
+        if (c < n && g < gpad) {
+            const int tile = g / Gt, fl = g - tile * Gt;
+            C.mu[((size_t)tile * n + c) * Gt + fl] = tileS[tx][r];
+        }
+    }
+}
+
+// Output: posterior and decisions of every frame from the package layout to
+// the caller's [gamma][n] buffers, through LDS.
+__global__ void __launch_bounds__(256) plan_output_kernel(const PlanCode* __restrict__ codes, int ncodes) {
+    __shared__ float Ps[64][65];
+    __shared__ uint8_t Bs[64][65];
+    const PlanCode& C = codes[plan_find(codes, ncodes, blockIdx.x, &PlanCode::io0)];
+    const int64_t b = blockIdx.x - C.io0;
+    if (b >= (int64_t)C.io_vchunks * C.io_fchunks) return;
+    const int n = C.D.n, Gt = C.Gt, fpl = C.fpl;
+    const int c0 = (int)(b % C.io_vchunks) * 64, f0 = (int)(b / C.io_vchunks) * 64;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    for (int r = ty; r < 64; r += 4) {           // r: variable, tx: frame
+        const int c = c0 + r, g = f0 + tx;
+        if (c < n && g < C.gamma) {
+            const int tile = g / Gt, fl = g - tile * Gt;
+            Ps[r][tx] = C.postw[((size_t)tile * n + c) * Gt + fl];
+            const uint64_t w = C.bits[((size_t)tile * n + c) * fpl + fl % fpl];
+            Bs[r][tx] = (uint8_t)((w >> (fl / fpl)) & 1ull);
+        }
+    }
+    __syncthreads();
+    for (int r = ty; r < 64; r += 4) {           // r: frame, tx: variable
+        const int c = c0 + tx, g = f0 + r;
+        if (c < n && g < C.gamma) {
+            const size_t o = (size_t)g * n + c;
+            C.post[o] = Ps[tx][r];
+            C.bits_out[o] = Bs[tx][r];
+        }
+    }
+}
+
+}  // namespace ldpc
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+
+using namespace ldpc;
+
+namespace {
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+constexpr int kPlanMaxRowWeight = 24;
+
+int plan_dc_class(int d) {
+    for (int c : {4, 6, 8, 12, 16, 24})
+        if (d <= c) return c;
+    return -1;
+}
+int plan_dv_class(int d) {
+    for (int c : {2, 3, 4, 6, 8, 16})
+        if (d <= c) return c;
+    return -1;
+}
+
+bool layout_allowed(const ldpc_graph* g, int l) {
+    if (l < 0 || l >= kPlanLayouts) return false;
+    return layout_fpl(l) == 1 || (g->dc_max <= 6 && g->dv_max <= 8);
+}
+
+struct CodeRegion {
+    int tiles, Gt;
+    int64_t flag_words;
+    size_t mu, msg, postw, bits, flags, total;
+};
+
+CodeRegion code_region(const ldpc_graph* g, int gamma, int layout, int max_iters) {
+    CodeRegion R{};
+    R.Gt = layout_g(layout) * layout_fpl(layout);
+    R.tiles = (gamma + R.Gt - 1) / R.Gt;
+    const size_t gpad = (size_t)R.tiles * R.Gt;
+    R.flag_words = (int64_t)(max_iters + 1) * R.tiles * layout_fpl(layout);
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
+    R.mu = take(gpad * g->n * sizeof(float));
+    R.msg = take(gpad * g->E * sizeof(float));
+    R.postw = take(gpad * g->n * sizeof(float));
+    R.bits = take((size_t)R.tiles * g->n * layout_fpl(layout) * sizeof(uint64_t));
+    R.flags = take(2 * (size_t)R.flag_words * sizeof(uint64_t));
+    R.total = off;
+    return R;
+}
+
+// default layout: the smallest G >= gamma (at least 8); 64 frames per lane
+// group with 4 frames per lane when the row weight allows it and the padding
+// stays under 1/8
+int default_layout(const ldpc_graph* g, int gamma) {
+    if (gamma <= 8) return 0;
+    if (gamma <= 16) return 1;
+    if (gamma <= 32) return 2;
+    if (layout_allowed(g, 4)) {
+        const int base = (gamma + 63) / 64 * 64, pad4 = (gamma + 255) / 256 * 256;
+        if (pad4 * 8 <= base * 9) return 4;
+    }
+    return 3;
+}
+
+}  // namespace
+
+struct ldpc_plan {
+    int ncodes = 0, max_iters = 0, early = 0;
+    std::vector<const ldpc_graph*> graphs;
+    std::vector<int> gammas, layouts;
+    std::vector<size_t> region_off;       // byte offset of each code's region in the workspace
+    size_t table_bytes = 0, ws_bytes = 0;
+    std::vector<PlanCode> table;          // host copy of the device table
+    // launch geometry
+    int64_t cn_waves = 0, vn_waves = 0, syn_threads = 0, st_threads = 0, io_blocks = 0;
+    // what the device table currently describes
+    bool table_valid = false;
+    const void* table_ws = nullptr;
+    uint64_t generation = 1;              // bumped whenever layouts or bound buffers change
+    // graph
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    uint64_t graph_generation = 0;
+};
+
+namespace {
+
+struct PlanBuffers {
+    const float* const* llr;
+    float* const* post;
+    uint8_t* const* bits;
+    int32_t* const* iters;
+    uint8_t* const* converged;
+};
+
+ldpc_status check_buffers(const ldpc_plan* P, const PlanBuffers& B, const void* ws, size_t ws_bytes) {
+    if (!B.llr || !B.post || !B.bits) return LDPC_EINVAL;
+    for (int c = 0; c < P->ncodes; ++c) {
+        if (!B.llr[c] || !B.post[c] || !B.bits[c]) return LDPC_EINVAL;
+        if ((reinterpret_cast<uintptr_t>(B.llr[c]) | reinterpret_cast<uintptr_t>(B.post[c])) & 3) return LDPC_EINVAL;
+        if (B.iters && B.iters[c] && (reinterpret_cast<uintptr_t>(B.iters[c]) & 3)) return LDPC_EINVAL;
+    }
+    if (!ws || ws_bytes < P->ws_bytes) return LDPC_EWORKSPACE;
+    if (reinterpret_cast<uintptr_t>(ws) & 255) return LDPC_EINVAL;
+    return LDPC_OK;
+}
+
+// fill the host table for the current layouts and buffers
+void build_table(ldpc_plan* P, const PlanBuffers& B, char* ws) {
+    P->table.assign(P->ncodes, PlanCode{});
+    int64_t cn = 0, vn = 0, syn = 0, st = 0, io = 0;
+    for (int c = 0; c < P->ncodes; ++c) {
+        const ldpc_graph* g = P->graphs[c];
+        const int l = P->layouts[c];
+        const CodeRegion R = code_region(g, P->gammas[c], l, P->max_iters);
+        char* base = ws + P->region_off[c];
+        PlanCode& T = P->table[c];
+        T.D = g->qc;
+        T.mu = reinterpret_cast<float*>(base + R.mu);
+        T.msg = reinterpret_cast<float*>(base + R.msg);
+        T.postw = reinterpret_cast<float*>(base + R.postw);
+        T.bits = reinterpret_cast<uint64_t*>(base + R.bits);
+        T.unsat = reinterpret_cast<uint64_t*>(base + R.flags);
+        T.frozen = T.unsat + R.flag_words;
+        T.llr = B.llr[c];
+        T.post = B.post[c];
+        T.bits_out = B.bits[c];
+        T.iters = B.iters ? B.iters[c] : nullptr;
+        T.converged = B.converged ? B.converged[c] : nullptr;
+        T.flag_words = R.flag_words;
+        T.gamma = P->gammas[c];
+        T.tiles = R.tiles;
+        T.layout = l;
+        T.Gt = R.Gt;
+        T.fpl = layout_fpl(l);
+        T.dcc = plan_dc_class(g->dc_max);
+        T.dvc = plan_dv_class(g->dv_max);
+        const int rows_per_wave = 64 / layout_g(l);
+        T.cn_wpt = (g->m + rows_per_wave - 1) / rows_per_wave;
+        T.vn_wpt = (g->n + rows_per_wave - 1) / rows_per_wave;
+        T.io_vchunks = (g->n + 63) / 64;
+        T.io_fchunks = (R.tiles * R.Gt + 63) / 64;
+        T.cn0 = cn;
+        T.vn0 = vn;
+        T.syn0 = syn;
+        T.st0 = st;
+        T.io0 = io;
+        cn += (int64_t)T.tiles * T.cn_wpt;
+        vn += (int64_t)T.tiles * T.vn_wpt;
+        syn += ((int64_t)T.tiles * g->m + 63) / 64 * 64;
+        st += ((int64_t)T.gamma + 63) / 64 * 64;
+        io += (int64_t)T.io_vchunks * T.io_fchunks;
+    }
+    P->cn_waves = cn;
+    P->vn_waves = vn;
+    P->syn_threads = syn;
+    P->st_threads = st;
+    P->io_blocks = io;
+}
+
+bool same_buffers(const ldpc_plan* P, const PlanBuffers& B, const void* ws) {
+    if (!P->table_valid || P->table_ws != ws) return false;
+    for (int c = 0; c < P->ncodes; ++c) {
+        const PlanCode& T = P->table[c];
+        if (T.llr != B.llr[c] || T.post != B.post[c] || T.bits_out != B.bits[c]) return false;
+        if (T.iters != (B.iters ? B.iters[c] : nullptr)) return false;
+        if (T.converged != (B.converged ? B.converged[c] : nullptr)) return false;
+    }
+    return true;
+}
+
+// make the device table describe (layouts, B, ws); synchronous when it changes
+ldpc_status upload_table(ldpc_plan* P, const PlanBuffers& B, char* ws, hipStream_t st) {
+    if (same_buffers(P, B, ws)) return LDPC_OK;
+    build_table(P, B, ws);
+    if (hipMemcpyAsync(ws, P->table.data(), P->table.size() * sizeof(PlanCode), hipMemcpyHostToDevice, st) !=
+            hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return LDPC_EHIP;
+    P->table_valid = true;
+    P->table_ws = ws;
+    P->generation += 1;
+    return LDPC_OK;
+}
+
+unsigned blocks_for(int64_t units, int per_block) { return (unsigned)((units + per_block - 1) / per_block); }
+
+// enqueue one whole decode of the plan on st (table already on the device)
+void enqueue(ldpc_plan* P, char* ws, hipStream_t st) {
+    const PlanCode* T = reinterpret_cast<const PlanCode*>(ws);
+    const int nc = P->ncodes;
+    PlanStep S{0, 0, P->early, P->max_iters};
+    {
+        timing::Scope ts(17, st);
+        plan_ingest_kernel<<<(unsigned)P->io_blocks, 256, 0, st>>>(T, nc);
+    }
+    const unsigned cn_grid = blocks_for(P->cn_waves, kWavesPerBlock);
+    const unsigned vn_grid = blocks_for(P->vn_waves, kWavesPerBlock);
+    for (int it = 1; it <= P->max_iters; ++it) {
+        S.iter = it;
+        S.last = it == P->max_iters;
+        {
+            timing::Scope ts(18, st);
+            plan_cn_kernel<<<cn_grid, kBlock, 0, st>>>(T, nc, S);
+        }
+        {
+            timing::Scope ts(19, st);
+            plan_vn_kernel<<<vn_grid, kBlock, 0, st>>>(T, nc, S);
+        }
+    }
+    S.iter = P->max_iters;
+    timing::Scope ts(20, st);
+    plan_syndrome_kernel<<<blocks_for(P->syn_threads, kBlock), kBlock, 0, st>>>(T, nc, S);
+    plan_status_kernel<<<blocks_for(P->st_threads, kBlock), kBlock, 0, st>>>(T, nc, S);
+    plan_output_kernel<<<(unsigned)P->io_blocks, 256, 0, st>>>(T, nc);
+}
+
+void drop_graph(ldpc_plan* P) {
+    if (P->exec) (void)hipGraphExecDestroy(P->exec);
+    if (P->graph) (void)hipGraphDestroy(P->graph);
+    P->exec = nullptr;
+    P->graph = nullptr;
+    P->graph_generation = 0;
+}
+
+PlanBuffers make_buffers(const float* const* llr, float* const* post, uint8_t* const* bits, int32_t* const* iters,
+                         uint8_t* const* converged) {
+    return PlanBuffers{llr, post, bits, iters, converged};
+}
+
+}  // namespace
+
+extern "C" {
+
+ldpc_status ldpc_plan_create(const ldpc_graph* const* graphs, const int32_t* gammas, int32_t ncodes,
+                             int32_t max_iters, int32_t early_stop, ldpc_plan** out) {
+    if (!out) return LDPC_EINVAL;
+    *out = nullptr;
+    if (!graphs || !gammas || ncodes < 1 || ncodes > LDPC_PLAN_MAX_CODES) return LDPC_EINVAL;
+    if (max_iters < 1 || max_iters > LDPC_MAX_ITERS) return LDPC_EINVAL;
+    for (int c = 0; c < ncodes; ++c) {
+        if (!graphs[c] || graphs[c]->kind != LDPC_GRAPH_QC || gammas[c] < 1) return LDPC_EINVAL;
+        if (graphs[c]->dc_max > kPlanMaxRowWeight) return LDPC_EUNSUPPORTED;
+        if ((int64_t)gammas[c] * graphs[c]->n > ((int64_t)1 << 40)) return LDPC_EUNSUPPORTED;
+    }
+    ldpc_plan* P = new (std::nothrow) ldpc_plan();
+    if (!P) return LDPC_ENOMEM;
+    P->ncodes = ncodes;
+    P->max_iters = max_iters;
+    P->early = early_stop ? 1 : 0;
+    P->graphs.assign(graphs, graphs + ncodes);
+    P->gammas.assign(gammas, gammas + ncodes);
+    P->layouts.resize(ncodes);
+    P->table_bytes = align256((size_t)ncodes * sizeof(PlanCode));
+    size_t off = P->table_bytes;
+    for (int c = 0; c < ncodes; ++c) {
+        P->layouts[c] = default_layout(graphs[c], gammas[c]);
+        size_t most = 0;
+        for (int l = 0; l < kPlanLayouts; ++l)
+            if (layout_allowed(graphs[c], l)) most = std::max(most, code_region(graphs[c], gammas[c], l, max_iters).total);
+        P->region_off.push_back(off);
+        off = align256(off + most);
+    }
+    P->ws_bytes = off;
+    *out = P;
+    return LDPC_OK;
+}
+
+void ldpc_plan_destroy(ldpc_plan* P) {
+    if (!P) return;
+    drop_graph(P);
+    if (P->cap_stream) (void)hipStreamDestroy(P->cap_stream);
+    delete P;
+}
+
+ldpc_status ldpc_plan_workspace_size(const ldpc_plan* P, size_t* bytes) {
+    if (!P || !bytes) return LDPC_EINVAL;
+    *bytes = P->ws_bytes;
+    return LDPC_OK;
+}
+
+ldpc_status ldpc_plan_set_layout(ldpc_plan* P, int32_t code, int32_t layout) {
+    if (!P || code < 0 || code >= P->ncodes) return LDPC_EINVAL;
+    if (layout == -1) layout = default_layout(P->graphs[code], P->gammas[code]);
+    if (!layout_allowed(P->graphs[code], layout)) return LDPC_EINVAL;
+    if (P->layouts[code] != layout) {
+        P->layouts[code] = layout;
+        P->table_valid = false;
+    }
+    return LDPC_OK;
+}
+
+ldpc_status ldpc_plan_get_layout(const ldpc_plan* P, int32_t code, int32_t* layout) {
+    if (!P || !layout || code < 0 || code >= P->ncodes) return LDPC_EINVAL;
+    *layout = P->layouts[code];
+    return LDPC_OK;
+}
+
+ldpc_status ldpc_plan_decode(ldpc_plan* P, const float* const* llr, float* const* post, uint8_t* const* bits,
+                             int32_t* const* iters, uint8_t* const* converged, void* workspace,
+                             size_t workspace_bytes, void* stream) {
+    if (!P) return LDPC_EINVAL;
+    const PlanBuffers B = make_buffers(llr, post, bits, iters, converged);
+    ldpc_status chk = check_buffers(P, B, workspace, workspace_bytes);
+    if (chk != LDPC_OK) return chk;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    char* ws = reinterpret_cast<char*>(workspace);
+    (void)hipGetLastError();
+    ldpc_status up = upload_table(P, B, ws, st);
+    if (up != LDPC_OK) return up;
+    enqueue(P, ws, st);
+    return hipGetLastError() == hipSuccess ? LDPC_OK : LDPC_EHIP;
+}
+
+ldpc_status ldpc_plan_capture(ldpc_plan* P, const float* const* llr, float* const* post, uint8_t* const* bits,
+                              int32_t* const* iters, uint8_t* const* converged, void* workspace,
+                              size_t workspace_bytes, void* stream) {
+    if (!P) return LDPC_EINVAL;
+    const PlanBuffers B = make_buffers(llr, post, bits, iters, converged);
+    ldpc_status chk = check_buffers(P, B, workspace, workspace_bytes);
+    if (chk != LDPC_OK) return chk;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    char* ws = reinterpret_cast<char*>(workspace);
+    (void)hipGetLastError();
+    ldpc_status up = upload_table(P, B, ws, st);
+    if (up != LDPC_OK) return up;
+    if (!P->cap_stream && hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+        P->cap_stream = nullptr;
+        return LDPC_EHIP;
+    }
+    drop_graph(P);
+    const bool timing_was = timing::set_enabled(false);
+    hipError_t e = hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        enqueue(P, ws, P->cap_stream);
+        e = hipStreamEndCapture(P->cap_stream, &P->graph);
+    }
+    timing::set_enabled(timing_was);
+    if (e == hipSuccess) e = hipGraphInstantiate(&P->exec, P->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        drop_graph(P);
+        (void)hipGetLastError();
+        return LDPC_EHIP;
+    }
+    P->graph_generation = P->generation;
+    return LDPC_OK;
+}
+
+ldpc_status ldpc_plan_replay(ldpc_plan* P, void* stream) {
+    if (!P) return LDPC_EINVAL;
+    if (!P->exec || P->graph_generation != P->generation || !P->table_valid) return LDPC_EINVAL;
+    (void)hipGetLastError();
+    if (hipGraphLaunch(P->exec, reinterpret_cast<hipStream_t>(stream)) != hipSuccess) return LDPC_EHIP;
+    return LDPC_OK;
+}
+
+ldpc_status ldpc_plan_autotune(ldpc_plan* P, const float* const* llr, float* const* post, uint8_t* const* bits,
+                               int32_t* const* iters, uint8_t* const* converged, void* workspace,
+                               size_t workspace_bytes, int32_t trials, void* stream, double* best_ms) {
+    if (!P || trials < 1) return LDPC_EINVAL;
+    const PlanBuffers B = make_buffers(llr, post, bits, iters, converged);
+    ldpc_status chk = check_buffers(P, B, workspace, workspace_bytes);
+    if (chk != LDPC_OK) return chk;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    char* ws = reinterpret_cast<char*>(workspace);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        return LDPC_EHIP;
+    }
+    const bool timing_was = timing::set_enabled(false);
+    // time of one whole decode with the current layouts (after one warm-up)
+    auto measure = [&](double& out) -> ldpc_status {
+        (void)hipGetLastError();
+        ldpc_status up = upload_table(P, B, ws, st);
+        if (up != LDPC_OK) return up;
+        enqueue(P, ws, st);
+        float ms = 0.0f;
+        if (hipEventRecord(e0, st) != hipSuccess) return LDPC_EHIP;
+        for (int t = 0; t < trials; ++t) enqueue(P, ws, st);
+        if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess || hipGetLastError() != hipSuccess)
+            return LDPC_EHIP;
+        out = (double)ms / trials;
+        return LDPC_OK;
+    };
+    // one pass of coordinate descent: each code in turn tries its other
+    // layouts with the rest of the plan fixed, and keeps the fastest whole decode
+    double best = 0.0;
+    ldpc_status status = measure(best);
+    for (int c = 0; c < P->ncodes && status == LDPC_OK; ++c) {
+        const int start = P->layouts[c];
+        int keep = start;
+        for (int l = 0; l < kPlanLayouts && status == LDPC_OK; ++l) {
+            if (l == start || !layout_allowed(P->graphs[c], l)) continue;
+            if (layout_g(l) > 8 && layout_g(l) / 2 >= P->gammas[c]) continue;   // G at most the next power of two
+            P->layouts[c] = l;
+            P->table_valid = false;
+            double ms = 0.0;
+            status = measure(ms);
+            if (status == LDPC_OK && ms < best) {
+                best = ms;
+                keep = l;
+            }
+        }
+        P->layouts[c] = keep;
+        P->table_valid = false;
+    }
+    timing::set_enabled(timing_was);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (status == LDPC_OK && best_ms) *best_ms = best;
+    return status;
+}
+
+}  // extern "C"

@@ -29,7 +29,10 @@ _vp, _i32, _i64, _sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c
 
 OK, EINVAL, EWORKSPACE, EHIP, EUNSUPPORTED, ENOMEM = 0, -1, -2, -3, -4, -5
 GRAPH_QC, GRAPH_CONV = 0, 1
-TIMING_CLASSES = 17
+LAYOUT_G8, LAYOUT_G16, LAYOUT_G32, LAYOUT_G64, LAYOUT_G64F4 = 0, 1, 2, 3, 4
+LAYOUT_NAMES = ["G8", "G16", "G32", "G64", "G64F4"]
+PLAN_MAX_CODES = 16
+TIMING_CLASSES = 21
 MAX_ITERS = 100000
 
 
@@ -59,6 +62,16 @@ _nms_decode = _sig("ldpc_nms_decode", _i32, [_vp, _vp, _i32, _i32, _vp, _i32, _v
 _nms_ws_size = _sig("ldpc_nms_train_workspace_size", _i32, [_vp, _i32, _i32, _i32, ctypes.POINTER(_sz)])
 _nms_forward = _sig("ldpc_nms_train_forward", _i32, [_vp, _vp, _i32, _i32, _i32, _vp, _vp, _vp, _sz, _vp])
 _nms_backward = _sig("ldpc_nms_train_backward", _i32, [_vp, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _sz, _vp])
+_plan_create = _sig("ldpc_plan_create", _i32, [_vp, _vp, _i32, _i32, _i32, ctypes.POINTER(_vp)])
+_plan_destroy = _sig("ldpc_plan_destroy", None, [_vp])
+_plan_ws_size = _sig("ldpc_plan_workspace_size", _i32, [_vp, ctypes.POINTER(_sz)])
+_plan_set_layout = _sig("ldpc_plan_set_layout", _i32, [_vp, _i32, _i32])
+_plan_get_layout = _sig("ldpc_plan_get_layout", _i32, [_vp, _i32, ctypes.POINTER(_i32)])
+_plan_decode = _sig("ldpc_plan_decode", _i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp])
+_plan_capture = _sig("ldpc_plan_capture", _i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp])
+_plan_replay = _sig("ldpc_plan_replay", _i32, [_vp, _vp])
+_plan_autotune = _sig("ldpc_plan_autotune", _i32,
+                      [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _i32, _vp, ctypes.POINTER(ctypes.c_double)])
 _decode_window = _sig("ldpc_decode_window", _i32, [_vp, _vp, _i32, _i32, _i32, _vp, _vp, _vp, _sz, _vp])
 _decode_pipeline = _sig("ldpc_decode_pipeline", _i32, [_vp, _vp, _i32, _i32, _vp, _vp, _vp, _sz, _vp])
 _awgn_llr = _sig("ldpc_awgn_llr", _i32, [_i64, _i32, ctypes.c_double, ctypes.c_uint64, _i64, _vp, _vp])
@@ -71,7 +84,9 @@ _class_name = _sig("ldpc_kernel_class_name", ctypes.c_char_p, [_i32])
 EXPORTED = ["ldpc_graph_create_qc", "ldpc_graph_create_ldpccc_from_qc", "ldpc_graph_create_ldpccc_sf",
             "ldpc_graph_get_info", "ldpc_graph_destroy", "ldpc_workspace_size", "ldpc_decode",
             "ldpc_nms_decode", "ldpc_nms_train_workspace_size", "ldpc_nms_train_forward",
-            "ldpc_nms_train_backward", "ldpc_decode_window", "ldpc_decode_pipeline", "ldpc_awgn_llr",
+            "ldpc_nms_train_backward", "ldpc_plan_create", "ldpc_plan_destroy", "ldpc_plan_workspace_size",
+            "ldpc_plan_set_layout", "ldpc_plan_get_layout", "ldpc_plan_decode", "ldpc_plan_capture",
+            "ldpc_plan_replay", "ldpc_plan_autotune", "ldpc_decode_window", "ldpc_decode_pipeline", "ldpc_awgn_llr",
             "ldpc_count_errors", "ldpc_status_str", "ldpc_timing_enable", "ldpc_timing_read",
             "ldpc_kernel_class_name"]
 
@@ -359,3 +374,105 @@ def timing_read() -> dict:
     ms = (ctypes.c_double * TIMING_CLASSES)()
     _check(_timing_read(cnt, ms, TIMING_CLASSES), "ldpc_timing_read")
     return {_class_name(c).decode(): (int(cnt[c]), float(ms[c])) for c in range(TIMING_CLASSES)}
+
+
+class Plan:
+    """Several QC graphs, each with its own batch size, decoded together by
+    one check-node and one variable-node launch per iteration
+    (`ldpc_plan_*`).  Buffers are lists of device tensors, one per code."""
+
+    def __init__(self, graphs, gammas, max_iters: int, early_stop: bool = False):
+        n = len(graphs)
+        if n != len(gammas):
+            raise ValueError("one batch size per graph")
+        self.graphs = list(graphs)          # the plan refers to them
+        self.gammas = [int(x) for x in gammas]
+        self.max_iters = int(max_iters)
+        hs = (_vp * max(n, 1))(*[g.handle for g in graphs])
+        gs = (_i32 * max(n, 1))(*self.gammas)
+        h = _vp()
+        _check(_plan_create(hs, gs, n, self.max_iters, int(bool(early_stop)), ctypes.byref(h)), "ldpc_plan_create")
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def workspace_size(self) -> int:
+        out = _sz()
+        _check(_plan_ws_size(self._h, ctypes.byref(out)), "ldpc_plan_workspace_size")
+        return int(out.value)
+
+    def workspace(self, device=None):
+        return torch.empty(max(self.workspace_size(), 1), dtype=torch.uint8, device=device or "cuda")
+
+    def set_layout(self, code: int, layout: int):
+        _check(_plan_set_layout(self._h, int(code), int(layout)), "ldpc_plan_set_layout")
+
+    def layout(self, code: int) -> int:
+        out = _i32()
+        _check(_plan_get_layout(self._h, int(code), ctypes.byref(out)), "ldpc_plan_get_layout")
+        return int(out.value)
+
+    def outputs(self, device=None):
+        dev = device or "cuda"
+        outs = []
+        for g, gamma in zip(self.graphs, self.gammas):
+            outs.append((torch.empty((gamma, g.n), dtype=torch.float32, device=dev),
+                         torch.empty((gamma, g.n), dtype=torch.uint8, device=dev),
+                         torch.empty((gamma,), dtype=torch.int32, device=dev),
+                         torch.empty((gamma,), dtype=torch.uint8, device=dev)))
+        return outs
+
+    def _arrays(self, llrs, outs):
+        n = len(self.graphs)
+        if len(llrs) != n or len(outs) != n:
+            raise ValueError("one llr tensor and one output tuple per code")
+        for c, (g, gamma) in enumerate(zip(self.graphs, self.gammas)):
+            _need(llrs[c], torch.float32, (gamma, g.n), f"llr[{c}]")
+            post, bits, it, conv = outs[c]
+            _need(post, torch.float32, (gamma, g.n), f"post[{c}]")
+            _need(bits, torch.uint8, (gamma, g.n), f"bits[{c}]")
+            _need(it, torch.int32, (gamma,), f"iters[{c}]")
+            _need(conv, torch.uint8, (gamma,), f"converged[{c}]")
+
+        def arr(ts):
+            return (_vp * n)(*[t.data_ptr() for t in ts])
+        return (arr(llrs), arr([o[0] for o in outs]), arr([o[1] for o in outs]), arr([o[2] for o in outs]),
+                arr([o[3] for o in outs]))
+
+    def decode(self, llrs, outs=None, ws=None, stream=None):
+        """Decode llrs[c] [gamma_c, n_c]; returns [(post, bits, iters, converged)] per code."""
+        if outs is None:
+            outs = self.outputs(llrs[0].device)
+        if ws is None:
+            ws = self.workspace(llrs[0].device)
+        a = self._arrays(llrs, outs)
+        _check(_plan_decode(self._h, *a, ws.data_ptr(), ws.numel(), _stream_handle(stream)), "ldpc_plan_decode")
+        return outs
+
+    def capture(self, llrs, outs, ws, stream=None):
+        """Record the decode of these buffers into a HIP graph (runs nothing)."""
+        a = self._arrays(llrs, outs)
+        _check(_plan_capture(self._h, *a, ws.data_ptr(), ws.numel(), _stream_handle(stream)), "ldpc_plan_capture")
+
+    def replay(self, stream=None):
+        _check(_plan_replay(self._h, _stream_handle(stream)), "ldpc_plan_replay")
+
+    def autotune(self, llrs, outs, ws, trials: int = 3, stream=None) -> float:
+        """Coordinate descent over the codes' layouts, timing whole decodes of
+        the plan on these buffers; returns the final time per decode (ms)."""
+        a = self._arrays(llrs, outs)
+        best = ctypes.c_double()
+        _check(_plan_autotune(self._h, *a, ws.data_ptr(), ws.numel(), int(trials), _stream_handle(stream),
+                              ctypes.byref(best)), "ldpc_plan_autotune")
+        return float(best.value)
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h and _plan_destroy is not None:
+            _plan_destroy(h)
+        self._h = None
+
+    def __del__(self):
+        self.close()

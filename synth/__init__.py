@@ -277,6 +277,25 @@ def encoder_for(shifts, p: int) -> QCEncoder:
 # named workloads (the shapes of the paper-scale experiments this package runs)
 # ----------------------------------------------------------------------------
 
+# Mixed batch for the multi-code plan: QC codes of rates 1/2, 2/3 and 5/6
+# (3 x 6, 3 x 9, 3 x 18 bases), small to large circulants, 8 to 1024 frames
+# per code, each at its own Eb/N0; shifts drawn with seed 50 + index.
+MIXED_CODES = [
+    dict(J=3, L=6, p=27, gamma=1024, ebn0_db=3.0),
+    dict(J=3, L=6, p=81, gamma=256, ebn0_db=2.5),
+    dict(J=3, L=6, p=2700, gamma=64, ebn0_db=1.75),
+    dict(J=3, L=9, p=72, gamma=512, ebn0_db=3.0),
+    dict(J=3, L=9, p=2400, gamma=32, ebn0_db=2.5),
+    dict(J=3, L=18, p=36, gamma=128, ebn0_db=3.5),
+    dict(J=3, L=18, p=3600, gamma=8, ebn0_db=3.5),
+]
+
+
+def mixed_shifts(i: int):
+    c = MIXED_CODES[i]
+    return draw_qc_shifts(c["J"], c["L"], c["p"], 50 + i)
+
+
 WORKLOADS = {
     # (3,6)-regular QC code, p = 64: n = 384, m = 192; 64 frames, all-zero codeword, 2.0 dB
     "qc36_p64": dict(J=3, L=6, p=64, shift_seed=1, noise_seed=101, gamma=64, ebn0_db=2.0,

@@ -250,3 +250,63 @@ def test_training_workspace_and_validation():
     assert b(qc.handle, 64, 12, 4, FAKE, FAKE, FAKE, FAKE, ws - 1, None) == ldpc.EWORKSPACE
     assert b(cc.handle, 64, 12, 4, FAKE, FAKE, FAKE, FAKE, ws, None) == ldpc.EINVAL
     assert b(qc.handle, 64, 12, 0, FAKE, FAKE, FAKE, FAKE, ws, None) == ldpc.EINVAL
+
+
+def test_plan_creation_and_layout_rules():
+    g36 = ldpc.Graph.qc(synth.draw_qc_shifts(3, 6, 27, 1), 27)
+    g39 = ldpc.Graph.qc(synth.draw_qc_shifts(3, 9, 72, 2), 72)
+    cc = ldpc.Graph.ldpccc_from_qc(synth.draw_qc_shifts(3, 6, 32, 2), 32, 16)
+    wide = ldpc.Graph.qc(synth.draw_qc_shifts(1, 25, 7, 3), 7)     # row weight 25
+    h = ctypes.c_void_p()
+    arr = lambda gs: (ctypes.c_void_p * len(gs))(*[g.handle for g in gs])
+    gam = lambda xs: (ctypes.c_int32 * len(xs))(*xs)
+    create = ldpc._plan_create
+    assert create(arr([g36]), gam([8]), 1, 20, 1, None) == ldpc.EINVAL
+    assert create(None, gam([8]), 1, 20, 1, ctypes.byref(h)) == ldpc.EINVAL
+    assert create(arr([g36]), gam([8]), 0, 20, 1, ctypes.byref(h)) == ldpc.EINVAL
+    assert create(arr([g36] * 17), gam([8] * 17), 17, 20, 1, ctypes.byref(h)) == ldpc.EINVAL
+    assert create(arr([g36]), gam([0]), 1, 20, 1, ctypes.byref(h)) == ldpc.EINVAL
+    assert create(arr([g36]), gam([8]), 1, 0, 1, ctypes.byref(h)) == ldpc.EINVAL
+    assert create(arr([g36, cc]), gam([8, 8]), 2, 20, 1, ctypes.byref(h)) == ldpc.EINVAL
+    assert create(arr([g36, wide]), gam([8, 8]), 2, 20, 1, ctypes.byref(h)) == ldpc.EUNSUPPORTED
+    # default layouts: the smallest tile holding the batch; 4 frames per lane
+    # only for row weight <= 6 and large batches
+    gammas = [8, 12, 20, 64, 1024, 1024, 33]
+    graphs = [g36, g36, g36, g36, g36, g39, g39]
+    plan = ldpc.Plan(graphs, gammas, 20, early_stop=True)
+    want = [ldpc.LAYOUT_G8, ldpc.LAYOUT_G16, ldpc.LAYOUT_G32, ldpc.LAYOUT_G64, ldpc.LAYOUT_G64F4, ldpc.LAYOUT_G64,
+            ldpc.LAYOUT_G64]
+    assert [plan.layout(c) for c in range(len(graphs))] == want
+    with pytest.raises(ldpc.LdpcError):
+        plan.set_layout(5, ldpc.LAYOUT_G64F4)          # 3 x 9: row weight 9
+    with pytest.raises(ldpc.LdpcError):
+        plan.set_layout(7, ldpc.LAYOUT_G8)
+    plan.set_layout(4, ldpc.LAYOUT_G8)
+    assert plan.layout(4) == ldpc.LAYOUT_G8
+    plan.set_layout(4, -1)
+    assert plan.layout(4) == ldpc.LAYOUT_G64F4
+    # the workspace holds every code in any allowed layout
+    ws = plan.workspace_size()
+    single = sum(g.workspace_size(x, 20) for g, x in zip(graphs, gammas))
+    assert ws >= single
+    # nothing captured yet
+    assert ldpc._plan_replay(plan.handle, None) == ldpc.EINVAL
+    n = len(graphs)
+    fake = (ctypes.c_void_p * n)(*([FAKE] * n))
+    d = ldpc._plan_decode
+    assert d(plan.handle, fake, fake, fake, None, None, FAKE, ws - 1, None) == ldpc.EWORKSPACE
+    assert d(plan.handle, fake, fake, fake, None, None, FAKE + 4, ws, None) == ldpc.EINVAL
+    assert d(plan.handle, None, fake, fake, None, None, FAKE, ws, None) == ldpc.EINVAL
+    bad = (ctypes.c_void_p * n)(*([FAKE] * (n - 1) + [0]))
+    assert d(plan.handle, fake, bad, fake, None, None, FAKE, ws, None) == ldpc.EINVAL
+    assert d(None, fake, fake, fake, None, None, FAKE, ws, None) == ldpc.EINVAL
+    assert ldpc._plan_autotune(plan.handle, fake, fake, fake, None, None, FAKE, ws, 0, None, None) == ldpc.EINVAL
+    plan.close()
+    ldpc._plan_destroy(None)
+
+
+def test_mixed_workload_codes_fit_a_plan():
+    graphs = [ldpc.Graph.qc(synth.mixed_shifts(i), c["p"]) for i, c in enumerate(synth.MIXED_CODES)]
+    plan = ldpc.Plan(graphs, [c["gamma"] for c in synth.MIXED_CODES], 20, early_stop=True)
+    assert plan.workspace_size() > 0
+    assert [g.info["dc_max"] for g in graphs] == [6, 6, 6, 9, 9, 18, 18]

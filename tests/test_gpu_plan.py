@@ -1,0 +1,151 @@
+"""GPU tests of the multi-code plan (through the C ABI): every code of a
+plan decodes exactly as ldpc_decode decodes it alone (same arithmetic and
+edge order, so bit for bit: posteriors, decisions, iteration counts,
+convergence flags), in every lane layout, eagerly and by graph replay; and a
+small code of a plan against the FP64 reference with the tolerances of
+test_gpu_decode."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from paper_1204_0334_amd import ldpc
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+RAGGED = [dict(J=3, L=6, p=27, gamma=1, ebn0_db=2.5), dict(J=3, L=6, p=27, gamma=7, ebn0_db=2.5),
+          dict(J=3, L=9, p=72, gamma=9, ebn0_db=3.0), dict(J=3, L=18, p=36, gamma=33, ebn0_db=3.5),
+          dict(J=3, L=6, p=81, gamma=65, ebn0_db=2.0), dict(J=3, L=6, p=64, gamma=300, ebn0_db=2.0),
+          dict(J=3, L=9, p=40, gamma=200, ebn0_db=3.0)]
+
+
+def make_case(specs, seed):
+    graphs, llrs = [], []
+    for i, c in enumerate(specs):
+        g = ldpc.Graph.qc(synth.draw_qc_shifts(c["J"], c["L"], c["p"], 50 + i), c["p"])
+        s2 = synth.ebn0_to_sigma2(c["ebn0_db"], 1.0 - c["J"] / c["L"])
+        graphs.append(g)
+        llrs.append(ldpc.awgn_llr(g.n, c["gamma"], s2, seed + i, 0, device=DEV))
+    return graphs, llrs
+
+
+def single_code(graphs, llrs, iters, early):
+    return [ldpc.decode(g, x, iters, early_stop=early) for g, x in zip(graphs, llrs)]
+
+
+def assert_same(outs, refs, what):
+    torch.cuda.synchronize()
+    for c, (o, r) in enumerate(zip(outs, refs)):
+        for name, a, b in zip(("post", "bits", "iters", "converged"), o, r):
+            assert torch.equal(a, b), f"{what}: code {c} {name} differs"
+
+
+@pytest.mark.parametrize("early", [True, False])
+def test_mixed_plan_matches_single_code_decoder(early):
+    specs = synth.MIXED_CODES
+    print(f"[gpu] mixed plan early={early}", flush=True)
+    graphs, llrs = make_case(specs, 1000)
+    plan = ldpc.Plan(graphs, [c["gamma"] for c in specs], 20, early_stop=early)
+    outs = plan.decode(llrs)
+    assert_same(outs, single_code(graphs, llrs, 20, early), "mixed")
+    if early:
+        assert sum(int(o[3].sum()) for o in outs) > 0
+
+
+def test_every_layout_matches_single_code_decoder():
+    graphs, llrs = make_case(RAGGED, 2000)
+    gammas = [c["gamma"] for c in RAGGED]
+    refs = single_code(graphs, llrs, 12, True)
+    ws = None
+    for layout in range(5):
+        plan = ldpc.Plan(graphs, gammas, 12, early_stop=True)
+        for c in range(len(graphs)):
+            try:
+                plan.set_layout(c, layout)
+            except ldpc.LdpcError:
+                pass                       # G64F4 where the row weight exceeds 6
+        print(f"[gpu] ragged plan layout={ldpc.LAYOUT_NAMES[layout]}", flush=True)
+        ws = plan.workspace(DEV) if ws is None else ws
+        assert_same(plan.decode(llrs, ws=ws), refs, f"layout {ldpc.LAYOUT_NAMES[layout]}")
+
+
+def test_fixed_iterations_every_layout():
+    graphs, llrs = make_case(RAGGED[:5], 3000)
+    gammas = [c["gamma"] for c in RAGGED[:5]]
+    refs = single_code(graphs, llrs, 3, False)
+    for layout in (0, 2, 3):
+        plan = ldpc.Plan(graphs, gammas, 3, early_stop=False)
+        for c in range(len(graphs)):
+            plan.set_layout(c, layout)
+        print(f"[gpu] fixed-iteration plan layout={ldpc.LAYOUT_NAMES[layout]}", flush=True)
+        assert_same(plan.decode(llrs), refs, f"3 iterations, layout {ldpc.LAYOUT_NAMES[layout]}")
+
+
+def test_plan_code_against_fp64_reference():
+    spec = [dict(J=3, L=6, p=27, gamma=20, ebn0_db=2.5), dict(J=3, L=18, p=36, gamma=40, ebn0_db=3.5)]
+    graphs, llrs = make_case(spec, 4000)
+    plan = ldpc.Plan(graphs, [20, 40], 20, early_stop=True)
+    print("[gpu] plan vs reference", flush=True)
+    outs = plan.decode(llrs)
+    torch.cuda.synchronize()
+    for i, c in enumerate(spec):
+        H = oracle.qc_parity_check(synth.draw_qc_shifts(c["J"], c["L"], c["p"], 50 + i), c["p"])
+        x = llrs[i].cpu().numpy()
+        ref = oracle.decode_block(H, x, 20, early_stop=True)
+        post, bits, it, conv = (t.cpu().numpy() for t in outs[i])
+        ok = ref["min_abs"] >= 1e-3
+        assert np.array_equal(bits[ok], ref["bits"][ok])
+        assert np.array_equal(it[ok], ref["iters"][ok])
+        assert np.array_equal(conv[ok], ref["converged"][ok])
+        gate = ok & (conv == 1) & (ref["converged"] == 1)
+        r = np.clip(ref["post"][gate], -30, 30)
+        err = np.abs(np.clip(post[gate].astype(np.float64), -30, 30) - r) / np.maximum(np.abs(r), 1.0)
+        assert err.max() <= 1e-4
+        assert np.array_equal(conv.astype(bool), ~H.syndrome(bits).any(1))
+
+
+def test_graph_replay_matches_eager_decode():
+    graphs, llrs = make_case(synth.MIXED_CODES, 5000)
+    gammas = [c["gamma"] for c in synth.MIXED_CODES]
+    plan = ldpc.Plan(graphs, gammas, 20, early_stop=True)
+    ws = plan.workspace(DEV)
+    eager = plan.decode(llrs, ws=ws)
+    torch.cuda.synchronize()
+    eager = [tuple(t.clone() for t in o) for o in eager]
+    outs = plan.outputs(DEV)
+    print("[gpu] plan capture", flush=True)
+    plan.capture(llrs, outs, ws)
+    scratch = torch.zeros(1 << 20, device=DEV)
+    for rep in range(3):
+        for o in outs:
+            for t in o:
+                t.zero_()
+        scratch.add_(1.0)                  # eager work between replays
+        torch.cuda.synchronize()
+        print(f"[gpu] plan replay {rep}", flush=True)
+        plan.replay()
+        torch.cuda.synchronize()
+        assert_same(outs, eager, f"replay {rep}")
+    # binding other buffers invalidates the graph
+    plan.decode(llrs, ws=ws)
+    with pytest.raises(ldpc.LdpcError):
+        plan.replay()
+
+
+def test_autotune_keeps_results():
+    graphs, llrs = make_case(synth.MIXED_CODES, 6000)
+    gammas = [c["gamma"] for c in synth.MIXED_CODES]
+    plan = ldpc.Plan(graphs, gammas, 20, early_stop=True)
+    ws = plan.workspace(DEV)
+    outs = plan.outputs(DEV)
+    print("[gpu] plan autotune", flush=True)
+    best = plan.autotune(llrs, outs, ws, trials=2)
+    assert best > 0
+    for c, g in enumerate(graphs):
+        l = plan.layout(c)
+        assert 0 <= l <= 4 and (l != ldpc.LAYOUT_G64F4 or g.info["dc_max"] <= 6)
+        assert ldpc.LAYOUT_NAMES[l] in ldpc.LAYOUT_NAMES
+    assert_same(plan.decode(llrs, outs=outs, ws=ws), single_code(graphs, llrs, 20, True), "after autotune")
