@@ -237,11 +237,13 @@ ldpc_status ldpc_nms_train_backward(const ldpc_graph* g, int32_t gamma, int32_t 
  *     working on 8, 4 or 2 consecutive rows (variables) at once;
  *   LDPC_LAYOUT_G64: tiles of 64 frames, one row per wavefront;
  *   LDPC_LAYOUT_G64F4: tiles of 256 frames, 4 frames per lane (row weight
- *     <= 6 and column weight <= 8 only).
+ *     <= 6 and column weight <= 8 only);
+ *   LDPC_LAYOUT_G64F2: tiles of 128 frames, 2 frames per lane (row weight
+ *     <= 12 and column weight <= 8 only).
  * Graphs in a plan have row weight <= 24 (EUNSUPPORTED otherwise): one
  * kernel serves all codes and carries the registers of its heaviest case.
- * The default is the smallest tile >= gamma (G64F4 for large batches when
- * allowed); ldpc_plan_autotune times every candidate per code and keeps the
+ * The default is the smallest tile >= gamma (for large batches G64F4, else
+ * G64F2, when allowed and padding stays under 1/8); ldpc_plan_autotune times every candidate per code and keeps the
  * fastest; ldpc_plan_set_layout sets one (-1 = the default).
  *
  * ldpc_plan_create: graphs (host array of ncodes QC graphs, which must
@@ -277,7 +279,8 @@ ldpc_status ldpc_nms_train_backward(const ldpc_graph* g, int32_t gamma, int32_t 
  */
 typedef struct ldpc_plan ldpc_plan;
 #define LDPC_PLAN_MAX_CODES 16
-enum { LDPC_LAYOUT_G8 = 0, LDPC_LAYOUT_G16 = 1, LDPC_LAYOUT_G32 = 2, LDPC_LAYOUT_G64 = 3, LDPC_LAYOUT_G64F4 = 4 };
+enum { LDPC_LAYOUT_G8 = 0, LDPC_LAYOUT_G16 = 1, LDPC_LAYOUT_G32 = 2, LDPC_LAYOUT_G64 = 3, LDPC_LAYOUT_G64F4 = 4,
+       LDPC_LAYOUT_G64F2 = 5 };
 
 ldpc_status ldpc_plan_create(const ldpc_graph* const* graphs, const int32_t* gammas, int32_t ncodes,
                              int32_t max_iters, int32_t early_stop, ldpc_plan** out);

@@ -195,56 +195,47 @@ __device__ __forceinline__ MinInfo row_minima(const float (&mag)[DC], const uint
     return r;
 }
 
-// Check-node pass, prologue shared by both check rules: with early stopping,
-// skip tiles whose frames were all frozen by iteration iter-2, and OR the
-// syndrome of iteration iter-1's decisions into unsat[iter-1].  Returns false
-// when the wave has nothing to do.
-template <int DCMAX, int FPL>
-__device__ __forceinline__ bool cn_prologue(const QCDesc& D, const BlockParams& P, const QCRow& R, int tile,
-                                            int lane, int nvalid) {
-    if (P.early && P.iter >= 3) {
-        const uint64_t* fz = P.frozen + ((size_t)(P.iter - 2) * P.tiles + tile) * FPL;
-        bool all = true;
+// Check-node pass with early stopping: false when every frame of the tile was
+// frozen by iteration iter-2 (the wave has nothing to do).
+template <int FPL>
+__device__ __forceinline__ bool cn_tile_live(const BlockParams& P, int tile) {
+    if (!(P.early && P.iter >= 3)) return true;
+    const uint64_t* fz = P.frozen + ((size_t)(P.iter - 2) * P.tiles + tile) * FPL;
+    bool all = true;
 #pragma unroll
-        for (int f = 0; f < FPL; ++f) all = all && (fz[f] == ~0ull);
-        if (all) return false;
-    }
-    if (P.early && P.iter >= 2) {
-        uint64_t par[FPL];
+    for (int f = 0; f < FPL; ++f) all = all && (fz[f] == ~0ull);
+    return !all;
+}
+
+// OR the frames whose decisions of iteration iter-1 violate the row (bad,
+// already masked to valid frames) into unsat[iter-1]: lane f handles word f.
+// A stale read can only miss bits (the word only gains bits during the
+// pass), which costs a redundant atomic, never a missed one.
+template <int FPL>
+__device__ __forceinline__ void cn_publish_unsat(const BlockParams& P, int tile, int lane,
+                                                 const uint64_t (&bad)[FPL]) {
+    uint64_t* un = P.unsat + ((size_t)(P.iter - 1) * P.tiles + tile) * FPL;
 #pragma unroll
-        for (int f = 0; f < FPL; ++f) par[f] = 0;
-        const uint64_t* bt = P.bits + (size_t)tile * D.n * FPL;
-#pragma unroll
-        for (int k = 0; k < DCMAX; ++k) {
-            if (!R.valid(D, k)) continue;
-            const uint64_t* w = bt + (size_t)R.var(D, k) * FPL;
-#pragma unroll
-            for (int f = 0; f < FPL; ++f) par[f] ^= w[f];
-        }
-        uint64_t* un = P.unsat + ((size_t)(P.iter - 1) * P.tiles + tile) * FPL;
-#pragma unroll
-        for (int f = 0; f < FPL; ++f) {
-            const uint64_t bad = par[f] & valid_word<FPL>(nvalid, f);
-            if (bad && lane == f) {
-                // a stale read can only miss bits (the word only gains bits
-                // during this pass), which costs a redundant atomic, never a
-                // missed one
-                if ((__atomic_load_n(un + f, __ATOMIC_RELAXED) & bad) != bad)
-                    atomicOr((unsigned long long*)(un + f), (unsigned long long)bad);
-            }
+    for (int f = 0; f < FPL; ++f) {
+        if (bad[f] && lane == f) {
+            if ((__atomic_load_n(un + f, __ATOMIC_RELAXED) & bad[f]) != bad[f])
+                atomicOr((unsigned long long*)(un + f), (unsigned long long)bad[f]);
         }
     }
-    return true;
 }
 
 // Horizontal step of iteration P.iter for the check row R and the 64*FPL
 // frames of the wave, reading beta from `src` (iteration 1: the channel LLRs
 // gathered from `mu`) and writing alpha to `dst` (which may be `src`: each
 // package belongs to one row).  RULE 0: sum-product (Eq. 3); RULE 1: learned
-// min-sum with the weights of P.nms_w.
-template <int DCMAX, int FPL, int RULE>
+// min-sum with the weights of P.nms_w.  SYN: with early stopping from
+// iteration 2 on, also test the row against iteration iter-1's packed
+// decisions; their loads are issued right after the message loads and the
+// flag update comes last, so the test adds no round trip before the work.
+template <int DCMAX, int FPL, int RULE, bool SYN = false>
 __device__ __forceinline__ void cn_row(const QCDesc& D, const BlockParams& P, const QCRow& R, int tile, int lane,
-                                       const float* src, const float* mu, float* dst, bool from_mu) {
+                                       const float* src, const float* mu, float* dst, bool from_mu,
+                                       int nvalid = 0) {
     constexpr int Gt = 64 * FPL;
     const size_t lane_off = (size_t)lane * FPL;
     const float* st = src + (size_t)tile * D.E * Gt + lane_off;
@@ -259,6 +250,20 @@ __device__ __forceinline__ void cn_row(const QCDesc& D, const BlockParams& P, co
         } else {
 #pragma unroll
             for (int f = 0; f < FPL; ++f) in[k][f] = 0.0f;
+        }
+    }
+    const bool syn = SYN && P.early && P.iter >= 2;
+    uint64_t par[FPL];
+#pragma unroll
+    for (int f = 0; f < FPL; ++f) par[f] = 0;
+    if (syn) {
+        const uint64_t* bt = P.bits + (size_t)tile * D.n * FPL;
+#pragma unroll
+        for (int k = 0; k < DCMAX; ++k) {
+            if (!R.valid(D, k)) continue;
+            const uint64_t* w = bt + (size_t)R.var(D, k) * FPL;
+#pragma unroll
+            for (int f = 0; f < FPL; ++f) par[f] ^= w[f];
         }
     }
     float outv[DCMAX][FPL];
@@ -289,6 +294,11 @@ __device__ __forceinline__ void cn_row(const QCDesc& D, const BlockParams& P, co
 #pragma unroll
     for (int k = 0; k < DCMAX; ++k)
         if (R.valid(D, k)) store_frames<FPL>(dt + (size_t)R.pkg(D, k) * Gt, outv[k]);
+    if (syn) {
+#pragma unroll
+        for (int f = 0; f < FPL; ++f) par[f] &= valid_word<FPL>(nvalid, f);
+        cn_publish_unsat<FPL>(P, tile, lane, par);
+    }
 }
 
 // Check-node pass of iteration P.iter (in place in P.msg; iteration 1 reads
@@ -303,8 +313,8 @@ __global__ void __launch_bounds__(kBlock) cn_block_kernel(const QCDesc D, const 
     if (tile >= P.tiles) return;
     const int nvalid = min(P.gamma - tile * Gt, Gt);
     const QCRow R(D, row);
-    if (!cn_prologue<DCMAX, FPL>(D, P, R, tile, lane, nvalid)) return;
-    cn_row<DCMAX, FPL, RULE>(D, P, R, tile, lane, P.msg, P.mu, P.msg, P.iter == 1);
+    if (!cn_tile_live<FPL>(P, tile)) return;
+    cn_row<DCMAX, FPL, RULE, true>(D, P, R, tile, lane, P.msg, P.mu, P.msg, P.iter == 1, nvalid);
 }
 
 // Frames of a tile frozen before iteration P.iter (bit set = frozen; padding

@@ -36,10 +36,10 @@
 
 namespace ldpc {
 
-constexpr int kPlanLayouts = 5;   // G8, G16, G32, G64, G64 with 4 frames per lane
+constexpr int kPlanLayouts = 6;   // G8, G16, G32, G64, G64 with 4 and with 2 frames per lane
 
 __host__ __device__ constexpr int layout_g(int l) { return l == 0 ? 8 : l == 1 ? 16 : l == 2 ? 32 : 64; }
-__host__ __device__ constexpr int layout_fpl(int l) { return l == 4 ? 4 : 1; }
+__host__ __device__ constexpr int layout_fpl(int l) { return l == 4 ? 4 : l == 5 ? 2 : 1; }
 
 struct PlanCode {
     QCDesc D;
@@ -94,7 +94,8 @@ __device__ __forceinline__ uint64_t plan_pick(const uint64_t (&a)[FPL], int i) {
         case 1: { constexpr int G = 16, FPL = 1; __VA_ARGS__; } break;        \
         case 2: { constexpr int G = 32, FPL = 1; __VA_ARGS__; } break;        \
         case 3: { constexpr int G = 64, FPL = 1; __VA_ARGS__; } break;        \
-        default: { constexpr int G = 64, FPL = 4; __VA_ARGS__; } break;       \
+        case 4: { constexpr int G = 64, FPL = 4; __VA_ARGS__; } break;        \
+        default: { constexpr int G = 64, FPL = 2; __VA_ARGS__; } break;       \
     }
 // row-weight classes of a plan (at most 24: one kernel serves every code, and
 // its register budget is that of the heaviest variant it contains)
@@ -120,7 +121,8 @@ __device__ __forceinline__ uint64_t plan_pick(const uint64_t (&a)[FPL], int i) {
 // Check-node pass of iteration S.iter for wave lw of code C (in place; the
 // first iteration gathers the channel LLRs).  With early stopping it first
 // skips tiles frozen by iteration iter-2 and ORs the syndrome of iteration
-// iter-1's decisions into unsat[iter-1].
+// iter-1's decisions into unsat[iter-1]; the decision words are loaded right
+// after the messages and the flag update comes after the stores.
 template <int DCMAX, int G, int FPL>
 __device__ __forceinline__ void plan_cn_body(const PlanCode& C, const PlanStep& S, int64_t lw, int lane) {
     constexpr int R = 64 / G;
@@ -141,39 +143,6 @@ __device__ __forceinline__ void plan_cn_body(const PlanCode& C, const PlanStep& 
     }
     const QCRow Rw(D, active ? row : 0);
     const int d = active ? Rw.d : 0;
-    if (S.early && S.iter >= 2) {
-        uint64_t par[FPL];
-#pragma unroll
-        for (int i = 0; i < FPL; ++i) par[i] = 0;
-        const uint64_t* bt = C.bits + (size_t)tile * D.n * FPL;
-#pragma unroll
-        for (int k = 0; k < DCMAX; ++k) {
-            if (k >= d) continue;
-            const uint64_t* w = bt + (size_t)Rw.var(D, k) * FPL;
-#pragma unroll
-            for (int i = 0; i < FPL; ++i) par[i] ^= w[i];
-        }
-        uint64_t* un = C.unsat + ((size_t)(S.iter - 1) * C.tiles + tile) * FPL;
-        if constexpr (G == 64) {
-#pragma unroll
-            for (int i = 0; i < FPL; ++i) {
-                const uint64_t bad = par[i] & valid_word<FPL>(nvalid, i);
-                if (bad && lane == i) {
-                    // a stale read can only miss bits: a redundant atomic at worst
-                    if ((__atomic_load_n(un + i, __ATOMIC_RELAXED) & bad) != bad)
-                        atomicOr((unsigned long long*)(un + i), (unsigned long long)bad);
-                }
-            }
-        } else {
-            uint64_t v = par[0] & valid_word<1>(nvalid, 0);
-#pragma unroll
-            for (int off = 32; off >= 1; off >>= 1) v |= __shfl_xor(v, off);
-            if (lane == 0 && v) {
-                if ((__atomic_load_n(un, __ATOMIC_RELAXED) & v) != v)
-                    atomicOr((unsigned long long*)un, (unsigned long long)v);
-            }
-        }
-    }
     const size_t lane_off = (G == 64) ? (size_t)lane * FPL : (size_t)f;
     float* mt = C.msg + (size_t)tile * D.E * Gt + lane_off;
     const float* ut = C.mu + (size_t)tile * D.n * Gt + lane_off;
@@ -188,11 +157,48 @@ __device__ __forceinline__ void plan_cn_body(const PlanCode& C, const PlanStep& 
             for (int i = 0; i < FPL; ++i) in[k][i] = 0.0f;
         }
     }
+    const bool syn = S.early && S.iter >= 2;
+    uint64_t par[FPL];
+#pragma unroll
+    for (int i = 0; i < FPL; ++i) par[i] = 0;
+    if (syn) {
+        const uint64_t* bt = C.bits + (size_t)tile * D.n * FPL;
+#pragma unroll
+        for (int k = 0; k < DCMAX; ++k) {
+            if (k >= d) continue;
+            const uint64_t* w = bt + (size_t)Rw.var(D, k) * FPL;
+#pragma unroll
+            for (int i = 0; i < FPL; ++i) par[i] ^= w[i];
+        }
+    }
     float out[DCMAX][FPL];
     sp_check<DCMAX, FPL>(in, d, out);
 #pragma unroll
     for (int k = 0; k < DCMAX; ++k)
         if (k < d) store_frames<FPL>(mt + (size_t)Rw.pkg(D, k) * Gt, out[k]);
+    if (syn) {
+        // a stale read of the flag word can only miss bits (it only gains bits
+        // during the pass): a redundant atomic at worst
+        uint64_t* un = C.unsat + ((size_t)(S.iter - 1) * C.tiles + tile) * FPL;
+        if constexpr (G == 64) {
+#pragma unroll
+            for (int i = 0; i < FPL; ++i) {
+                const uint64_t bad = par[i] & valid_word<FPL>(nvalid, i);
+                if (bad && lane == i) {
+                    if ((__atomic_load_n(un + i, __ATOMIC_RELAXED) & bad) != bad)
+                        atomicOr((unsigned long long*)(un + i), (unsigned long long)bad);
+                }
+            }
+        } else {
+            uint64_t v = par[0] & valid_word<1>(nvalid, 0);
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) v |= __shfl_xor(v, off);
+            if (lane == 0 && v) {
+                if ((__atomic_load_n(un, __ATOMIC_RELAXED) & v) != v)
+                    atomicOr((unsigned long long*)un, (unsigned long long)v);
+            }
+        }
+    }
 }
 
 // Variable-node pass of iteration S.iter for wave lw of code C: betas (not
@@ -294,7 +300,7 @@ __global__ void __launch_bounds__(kBlock) plan_cn_kernel(const PlanCode* __restr
     const PlanCode& C = codes[plan_find(codes, ncodes, wave, &PlanCode::cn0)];
     const int64_t lw = wave - C.cn0;
     if (lw >= (int64_t)C.tiles * C.cn_wpt) return;
-    PLAN_LAYOUT_SWITCH(C.layout, PLAN_DC_SWITCH(C.dcc, if constexpr (FPL == 1 || DC <= 6) {
+    PLAN_LAYOUT_SWITCH(C.layout, PLAN_DC_SWITCH(C.dcc, if constexpr (FPL == 1 || DC <= (FPL == 4 ? 6 : 12)) {
         plan_cn_body<DC, G, FPL>(C, S, lw, lane);
     }));
 }
@@ -362,6 +368,8 @@ __global__ void __launch_bounds__(kBlock) plan_syndrome_kernel(const PlanCode* _
     const int64_t t = gid - C.syn0;
     if (C.fpl == 4) {
         plan_syndrome_body<4>(C, S, t, threadIdx.x & 63);
+    } else if (C.fpl == 2) {
+        plan_syndrome_body<2>(C, S, t, threadIdx.x & 63);
     } else {
         plan_syndrome_body<1>(C, S, t, threadIdx.x & 63);
     }
@@ -479,7 +487,9 @@ int plan_dv_class(int d) {
 
 bool layout_allowed(const ldpc_graph* g, int l) {
     if (l < 0 || l >= kPlanLayouts) return false;
-    return layout_fpl(l) == 1 || (g->dc_max <= 6 && g->dv_max <= 8);
+    if (layout_fpl(l) == 4) return g->dc_max <= 6 && g->dv_max <= 8;
+    if (layout_fpl(l) == 2) return g->dc_max <= 12 && g->dv_max <= 8;
+    return true;
 }
 
 struct CodeRegion {
@@ -512,10 +522,9 @@ int default_layout(const ldpc_graph* g, int gamma) {
     if (gamma <= 8) return 0;
     if (gamma <= 16) return 1;
     if (gamma <= 32) return 2;
-    if (layout_allowed(g, 4)) {
-        const int base = (gamma + 63) / 64 * 64, pad4 = (gamma + 255) / 256 * 256;
-        if (pad4 * 8 <= base * 9) return 4;
-    }
+    const int base = (gamma + 63) / 64 * 64;
+    if (layout_allowed(g, 4) && (gamma + 255) / 256 * 256 * 8 <= base * 9) return 4;
+    if (layout_allowed(g, 5) && (gamma + 127) / 128 * 128 * 8 <= base * 9) return 5;
     return 3;
 }
 

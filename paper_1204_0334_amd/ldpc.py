@@ -29,8 +29,8 @@ _vp, _i32, _i64, _sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c
 
 OK, EINVAL, EWORKSPACE, EHIP, EUNSUPPORTED, ENOMEM = 0, -1, -2, -3, -4, -5
 GRAPH_QC, GRAPH_CONV = 0, 1
-LAYOUT_G8, LAYOUT_G16, LAYOUT_G32, LAYOUT_G64, LAYOUT_G64F4 = 0, 1, 2, 3, 4
-LAYOUT_NAMES = ["G8", "G16", "G32", "G64", "G64F4"]
+LAYOUT_G8, LAYOUT_G16, LAYOUT_G32, LAYOUT_G64, LAYOUT_G64F4, LAYOUT_G64F2 = 0, 1, 2, 3, 4, 5
+LAYOUT_NAMES = ["G8", "G16", "G32", "G64", "G64F4", "G64F2"]
 PLAN_MAX_CODES = 16
 TIMING_CLASSES = 21
 MAX_ITERS = 100000

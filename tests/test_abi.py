@@ -274,13 +274,18 @@ def test_plan_creation_and_layout_rules():
     gammas = [8, 12, 20, 64, 1024, 1024, 33]
     graphs = [g36, g36, g36, g36, g36, g39, g39]
     plan = ldpc.Plan(graphs, gammas, 20, early_stop=True)
-    want = [ldpc.LAYOUT_G8, ldpc.LAYOUT_G16, ldpc.LAYOUT_G32, ldpc.LAYOUT_G64, ldpc.LAYOUT_G64F4, ldpc.LAYOUT_G64,
+    want = [ldpc.LAYOUT_G8, ldpc.LAYOUT_G16, ldpc.LAYOUT_G32, ldpc.LAYOUT_G64, ldpc.LAYOUT_G64F4, ldpc.LAYOUT_G64F2,
             ldpc.LAYOUT_G64]
     assert [plan.layout(c) for c in range(len(graphs))] == want
     with pytest.raises(ldpc.LdpcError):
         plan.set_layout(5, ldpc.LAYOUT_G64F4)          # 3 x 9: row weight 9
     with pytest.raises(ldpc.LdpcError):
         plan.set_layout(7, ldpc.LAYOUT_G8)
+    plan.set_layout(5, ldpc.LAYOUT_G64F2)              # row weight 9 <= 12
+    wide18 = ldpc.Plan([ldpc.Graph.qc(synth.draw_qc_shifts(3, 18, 36, 4), 36)], [1024], 20)
+    assert wide18.layout(0) == ldpc.LAYOUT_G64
+    with pytest.raises(ldpc.LdpcError):
+        wide18.set_layout(0, ldpc.LAYOUT_G64F2)        # row weight 18
     plan.set_layout(4, ldpc.LAYOUT_G8)
     assert plan.layout(4) == ldpc.LAYOUT_G8
     plan.set_layout(4, -1)
