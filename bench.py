@@ -538,7 +538,21 @@ def nnms_report(args):
               f"{r['nms_untrained']['fer']:.3e} |")
 
 
-def cpu_baseline(shifts, p, llr, iters, sample):
+def host_cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(shifts, p, llr, iters, sample, single_sample=8):
+    """The FP64 reference decoder on the host: `sample` frames on all host
+    threads (OpenMP over frames) -- the value -- and `single_sample` frames on
+    one thread (the paper's serial-CPU analogue), same LLRs, no early stop."""
     import numpy as np
 
     import oracle
@@ -549,10 +563,72 @@ def cpu_baseline(shifts, p, llr, iters, sample):
     t0 = time.perf_counter()
     oracle.decode_block(H, x, iters, early_stop=False, nthreads=threads)
     dt = time.perf_counter() - t0
+    k = min(single_sample, sample)
+    t1 = time.perf_counter()
+    oracle.decode_block(H, np.ascontiguousarray(llr[:k]), iters, early_stop=False, nthreads=1)
+    d1 = time.perf_counter() - t1
     return {"value": round(sample * H.n / dt / 1e6, 4), "unit": "coded Mbit/s", "cores": threads,
             "kind": "oracle",
             "sample": f"{sample} of the {llr.shape[0]} frames, {iters} iterations, no early stop, FP64, "
-                      f"{threads} OpenMP threads over frames, {dt:.2f} s wall"}
+                      f"{threads} OpenMP threads over frames, {dt:.2f} s wall ({dt * threads:.1f} thread-s)",
+            "single_thread": {"value": round(k * H.n / d1 / 1e6, 4), "frames": k, "seconds": round(d1, 3),
+                              "ms_per_frame": round(d1 * 1e3 / k, 2)},
+            "host": {"model": host_cpu_model(), "logical_cpus": os.cpu_count()}}
+
+
+def early_stop_sweep(g, gamma, iters, points, steps=5):
+    """Throughput of the benchmark code with early stopping at each Eb/N0
+    (GPU channel, all-zero codeword: the decoder treats every codeword alike),
+    with the average iteration count."""
+    import torch
+
+    from paper_1204_0334_amd import fer, ldpc
+    dev = torch.device("cuda:0")
+    n = g.n
+    ws = ldpc.workspace(g, gamma, iters, 0, dev)
+    out = (torch.empty((gamma, n), dtype=torch.float32, device=dev),
+           torch.empty((gamma, n), dtype=torch.uint8, device=dev),
+           torch.empty((gamma,), dtype=torch.int32, device=dev),
+           torch.empty((gamma,), dtype=torch.uint8, device=dev))
+    rows = []
+    for k, e in enumerate(points):
+        llr = ldpc.awgn_llr(n, gamma, fer.ebn0_to_sigma2(e, g.info["design_rate"]), 900 + k, 0, device=dev)
+        ldpc.decode(g, llr, iters, True, out=out, ws=ws)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(steps):
+            ldpc.decode(g, llr, iters, True, out=out, ws=ws)
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / steps
+        rows.append({"ebn0_db": e, "coded_mbps": round(gamma * n / (ms * 1e-3) / 1e6, 1), "ms": round(ms, 4),
+                     "avg_iters": round(float(out[2].float().mean().item()), 3),
+                     "frames_converged": round(float(out[3].float().mean().item()), 4)})
+    return rows
+
+
+def gamma_control(g, llr_dev, iters, gamma, steps=5):
+    """The benchmark decode at a larger batch whose working set exceeds the
+    256 MB Infinity Cache (frames repeated from the benchmark batch)."""
+    import torch
+
+    from paper_1204_0334_amd import ldpc
+    dev = llr_dev.device
+    reps = (gamma + llr_dev.shape[0] - 1) // llr_dev.shape[0]
+    x = llr_dev.repeat(reps, 1)[:gamma].contiguous()
+    ws = ldpc.workspace(g, gamma, iters, 0, dev)
+    out = ldpc.decode(g, x, iters, False, ws=ws)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(steps):
+        ldpc.decode(g, x, iters, False, out=out, ws=ws)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / steps
+    del out, ws, x
+    return {"gamma": gamma, "ms_per_step": round(ms, 4), "coded_mbps": round(gamma * g.n / (ms * 1e-3) / 1e6, 1)}
 
 
 def main():
@@ -562,7 +638,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--gamma", type=int, default=1024, help="frames per step (1024 is the benchmark workload)")
     ap.add_argument("--iters", type=int, default=20)
-    ap.add_argument("--cpu-sample", type=int, default=96, help="frames decoded by the FP64 reference")
+    ap.add_argument("--cpu-sample", type=int, default=1024, help="frames decoded by the FP64 reference")
+    ap.add_argument("--no-extras", dest="extras", action="store_false",
+                    help="benchmark line: skip the early-stop sweep over Eb/N0 and the 4096-frame control")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--workload", default="qc36_p3060",
                     choices=["qc36_p3060", "cc36_p512", "cc36_p512_pipeline", "nnms_train_p3060", "mixed_plan"],
@@ -686,6 +764,8 @@ def main():
                    "points": [{"ebn0_db": r["ebn0_db"], "fer_learned_nms12": r["learned_nms"]["fer"],
                                "fer_sp30": r["sp30"]["fer"], "avg_iters_learned": r["learned_nms"]["avg_iters"],
                                "avg_iters_sp30": r["sp30"]["avg_iters"]} for r in learned["points"]]}
+    sweep = early_stop_sweep(g, gamma, iters, [1.0, 1.25, 1.5, 1.75, 2.0, 2.25, 2.5]) if args.extras else None
+    control = gamma_control(g, llr, iters, 4096) if args.extras else None
     cpu = None if args.no_cpu else cpu_baseline(shifts, p, llr_h, iters, min(args.cpu_sample, gamma))
     line = {
         "metric": METRIC, "value": round(value, 2), "unit": "coded Mbit/s", "n_gpus": 1, "steps": args.steps,
@@ -698,6 +778,8 @@ def main():
                    "frames_converged": round(conv_rate, 4)},
         "roofline": roofline, "cpu_baseline": cpu, "kernels": kernels,
         "fer_learned_vs_plain": learned,
+        "early_stop_per_ebn0": sweep,
+        "gamma_control": control,
     }
     print(json.dumps(line), flush=True)
 
