@@ -11,6 +11,9 @@ library (`ldpc_nms_train_forward`, `ldpc_nms_train_backward`,
 """
 from __future__ import annotations
 
+import json
+import os
+
 import numpy as np
 import torch
 
@@ -51,12 +54,19 @@ def initial_weights(T: int, J: int, scale: float = 0.8, offset: float = 0.0, dev
 
 def train(g: ldpc.Graph, T: int = 12, ckpt_every: int = 4, frames: int = 1 << 20, batch: int = 1024,
           ebn0_range=(1.0, 2.5), chunk: int = 64, lr: float = 0.01, seed: int = 7, init=None,
-          loss_weights=None, log_every: int = 0, device=None):
+          loss_weights=None, log_every: int = 0, device=None, checkpoint_path: str | None = None,
+          checkpoint_every: int = 64):
     """Adam on sum_t loss_weights[t] * (BCE of iteration t) (default: the
     mean over iterations), batches of `batch` fresh frames, each run of
     `chunk` frames at an Eb/N0 drawn uniformly from `ebn0_range`.  Scales and
     offsets are kept >= 0 after every step.  Returns (weights [T, J, 2],
-    history of (frames, loss))."""
+    history of (frames, loss)).
+
+    With `checkpoint_path`, the weights, the Adam state, the step count, the
+    Eb/N0 generator's state and the history are saved there every
+    `checkpoint_every` steps and at the end; an existing checkpoint is
+    resumed (the frames are counter-based, so a resumed run sees the same
+    frames as an uninterrupted one)."""
     dev = torch.device(device or "cuda:0")
     info = g.info
     n, J, rate = info["n"], info["J"], info["design_rate"]
@@ -71,7 +81,23 @@ def train(g: ldpc.Graph, T: int = 12, ckpt_every: int = 4, frames: int = 1 << 20
         torch.as_tensor(loss_weights, dtype=torch.float32, device=dev)
     history = []
     steps = max(frames // batch, 1)
-    for step in range(steps):
+    first = 0
+    if checkpoint_path and os.path.exists(checkpoint_path):
+        ck = torch.load(checkpoint_path, map_location=dev, weights_only=True)
+        with torch.no_grad():
+            W.copy_(ck["weights"])
+        opt.load_state_dict(ck["adam"])
+        rng.bit_generator.state = json.loads(ck["rng"])
+        history = [tuple(h) for h in ck["history"]]
+        first = int(ck["step"])
+
+    def save(step_done):
+        tmp = checkpoint_path + ".tmp"
+        torch.save({"weights": W.detach().clone(), "adam": opt.state_dict(), "step": step_done,
+                    "rng": json.dumps(rng.bit_generator.state), "history": [list(h) for h in history]}, tmp)
+        os.replace(tmp, checkpoint_path)
+
+    for step in range(first, steps):
         frame0 = step * batch
         for c in range(batch // chunk):
             sigma2 = fer.ebn0_to_sigma2(float(rng.uniform(*ebn0_range)), rate)
@@ -85,6 +111,8 @@ def train(g: ldpc.Graph, T: int = 12, ckpt_every: int = 4, frames: int = 1 << 20
             W.clamp_(min=0.0)
         if log_every and (step % log_every == 0 or step == steps - 1):
             history.append((frame0 + batch, float(loss.detach())))
+        if checkpoint_path and ((step + 1) % checkpoint_every == 0 or step == steps - 1):
+            save(step + 1)
     return W.detach(), history
 
 

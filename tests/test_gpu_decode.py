@@ -427,3 +427,26 @@ def test_fer_loop_pipeline_decoder():
     close = (np.abs(ref["post"]) < 1e-3).any(1)
     errs = ref["bits"].sum(1)
     assert int(((errs > 0) & ~close).sum()) <= r["frame_errors"] <= int(((errs > 0) | close).sum())
+
+
+def test_fer_simulation_resumes_exactly(tmp_path):
+    # an interrupted FER run resumed from its last checkpoint gives the same
+    # counters as an uninterrupted one (counter-based generator)
+    from paper_1204_0334_amd import fer
+    a = synth.draw_qc_shifts(3, 6, 64, 1)
+    g = ldpc.Graph.qc(a, 64)
+    print("[gpu] fer resume", flush=True)
+    kw = dict(gamma=256, iters=10, early_stop=True, seed=5, min_frame_errors=1 << 30, max_frames=8 * 256)
+    full = fer.simulate(g, 2.0, **kw)
+    states = []
+    fer.simulate(g, 2.0, checkpoint=states.append, checkpoint_every=3, **dict(kw, max_frames=3 * 256))
+    assert states[-1]["frames"] == 3 * 256
+    rest = fer.simulate(g, 2.0, resume=states[-1], **kw)
+    for k in ("frames", "frame_errors", "bit_errors", "avg_iters"):
+        assert rest[k] == full[k], k
+    # the JSONL sweep skips finished points and resumes unfinished ones
+    log = str(tmp_path / "sweep.jsonl")
+    r1 = fer.sweep(g, [2.0, 2.5], log, key="p64", **kw)
+    r2 = fer.sweep(g, [2.0, 2.5], log, key="p64", **kw)
+    assert [x["frame_errors"] for x in r1] == [x["frame_errors"] for x in r2]
+    assert r1[0]["frame_errors"] == full["frame_errors"]

@@ -216,3 +216,20 @@ def test_training_improves_on_plain_min_sum():
     base = nnms.compare_fer(g, plain, [2.5], sp_iters=20, frames=8192, gamma=1024)[0]["learned"]
     assert learned["frames"] == base["frames"] == 8192
     assert learned["fer"] < base["fer"] - 0.05
+
+
+def test_training_resumes_from_checkpoint(tmp_path):
+    # 6 steps in one run equal 3 steps, a checkpoint, and 3 resumed steps
+    a = synth.draw_qc_shifts(3, 6, 64, 1)
+    g = ldpc.Graph.qc(a, 64)
+    T = 4
+    init = nnms.initial_weights(T, 3, 0.8, 0.1, device=DEV)
+    print("[gpu] nnms.train checkpoint", flush=True)
+    W_full, h_full = nnms.train(g, T=T, ckpt_every=2, frames=6 * 512, batch=512, lr=0.02, init=init, log_every=1)
+    path = str(tmp_path / "nnms.pt")
+    nnms.train(g, T=T, ckpt_every=2, frames=3 * 512, batch=512, lr=0.02, init=init, log_every=1,
+               checkpoint_path=path, checkpoint_every=2)
+    W_res, h_res = nnms.train(g, T=T, ckpt_every=2, frames=6 * 512, batch=512, lr=0.02, init=init, log_every=1,
+                              checkpoint_path=path, checkpoint_every=2)
+    assert torch.equal(W_full, W_res)
+    assert h_full == h_res
