@@ -697,7 +697,8 @@ def main():
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this decoder runs on a single MI355X; a batch of frames "
-              "would shard over GPUs with no exchange (see DESIGN.md), but no multi-GPU run is made.",
+              "would shard over GPUs with no exchange during decoding (each GPU takes a share of the frames), "
+              "but no multi-GPU run is made.",
               file=sys.stderr)
         sys.exit(2)
 
