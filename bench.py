@@ -417,7 +417,7 @@ def bench_plan(args):
     ws = plan.workspace(dev)
     outs = plan.outputs(dev)
     tuned_ms = plan.autotune(llrs, outs, ws, trials=3)
-    layouts = [ldpc.LAYOUT_NAMES[plan.layout(c)] for c in range(len(graphs))]
+    layouts = [ldpc.layout_name(plan.layout(c)) for c in range(len(graphs))]
     plan.capture(llrs, outs, ws)
     ms = timed(plan.replay, args.steps, args.warmup)
     conv = sum(int(o[3].sum()) for o in outs) / sum(gammas)

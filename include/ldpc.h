@@ -240,6 +240,9 @@ ldpc_status ldpc_nms_train_backward(const ldpc_graph* g, int32_t gamma, int32_t 
  *     <= 6 and column weight <= 8 only);
  *   LDPC_LAYOUT_G64F2: tiles of 128 frames, 2 frames per lane (row weight
  *     <= 12 and column weight <= 8 only).
+ * OR-ing LDPC_LAYOUT_VN2 or LDPC_LAYOUT_VN4 into a one-frame-per-lane
+ * layout (G8 .. G64, column weight <= 8) makes each variable-node wavefront
+ * handle 2 or 4 groups of variables (fewer, longer waves).
  * Graphs in a plan have row weight <= 24 (EUNSUPPORTED otherwise): one
  * kernel serves all codes and carries the registers of its heaviest case.
  * The default is the smallest tile >= gamma (for large batches G64F4, else
@@ -267,7 +270,7 @@ ldpc_status ldpc_nms_train_backward(const ldpc_graph* g, int32_t gamma, int32_t 
  * used by anything else between capture and replay.
  *
  * ldpc_plan_autotune: one pass of coordinate descent over the codes: each
- * code in turn tries every other allowed layout (tiles no larger than the
+ * code in turn tries every other allowed layout value (tiles no larger than the
  * next power of two above its batch) while the others stay fixed; each
  * candidate is timed over `trials` whole decodes of the plan (after one
  * warm-up) on the given buffers (outputs are overwritten); the fastest is
@@ -280,7 +283,7 @@ ldpc_status ldpc_nms_train_backward(const ldpc_graph* g, int32_t gamma, int32_t 
 typedef struct ldpc_plan ldpc_plan;
 #define LDPC_PLAN_MAX_CODES 16
 enum { LDPC_LAYOUT_G8 = 0, LDPC_LAYOUT_G16 = 1, LDPC_LAYOUT_G32 = 2, LDPC_LAYOUT_G64 = 3, LDPC_LAYOUT_G64F4 = 4,
-       LDPC_LAYOUT_G64F2 = 5 };
+       LDPC_LAYOUT_G64F2 = 5, LDPC_LAYOUT_VN2 = 16, LDPC_LAYOUT_VN4 = 32 };
 
 ldpc_status ldpc_plan_create(const ldpc_graph* const* graphs, const int32_t* gammas, int32_t ncodes,
                              int32_t max_iters, int32_t early_stop, ldpc_plan** out);

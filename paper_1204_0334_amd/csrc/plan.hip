@@ -38,8 +38,15 @@ namespace ldpc {
 
 constexpr int kPlanLayouts = 6;   // G8, G16, G32, G64, G64 with 4 and with 2 frames per lane
 
-__host__ __device__ constexpr int layout_g(int l) { return l == 0 ? 8 : l == 1 ? 16 : l == 2 ? 32 : 64; }
-__host__ __device__ constexpr int layout_fpl(int l) { return l == 4 ? 4 : l == 5 ? 2 : 1; }
+// A code's layout value: base lane layout (bits 0-3) and log2 of the number of
+// variable groups each variable-node wave handles (bits 4-5; one frame per
+// lane only).
+__host__ __device__ constexpr int layout_base(int l) { return l & 15; }
+__host__ __device__ constexpr int layout_vpw(int l) { return 1 << ((l >> 4) & 3); }
+__host__ __device__ constexpr int layout_g(int l) {
+    return layout_base(l) == 0 ? 8 : layout_base(l) == 1 ? 16 : layout_base(l) == 2 ? 32 : 64;
+}
+__host__ __device__ constexpr int layout_fpl(int l) { return layout_base(l) == 4 ? 4 : layout_base(l) == 5 ? 2 : 1; }
 
 struct PlanCode {
     QCDesc D;
@@ -55,12 +62,13 @@ struct PlanCode {
     int32_t* iters;       // caller, [gamma] or NULL
     uint8_t* converged;   // caller, [gamma] or NULL
     int64_t flag_words;   // (max_iters+1) * tiles * FPL
-    int gamma, tiles, layout, Gt, fpl, dcc, dvc;
+    int gamma, tiles, layout, Gt, fpl, dcc, dvc;   // layout: the base lane layout
     int cn_wpt, vn_wpt;   // waves per tile in the check / variable launches
     int io_vchunks, io_fchunks;
     int64_t cn0, vn0;     // first wave of the code in the check / variable launches
     int64_t syn0, st0;    // first thread in the syndrome / frame-status launches (multiples of 64)
     int64_t io0;          // first block in the ingest / output launches
+    int vpw;              // variable-node launch: groups of R variables per wave (1, 2 or 4)
 };
 
 struct PlanStep {
@@ -204,8 +212,9 @@ __device__ __forceinline__ void plan_cn_body(const PlanCode& C, const PlanStep& 
 // Variable-node pass of iteration S.iter for wave lw of code C: betas (not
 // after the last iteration), and with early stopping or at the last
 // iteration the packed decisions and the posterior of the frames still
-// running (frozen frames keep theirs).
-template <int DVMAX, int G, int FPL>
+// running (frozen frames keep theirs).  A wave handles V groups of R
+// variables; all their loads are issued before the first result is stored.
+template <int DVMAX, int G, int FPL, int V>
 __device__ __forceinline__ void plan_vn_body(const PlanCode& C, const PlanStep& S, int64_t lw, int lane) {
     constexpr int R = 64 / G;
     constexpr int Gt = G * FPL;
@@ -213,8 +222,6 @@ __device__ __forceinline__ void plan_vn_body(const PlanCode& C, const PlanStep& 
     const int tile = (int)(lw / C.vn_wpt);
     const int rw = (int)(lw - (int64_t)tile * C.vn_wpt);
     const int r = lane / G, f = lane % G;
-    const int var = rw * R + r;
-    const bool active = var < D.n;
     const int nvalid = min(C.gamma - tile * Gt, Gt);
     // frames frozen before this iteration (padding frames count as frozen)
     uint64_t frz[FPL];
@@ -233,67 +240,77 @@ __device__ __forceinline__ void plan_vn_body(const PlanCode& C, const PlanStep& 
     if (S.early && rw == 0 && lane < FPL)
         C.frozen[((size_t)(S.iter - 1) * C.tiles + tile) * FPL + lane] = plan_pick<FPL>(frz, lane);
     if (S.early && all) return;
-    const QCCol Cc(D, active ? var : 0);
-    const int dv = active ? Cc.d : 0;
     const size_t lane_off = (G == 64) ? (size_t)lane * FPL : (size_t)f;
     float* mt = C.msg + (size_t)tile * D.E * Gt + lane_off;
-    float mu[FPL];
-    if (active) {
-        load_frames<FPL>(C.mu + ((size_t)tile * D.n + var) * Gt + lane_off, mu);
-    } else {
+    int var[V], dv[V];
+    bool active[V];
+    float mu[V][FPL], a[V][DVMAX][FPL];
 #pragma unroll
-        for (int i = 0; i < FPL; ++i) mu[i] = 0.0f;
-    }
-    float a[DVMAX][FPL];
-#pragma unroll
-    for (int k = 0; k < DVMAX; ++k) {
-        if (k < dv) {
-            load_frames<FPL>(mt + (size_t)Cc.pkg(D, k) * Gt, a[k]);
+    for (int v = 0; v < V; ++v) {
+        var[v] = (rw * V + v) * R + r;
+        active[v] = var[v] < D.n;
+        const QCCol Cc(D, active[v] ? var[v] : 0);
+        dv[v] = active[v] ? Cc.d : 0;
+        if (active[v]) {
+            load_frames<FPL>(C.mu + ((size_t)tile * D.n + var[v]) * Gt + lane_off, mu[v]);
         } else {
 #pragma unroll
-            for (int i = 0; i < FPL; ++i) a[k][i] = 0.0f;
+            for (int i = 0; i < FPL; ++i) mu[v][i] = 0.0f;
         }
-    }
-    float b[DVMAX][FPL], L[FPL];
-    sp_variable<DVMAX, FPL>(mu, a, b, L);
-    if (!S.last) {
 #pragma unroll
-        for (int k = 0; k < DVMAX; ++k)
-            if (k < dv) store_frames<FPL>(mt + (size_t)Cc.pkg(D, k) * Gt, b[k]);
-    }
-    if (S.early || S.last) {
-        uint64_t* bw = C.bits + ((size_t)tile * D.n + var) * FPL;
-        if constexpr (G == 64) {
-            // word i, bit j <-> frame FPL * j + i
-            uint64_t mine = 0;
+        for (int k = 0; k < DVMAX; ++k) {
+            if (k < dv[v]) {
+                load_frames<FPL>(mt + (size_t)Cc.pkg(D, k) * Gt, a[v][k]);
+            } else {
 #pragma unroll
-            for (int i = 0; i < FPL; ++i) {
-                uint64_t w = __ballot(L[i] < 0.0f);
-                if (any) w = (w & ~frz[i]) | (bw[i] & frz[i]);
-                if (lane == i) mine = w;
-            }
-            if (lane < FPL) bw[lane] = mine;
-        } else {
-            // bits r*G .. r*G+G-1 of the ballot are the G frames of variable r
-            const uint64_t gmask = (1ull << G) - 1ull;
-            uint64_t w = (__ballot(active && L[0] < 0.0f) >> (r * G)) & gmask;
-            if (active && f == 0) {
-                if (any) w = (w & ~frz[0]) | (bw[0] & frz[0]);
-                bw[0] = w;
+                for (int i = 0; i < FPL; ++i) a[v][k][i] = 0.0f;
             }
         }
-        if (active) {
-            float* pw = C.postw + ((size_t)tile * D.n + var) * Gt + lane_off;
+    }
 #pragma unroll
-            for (int i = 0; i < FPL; ++i) {
-                const int bit = (G == 64) ? lane : f;   // frame lane_off + i: word i, bit `bit`
-                if (!((frz[i] >> bit) & 1ull)) pw[i] = clip30(L[i]);
+    for (int v = 0; v < V; ++v) {
+        const QCCol Cc(D, active[v] ? var[v] : 0);
+        float b[DVMAX][FPL], L[FPL];
+        sp_variable<DVMAX, FPL>(mu[v], a[v], b, L);
+        if (!S.last) {
+#pragma unroll
+            for (int k = 0; k < DVMAX; ++k)
+                if (k < dv[v]) store_frames<FPL>(mt + (size_t)Cc.pkg(D, k) * Gt, b[k]);
+        }
+        if (S.early || S.last) {
+            uint64_t* bw = C.bits + ((size_t)tile * D.n + (active[v] ? var[v] : 0)) * FPL;
+            if constexpr (G == 64) {
+                // word i, bit j <-> frame FPL * j + i
+                uint64_t mine = 0;
+#pragma unroll
+                for (int i = 0; i < FPL; ++i) {
+                    uint64_t w = __ballot(L[i] < 0.0f);
+                    if (any) w = (w & ~frz[i]) | (bw[i] & frz[i]);
+                    if (lane == i) mine = w;
+                }
+                if (active[v] && lane < FPL) bw[lane] = mine;
+            } else {
+                // bits r*G .. r*G+G-1 of the ballot are the G frames of variable r
+                const uint64_t gmask = (1ull << G) - 1ull;
+                uint64_t w = (__ballot(active[v] && L[0] < 0.0f) >> (r * G)) & gmask;
+                if (active[v] && f == 0) {
+                    if (any) w = (w & ~frz[0]) | (bw[0] & frz[0]);
+                    bw[0] = w;
+                }
+            }
+            if (active[v]) {
+                float* pw = C.postw + ((size_t)tile * D.n + var[v]) * Gt + lane_off;
+#pragma unroll
+                for (int i = 0; i < FPL; ++i) {
+                    const int bit = (G == 64) ? lane : f;   // frame lane_off + i: word i, bit `bit`
+                    if (!((frz[i] >> bit) & 1ull)) pw[i] = clip30(L[i]);
+                }
             }
         }
     }
 }
 
-__global__ void __launch_bounds__(kBlock) plan_cn_kernel(const PlanCode* __restrict__ codes, int ncodes,
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) plan_cn_kernel(const PlanCode* __restrict__ codes, int ncodes,
                                                          PlanStep S) {
     const int lane = threadIdx.x & 63;
     const int64_t wave = (int64_t)blockIdx.x * kWavesPerBlock + wave_in_block();
@@ -312,9 +329,19 @@ __global__ void __launch_bounds__(kBlock) plan_vn_kernel(const PlanCode* __restr
     const PlanCode& C = codes[plan_find(codes, ncodes, wave, &PlanCode::vn0)];
     const int64_t lw = wave - C.vn0;
     if (lw >= (int64_t)C.tiles * C.vn_wpt) return;
-    PLAN_LAYOUT_SWITCH(C.layout, PLAN_DV_SWITCH(C.dvc, if constexpr (FPL == 1 || DV <= 8) {
-        plan_vn_body<DV, G, FPL>(C, S, lw, lane);
-    }));
+    if (C.vpw == 1) {
+        PLAN_LAYOUT_SWITCH(C.layout, PLAN_DV_SWITCH(C.dvc, if constexpr (FPL == 1 || DV <= 8) {
+            plan_vn_body<DV, G, FPL, 1>(C, S, lw, lane);
+        }));
+    } else if (C.vpw == 2) {
+        PLAN_LAYOUT_SWITCH(C.layout, PLAN_DV_SWITCH(C.dvc, if constexpr (FPL == 1 && DV <= 8) {
+            plan_vn_body<DV, G, FPL, 2>(C, S, lw, lane);
+        }));
+    } else {
+        PLAN_LAYOUT_SWITCH(C.layout, PLAN_DV_SWITCH(C.dvc, if constexpr (FPL == 1 && DV <= 8) {
+            plan_vn_body<DV, G, FPL, 4>(C, S, lw, lane);
+        }));
+    }
 }
 
 // Syndrome of the final decisions into unsat[max_iters]: one thread per
@@ -486,7 +513,8 @@ int plan_dv_class(int d) {
 }
 
 bool layout_allowed(const ldpc_graph* g, int l) {
-    if (l < 0 || l >= kPlanLayouts) return false;
+    if (l < 0 || l >= 64 || layout_base(l) >= kPlanLayouts || ((l >> 4) & 3) == 3) return false;
+    if (layout_vpw(l) > 1 && (layout_fpl(l) != 1 || g->dv_max > 8)) return false;
     if (layout_fpl(l) == 4) return g->dc_max <= 6 && g->dv_max <= 8;
     if (layout_fpl(l) == 2) return g->dc_max <= 12 && g->dv_max <= 8;
     return true;
@@ -597,14 +625,15 @@ void build_table(ldpc_plan* P, const PlanBuffers& B, char* ws) {
         T.flag_words = R.flag_words;
         T.gamma = P->gammas[c];
         T.tiles = R.tiles;
-        T.layout = l;
+        T.layout = layout_base(l);
         T.Gt = R.Gt;
         T.fpl = layout_fpl(l);
         T.dcc = plan_dc_class(g->dc_max);
         T.dvc = plan_dv_class(g->dv_max);
         const int rows_per_wave = 64 / layout_g(l);
+        T.vpw = layout_vpw(l);
         T.cn_wpt = (g->m + rows_per_wave - 1) / rows_per_wave;
-        T.vn_wpt = (g->n + rows_per_wave - 1) / rows_per_wave;
+        T.vn_wpt = (g->n + rows_per_wave * T.vpw - 1) / (rows_per_wave * T.vpw);
         T.io_vchunks = (g->n + 63) / 64;
         T.io_fchunks = (R.tiles * R.Gt + 63) / 64;
         T.cn0 = cn;
@@ -858,7 +887,7 @@ ldpc_status ldpc_plan_autotune(ldpc_plan* P, const float* const* llr, float* con
     for (int c = 0; c < P->ncodes && status == LDPC_OK; ++c) {
         const int start = P->layouts[c];
         int keep = start;
-        for (int l = 0; l < kPlanLayouts && status == LDPC_OK; ++l) {
+        for (int l = 0; l < 48 && status == LDPC_OK; ++l) {
             if (l == start || !layout_allowed(P->graphs[c], l)) continue;
             if (layout_g(l) > 8 && layout_g(l) / 2 >= P->gammas[c]) continue;   // G at most the next power of two
             P->layouts[c] = l;

@@ -286,6 +286,11 @@ def test_plan_creation_and_layout_rules():
     assert wide18.layout(0) == ldpc.LAYOUT_G64
     with pytest.raises(ldpc.LdpcError):
         wide18.set_layout(0, ldpc.LAYOUT_G64F2)        # row weight 18
+    plan.set_layout(0, ldpc.LAYOUT_G8 | ldpc.LAYOUT_VN4)
+    assert plan.layout(0) == 32 and ldpc.layout_name(plan.layout(0)) == "G8/VN4"
+    for bad in (ldpc.LAYOUT_G64F4 | ldpc.LAYOUT_VN2, 48, 6, -2):
+        with pytest.raises(ldpc.LdpcError):
+            plan.set_layout(4, bad)
     plan.set_layout(4, ldpc.LAYOUT_G8)
     assert plan.layout(4) == ldpc.LAYOUT_G8
     plan.set_layout(4, -1)

@@ -60,28 +60,29 @@ def test_every_layout_matches_single_code_decoder():
     gammas = [c["gamma"] for c in RAGGED]
     refs = single_code(graphs, llrs, 12, True)
     ws = None
-    for layout in range(6):
+    for layout in list(range(6)) + [ldpc.LAYOUT_G8 | ldpc.LAYOUT_VN2, ldpc.LAYOUT_G32 | ldpc.LAYOUT_VN4,
+                                     ldpc.LAYOUT_G64 | ldpc.LAYOUT_VN2, ldpc.LAYOUT_G64 | ldpc.LAYOUT_VN4]:
         plan = ldpc.Plan(graphs, gammas, 12, early_stop=True)
         for c in range(len(graphs)):
             try:
                 plan.set_layout(c, layout)
             except ldpc.LdpcError:
                 pass                       # 2 or 4 frames per lane where rows are too heavy
-        print(f"[gpu] ragged plan layout={ldpc.LAYOUT_NAMES[layout]}", flush=True)
+        print(f"[gpu] ragged plan layout={ldpc.layout_name(layout)}", flush=True)
         ws = plan.workspace(DEV) if ws is None else ws
-        assert_same(plan.decode(llrs, ws=ws), refs, f"layout {ldpc.LAYOUT_NAMES[layout]}")
+        assert_same(plan.decode(llrs, ws=ws), refs, f"layout {ldpc.layout_name(layout)}")
 
 
 def test_fixed_iterations_every_layout():
     graphs, llrs = make_case(RAGGED[:5], 3000)
     gammas = [c["gamma"] for c in RAGGED[:5]]
     refs = single_code(graphs, llrs, 3, False)
-    for layout in (0, 2, 3):
+    for layout in (0, 2, 3, ldpc.LAYOUT_G64 | ldpc.LAYOUT_VN4):
         plan = ldpc.Plan(graphs, gammas, 3, early_stop=False)
         for c in range(len(graphs)):
             plan.set_layout(c, layout)
-        print(f"[gpu] fixed-iteration plan layout={ldpc.LAYOUT_NAMES[layout]}", flush=True)
-        assert_same(plan.decode(llrs), refs, f"3 iterations, layout {ldpc.LAYOUT_NAMES[layout]}")
+        print(f"[gpu] fixed-iteration plan layout={ldpc.layout_name(layout)}", flush=True)
+        assert_same(plan.decode(llrs), refs, f"3 iterations, layout {ldpc.layout_name(layout)}")
 
 
 def test_plan_code_against_fp64_reference():
@@ -146,7 +147,8 @@ def test_autotune_keeps_results():
     assert best > 0
     for c, g in enumerate(graphs):
         l = plan.layout(c)
-        assert 0 <= l <= 5 and (l != ldpc.LAYOUT_G64F4 or g.info["dc_max"] <= 6)
-        assert l != ldpc.LAYOUT_G64F2 or g.info["dc_max"] <= 12
-        assert ldpc.LAYOUT_NAMES[l] in ldpc.LAYOUT_NAMES
+        base = l & 15
+        assert 0 <= base <= 5 and (base != ldpc.LAYOUT_G64F4 or g.info["dc_max"] <= 6)
+        assert base != ldpc.LAYOUT_G64F2 or g.info["dc_max"] <= 12
+        assert (l >> 4) == 0 or base in (0, 1, 2, 3)
     assert_same(plan.decode(llrs, outs=outs, ws=ws), single_code(graphs, llrs, 20, True), "after autotune")
