@@ -242,7 +242,9 @@ ldpc_status ldpc_nms_train_backward(const ldpc_graph* g, int32_t gamma, int32_t 
  *     <= 12 and column weight <= 8 only).
  * OR-ing LDPC_LAYOUT_VN2 or LDPC_LAYOUT_VN4 into a one-frame-per-lane
  * layout (G8 .. G64, column weight <= 8) makes each variable-node wavefront
- * handle 2 or 4 groups of variables (fewer, longer waves).
+ * handle 2 or 4 groups of variables (fewer, longer waves); LDPC_LAYOUT_CN2
+ * (row weight <= 8) or LDPC_LAYOUT_CN4 (row weight <= 6) does the same for
+ * the check-node wavefronts.
  * Graphs in a plan have row weight <= 24 (EUNSUPPORTED otherwise): one
  * kernel serves all codes and carries the registers of its heaviest case.
  * The default is the smallest tile >= gamma (for large batches G64F4, else
@@ -283,7 +285,8 @@ ldpc_status ldpc_nms_train_backward(const ldpc_graph* g, int32_t gamma, int32_t 
 typedef struct ldpc_plan ldpc_plan;
 #define LDPC_PLAN_MAX_CODES 16
 enum { LDPC_LAYOUT_G8 = 0, LDPC_LAYOUT_G16 = 1, LDPC_LAYOUT_G32 = 2, LDPC_LAYOUT_G64 = 3, LDPC_LAYOUT_G64F4 = 4,
-       LDPC_LAYOUT_G64F2 = 5, LDPC_LAYOUT_VN2 = 16, LDPC_LAYOUT_VN4 = 32 };
+       LDPC_LAYOUT_G64F2 = 5, LDPC_LAYOUT_VN2 = 16, LDPC_LAYOUT_VN4 = 32, LDPC_LAYOUT_CN2 = 64,
+       LDPC_LAYOUT_CN4 = 128 };
 
 ldpc_status ldpc_plan_create(const ldpc_graph* const* graphs, const int32_t* gammas, int32_t ncodes,
                              int32_t max_iters, int32_t early_stop, ldpc_plan** out);

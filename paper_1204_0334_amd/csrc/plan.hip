@@ -38,11 +38,12 @@ namespace ldpc {
 
 constexpr int kPlanLayouts = 6;   // G8, G16, G32, G64, G64 with 4 and with 2 frames per lane
 
-// A code's layout value: base lane layout (bits 0-3) and log2 of the number of
-// variable groups each variable-node wave handles (bits 4-5; one frame per
-// lane only).
+// A code's layout value: base lane layout (bits 0-3), log2 of the number of
+// variable groups each variable-node wave handles (bits 4-5) and of row groups
+// per check-node wave (bits 6-7); groups only with one frame per lane.
 __host__ __device__ constexpr int layout_base(int l) { return l & 15; }
 __host__ __device__ constexpr int layout_vpw(int l) { return 1 << ((l >> 4) & 3); }
+__host__ __device__ constexpr int layout_cpw(int l) { return 1 << ((l >> 6) & 3); }
 __host__ __device__ constexpr int layout_g(int l) {
     return layout_base(l) == 0 ? 8 : layout_base(l) == 1 ? 16 : layout_base(l) == 2 ? 32 : 64;
 }
@@ -69,6 +70,7 @@ struct PlanCode {
     int64_t syn0, st0;    // first thread in the syndrome / frame-status launches (multiples of 64)
     int64_t io0;          // first block in the ingest / output launches
     int vpw;              // variable-node launch: groups of R variables per wave (1, 2 or 4)
+    int cpw;              // check-node launch: groups of R rows per wave (1, 2 or 4)
 };
 
 struct PlanStep {
@@ -131,7 +133,7 @@ __device__ __forceinline__ uint64_t plan_pick(const uint64_t (&a)[FPL], int i) {
 // skips tiles frozen by iteration iter-2 and ORs the syndrome of iteration
 // iter-1's decisions into unsat[iter-1]; the decision words are loaded right
 // after the messages and the flag update comes after the stores.
-template <int DCMAX, int G, int FPL>
+template <int DCMAX, int G, int FPL, int V>
 __device__ __forceinline__ void plan_cn_body(const PlanCode& C, const PlanStep& S, int64_t lw, int lane) {
     constexpr int R = 64 / G;
     constexpr int Gt = G * FPL;
@@ -139,8 +141,6 @@ __device__ __forceinline__ void plan_cn_body(const PlanCode& C, const PlanStep& 
     const int tile = (int)(lw / C.cn_wpt);
     const int rw = (int)(lw - (int64_t)tile * C.cn_wpt);
     const int r = lane / G, f = lane % G;
-    const int row = rw * R + r;
-    const bool active = row < D.m;
     const int nvalid = min(C.gamma - tile * Gt, Gt);
     if (S.early && S.iter >= 3) {
         const uint64_t* fz = C.frozen + ((size_t)(S.iter - 2) * C.tiles + tile) * FPL;
@@ -149,22 +149,29 @@ __device__ __forceinline__ void plan_cn_body(const PlanCode& C, const PlanStep& 
         for (int i = 0; i < FPL; ++i) all = all && (fz[i] == ~0ull);
         if (all) return;
     }
-    const QCRow Rw(D, active ? row : 0);
-    const int d = active ? Rw.d : 0;
     const size_t lane_off = (G == 64) ? (size_t)lane * FPL : (size_t)f;
     float* mt = C.msg + (size_t)tile * D.E * Gt + lane_off;
     const float* ut = C.mu + (size_t)tile * D.n * Gt + lane_off;
-    float in[DCMAX][FPL];
+    int row[V], d[V];
+    float in[V][DCMAX][FPL];
 #pragma unroll
-    for (int k = 0; k < DCMAX; ++k) {
-        if (k < d) {
-            const float* s = S.iter == 1 ? ut + (size_t)Rw.var(D, k) * Gt : mt + (size_t)Rw.pkg(D, k) * Gt;
-            load_frames<FPL>(s, in[k]);
-        } else {
+    for (int v = 0; v < V; ++v) {
+        row[v] = (rw * V + v) * R + r;
+        const bool active = row[v] < D.m;
+        const QCRow Rw(D, active ? row[v] : 0);
+        d[v] = active ? Rw.d : 0;
 #pragma unroll
-            for (int i = 0; i < FPL; ++i) in[k][i] = 0.0f;
+        for (int k = 0; k < DCMAX; ++k) {
+            if (k < d[v]) {
+                const float* s = S.iter == 1 ? ut + (size_t)Rw.var(D, k) * Gt : mt + (size_t)Rw.pkg(D, k) * Gt;
+                load_frames<FPL>(s, in[v][k]);
+            } else {
+#pragma unroll
+                for (int i = 0; i < FPL; ++i) in[v][k][i] = 0.0f;
+            }
         }
     }
+    // frames violating any of the wave's rows (OR over rows of each row's parity)
     const bool syn = S.early && S.iter >= 2;
     uint64_t par[FPL];
 #pragma unroll
@@ -172,18 +179,31 @@ __device__ __forceinline__ void plan_cn_body(const PlanCode& C, const PlanStep& 
     if (syn) {
         const uint64_t* bt = C.bits + (size_t)tile * D.n * FPL;
 #pragma unroll
-        for (int k = 0; k < DCMAX; ++k) {
-            if (k >= d) continue;
-            const uint64_t* w = bt + (size_t)Rw.var(D, k) * FPL;
+        for (int v = 0; v < V; ++v) {
+            const QCRow Rw(D, d[v] ? row[v] : 0);
+            uint64_t pr[FPL];
 #pragma unroll
-            for (int i = 0; i < FPL; ++i) par[i] ^= w[i];
+            for (int i = 0; i < FPL; ++i) pr[i] = 0;
+#pragma unroll
+            for (int k = 0; k < DCMAX; ++k) {
+                if (k >= d[v]) continue;
+                const uint64_t* w = bt + (size_t)Rw.var(D, k) * FPL;
+#pragma unroll
+                for (int i = 0; i < FPL; ++i) pr[i] ^= w[i];
+            }
+#pragma unroll
+            for (int i = 0; i < FPL; ++i) par[i] |= pr[i];
         }
     }
-    float out[DCMAX][FPL];
-    sp_check<DCMAX, FPL>(in, d, out);
 #pragma unroll
-    for (int k = 0; k < DCMAX; ++k)
-        if (k < d) store_frames<FPL>(mt + (size_t)Rw.pkg(D, k) * Gt, out[k]);
+    for (int v = 0; v < V; ++v) {
+        const QCRow Rw(D, d[v] ? row[v] : 0);
+        float out[DCMAX][FPL];
+        sp_check<DCMAX, FPL>(in[v], d[v], out);
+#pragma unroll
+        for (int k = 0; k < DCMAX; ++k)
+            if (k < d[v]) store_frames<FPL>(mt + (size_t)Rw.pkg(D, k) * Gt, out[k]);
+    }
     if (syn) {
         // a stale read of the flag word can only miss bits (it only gains bits
         // during the pass): a redundant atomic at worst
@@ -317,9 +337,19 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))
     const PlanCode& C = codes[plan_find(codes, ncodes, wave, &PlanCode::cn0)];
     const int64_t lw = wave - C.cn0;
     if (lw >= (int64_t)C.tiles * C.cn_wpt) return;
-    PLAN_LAYOUT_SWITCH(C.layout, PLAN_DC_SWITCH(C.dcc, if constexpr (FPL == 1 || DC <= (FPL == 4 ? 6 : 12)) {
-        plan_cn_body<DC, G, FPL>(C, S, lw, lane);
-    }));
+    if (C.cpw == 1) {
+        PLAN_LAYOUT_SWITCH(C.layout, PLAN_DC_SWITCH(C.dcc, if constexpr (FPL == 1 || DC <= (FPL == 4 ? 6 : 12)) {
+            plan_cn_body<DC, G, FPL, 1>(C, S, lw, lane);
+        }));
+    } else if (C.cpw == 2) {
+        PLAN_LAYOUT_SWITCH(C.layout, PLAN_DC_SWITCH(C.dcc, if constexpr (FPL == 1 && DC <= 8) {
+            plan_cn_body<DC, G, FPL, 2>(C, S, lw, lane);
+        }));
+    } else {
+        PLAN_LAYOUT_SWITCH(C.layout, PLAN_DC_SWITCH(C.dcc, if constexpr (FPL == 1 && DC <= 6) {
+            plan_cn_body<DC, G, FPL, 4>(C, S, lw, lane);
+        }));
+    }
 }
 
 __global__ void __launch_bounds__(kBlock) plan_vn_kernel(const PlanCode* __restrict__ codes, int ncodes,
@@ -513,8 +543,10 @@ int plan_dv_class(int d) {
 }
 
 bool layout_allowed(const ldpc_graph* g, int l) {
-    if (l < 0 || l >= 64 || layout_base(l) >= kPlanLayouts || ((l >> 4) & 3) == 3) return false;
+    if (l < 0 || l >= 256 || layout_base(l) >= kPlanLayouts || ((l >> 4) & 3) == 3 || ((l >> 6) & 3) == 3)
+        return false;
     if (layout_vpw(l) > 1 && (layout_fpl(l) != 1 || g->dv_max > 8)) return false;
+    if (layout_cpw(l) > 1 && (layout_fpl(l) != 1 || g->dc_max > (layout_cpw(l) == 2 ? 8 : 6))) return false;
     if (layout_fpl(l) == 4) return g->dc_max <= 6 && g->dv_max <= 8;
     if (layout_fpl(l) == 2) return g->dc_max <= 12 && g->dv_max <= 8;
     return true;
@@ -632,7 +664,8 @@ void build_table(ldpc_plan* P, const PlanBuffers& B, char* ws) {
         T.dvc = plan_dv_class(g->dv_max);
         const int rows_per_wave = 64 / layout_g(l);
         T.vpw = layout_vpw(l);
-        T.cn_wpt = (g->m + rows_per_wave - 1) / rows_per_wave;
+        T.cpw = layout_cpw(l);
+        T.cn_wpt = (g->m + rows_per_wave * T.cpw - 1) / (rows_per_wave * T.cpw);
         T.vn_wpt = (g->n + rows_per_wave * T.vpw - 1) / (rows_per_wave * T.vpw);
         T.io_vchunks = (g->n + 63) / 64;
         T.io_fchunks = (R.tiles * R.Gt + 63) / 64;
@@ -887,7 +920,7 @@ ldpc_status ldpc_plan_autotune(ldpc_plan* P, const float* const* llr, float* con
     for (int c = 0; c < P->ncodes && status == LDPC_OK; ++c) {
         const int start = P->layouts[c];
         int keep = start;
-        for (int l = 0; l < 48 && status == LDPC_OK; ++l) {
+        for (int l = 0; l < 192 && status == LDPC_OK; ++l) {
             if (l == start || !layout_allowed(P->graphs[c], l)) continue;
             if (layout_g(l) > 8 && layout_g(l) / 2 >= P->gammas[c]) continue;   // G at most the next power of two
             P->layouts[c] = l;

@@ -31,12 +31,12 @@ OK, EINVAL, EWORKSPACE, EHIP, EUNSUPPORTED, ENOMEM = 0, -1, -2, -3, -4, -5
 GRAPH_QC, GRAPH_CONV = 0, 1
 LAYOUT_G8, LAYOUT_G16, LAYOUT_G32, LAYOUT_G64, LAYOUT_G64F4, LAYOUT_G64F2 = 0, 1, 2, 3, 4, 5
 LAYOUT_NAMES = ["G8", "G16", "G32", "G64", "G64F4", "G64F2"]
-LAYOUT_VN2, LAYOUT_VN4 = 16, 32
+LAYOUT_VN2, LAYOUT_VN4, LAYOUT_CN2, LAYOUT_CN4 = 16, 32, 64, 128
 
 
 def layout_name(layout: int) -> str:
-    v = (layout >> 4) & 3
-    return LAYOUT_NAMES[layout & 15] + ("" if v == 0 else f"/VN{1 << v}")
+    v, c = (layout >> 4) & 3, (layout >> 6) & 3
+    return LAYOUT_NAMES[layout & 15] + ("" if v == 0 else f"/VN{1 << v}") + ("" if c == 0 else f"/CN{1 << c}")
 PLAN_MAX_CODES = 16
 TIMING_CLASSES = 21
 MAX_ITERS = 100000

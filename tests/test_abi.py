@@ -288,7 +288,11 @@ def test_plan_creation_and_layout_rules():
         wide18.set_layout(0, ldpc.LAYOUT_G64F2)        # row weight 18
     plan.set_layout(0, ldpc.LAYOUT_G8 | ldpc.LAYOUT_VN4)
     assert plan.layout(0) == 32 and ldpc.layout_name(plan.layout(0)) == "G8/VN4"
-    for bad in (ldpc.LAYOUT_G64F4 | ldpc.LAYOUT_VN2, 48, 6, -2):
+    plan.set_layout(1, ldpc.LAYOUT_G16 | ldpc.LAYOUT_CN4 | ldpc.LAYOUT_VN2)
+    assert ldpc.layout_name(plan.layout(1)) == "G16/VN2/CN4"
+    with pytest.raises(ldpc.LdpcError):
+        plan.set_layout(6, ldpc.LAYOUT_G64 | ldpc.LAYOUT_CN2)      # 3 x 9: row weight 9
+    for bad in (ldpc.LAYOUT_G64F4 | ldpc.LAYOUT_VN2, ldpc.LAYOUT_G64F4 | ldpc.LAYOUT_CN2, 48, 192, 6, -2):
         with pytest.raises(ldpc.LdpcError):
             plan.set_layout(4, bad)
     plan.set_layout(4, ldpc.LAYOUT_G8)

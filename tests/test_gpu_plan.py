@@ -61,7 +61,9 @@ def test_every_layout_matches_single_code_decoder():
     refs = single_code(graphs, llrs, 12, True)
     ws = None
     for layout in list(range(6)) + [ldpc.LAYOUT_G8 | ldpc.LAYOUT_VN2, ldpc.LAYOUT_G32 | ldpc.LAYOUT_VN4,
-                                     ldpc.LAYOUT_G64 | ldpc.LAYOUT_VN2, ldpc.LAYOUT_G64 | ldpc.LAYOUT_VN4]:
+                                     ldpc.LAYOUT_G64 | ldpc.LAYOUT_VN2, ldpc.LAYOUT_G64 | ldpc.LAYOUT_VN4,
+                                     ldpc.LAYOUT_G8 | ldpc.LAYOUT_CN2, ldpc.LAYOUT_G16 | ldpc.LAYOUT_CN4,
+                                     ldpc.LAYOUT_G64 | ldpc.LAYOUT_CN4 | ldpc.LAYOUT_VN4]:
         plan = ldpc.Plan(graphs, gammas, 12, early_stop=True)
         for c in range(len(graphs)):
             try:
@@ -77,10 +79,13 @@ def test_fixed_iterations_every_layout():
     graphs, llrs = make_case(RAGGED[:5], 3000)
     gammas = [c["gamma"] for c in RAGGED[:5]]
     refs = single_code(graphs, llrs, 3, False)
-    for layout in (0, 2, 3, ldpc.LAYOUT_G64 | ldpc.LAYOUT_VN4):
+    for layout in (0, 2, 3, ldpc.LAYOUT_G64 | ldpc.LAYOUT_VN4, ldpc.LAYOUT_G32 | ldpc.LAYOUT_CN2):
         plan = ldpc.Plan(graphs, gammas, 3, early_stop=False)
         for c in range(len(graphs)):
-            plan.set_layout(c, layout)
+            try:
+                plan.set_layout(c, layout)
+            except ldpc.LdpcError:
+                pass                       # row groups where rows are too heavy
         print(f"[gpu] fixed-iteration plan layout={ldpc.layout_name(layout)}", flush=True)
         assert_same(plan.decode(llrs), refs, f"3 iterations, layout {ldpc.layout_name(layout)}")
 
@@ -151,4 +156,5 @@ def test_autotune_keeps_results():
         assert 0 <= base <= 5 and (base != ldpc.LAYOUT_G64F4 or g.info["dc_max"] <= 6)
         assert base != ldpc.LAYOUT_G64F2 or g.info["dc_max"] <= 12
         assert (l >> 4) == 0 or base in (0, 1, 2, 3)
+        assert (l >> 6) == 0 or g.info["dc_max"] <= 8
     assert_same(plan.decode(llrs, outs=outs, ws=ws), single_code(graphs, llrs, 20, True), "after autotune")
