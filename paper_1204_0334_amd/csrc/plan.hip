@@ -85,6 +85,39 @@ __device__ __forceinline__ int plan_find(const PlanCode* __restrict__ codes, int
     return c;
 }
 
+// Row (j, s) and variable (l, t) of a QC code with the base row / column
+// shared by the whole wave (so the circulant block indices and shifts are
+// wave-uniform) and the offset s (t) per lane; same edge order as QCRow /
+// QCCol.
+struct PlanRow {
+    int b0, d, s;
+    __device__ __forceinline__ PlanRow(const QCDesc& D, int j, int s_, bool active) : s(s_) {
+        b0 = D.rstart[j];
+        d = active ? D.rstart[j + 1] - b0 : 0;
+    }
+    __device__ __forceinline__ int64_t pkg(const QCDesc& D, int k) const { return (int64_t)(b0 + k) * D.p + s; }
+    __device__ __forceinline__ int var(const QCDesc& D, int k) const {
+        const int b = b0 + k;
+        int t = s + D.eshift[b];
+        if (t >= D.p) t -= D.p;
+        return D.ecol[b] * D.p + t;
+    }
+};
+
+struct PlanCol {
+    int c0, d, t;
+    __device__ __forceinline__ PlanCol(const QCDesc& D, int l, int t_, bool active) : t(t_) {
+        c0 = D.cstart[l];
+        d = active ? D.cstart[l + 1] - c0 : 0;
+    }
+    __device__ __forceinline__ int64_t pkg(const QCDesc& D, int k) const {
+        const int b = D.cedge[c0 + k];
+        int s = t - D.eshift[b];
+        if (s < 0) s += D.p;
+        return (int64_t)b * D.p + s;
+    }
+};
+
 // a[i] of a register array by mask blending (a dynamic index would move the
 // array to private memory)
 template <int FPL>
@@ -152,14 +185,17 @@ __device__ __forceinline__ void plan_cn_body(const PlanCode& C, const PlanStep& 
     const size_t lane_off = (G == 64) ? (size_t)lane * FPL : (size_t)f;
     float* mt = C.msg + (size_t)tile * D.E * Gt + lane_off;
     const float* ut = C.mu + (size_t)tile * D.n * Gt + lane_off;
-    int row[V], d[V];
+    // the wave's rows: base row j (uniform), offsets sw*V*R .. within it
+    const int spw = C.cn_wpt / D.J;
+    const int j = rw / spw, sw = rw - j * spw;
+    int srow[V], d[V];
     float in[V][DCMAX][FPL];
 #pragma unroll
     for (int v = 0; v < V; ++v) {
-        row[v] = (rw * V + v) * R + r;
-        const bool active = row[v] < D.m;
-        const QCRow Rw(D, active ? row[v] : 0);
-        d[v] = active ? Rw.d : 0;
+        srow[v] = (sw * V + v) * R + r;
+        const bool active = srow[v] < D.p;
+        const PlanRow Rw(D, j, active ? srow[v] : 0, active);
+        d[v] = Rw.d;
 #pragma unroll
         for (int k = 0; k < DCMAX; ++k) {
             if (k < d[v]) {
@@ -180,7 +216,7 @@ __device__ __forceinline__ void plan_cn_body(const PlanCode& C, const PlanStep& 
         const uint64_t* bt = C.bits + (size_t)tile * D.n * FPL;
 #pragma unroll
         for (int v = 0; v < V; ++v) {
-            const QCRow Rw(D, d[v] ? row[v] : 0);
+            const PlanRow Rw(D, j, d[v] ? srow[v] : 0, d[v] > 0);
             uint64_t pr[FPL];
 #pragma unroll
             for (int i = 0; i < FPL; ++i) pr[i] = 0;
@@ -197,7 +233,7 @@ __device__ __forceinline__ void plan_cn_body(const PlanCode& C, const PlanStep& 
     }
 #pragma unroll
     for (int v = 0; v < V; ++v) {
-        const QCRow Rw(D, d[v] ? row[v] : 0);
+        const PlanRow Rw(D, j, d[v] ? srow[v] : 0, d[v] > 0);
         float out[DCMAX][FPL];
         sp_check<DCMAX, FPL>(in[v], d[v], out);
 #pragma unroll
@@ -262,15 +298,19 @@ __device__ __forceinline__ void plan_vn_body(const PlanCode& C, const PlanStep& 
     if (S.early && all) return;
     const size_t lane_off = (G == 64) ? (size_t)lane * FPL : (size_t)f;
     float* mt = C.msg + (size_t)tile * D.E * Gt + lane_off;
-    int var[V], dv[V];
+    // the wave's variables: base column l (uniform), offsets sw*V*R .. within it
+    const int spw = C.vn_wpt / D.L;
+    const int l = rw / spw, sw = rw - l * spw;
+    int tcol[V], var[V], dv[V];
     bool active[V];
     float mu[V][FPL], a[V][DVMAX][FPL];
 #pragma unroll
     for (int v = 0; v < V; ++v) {
-        var[v] = (rw * V + v) * R + r;
-        active[v] = var[v] < D.n;
-        const QCCol Cc(D, active[v] ? var[v] : 0);
-        dv[v] = active[v] ? Cc.d : 0;
+        tcol[v] = (sw * V + v) * R + r;
+        active[v] = tcol[v] < D.p;
+        var[v] = l * D.p + (active[v] ? tcol[v] : 0);
+        const PlanCol Cc(D, l, active[v] ? tcol[v] : 0, active[v]);
+        dv[v] = Cc.d;
         if (active[v]) {
             load_frames<FPL>(C.mu + ((size_t)tile * D.n + var[v]) * Gt + lane_off, mu[v]);
         } else {
@@ -289,7 +329,7 @@ __device__ __forceinline__ void plan_vn_body(const PlanCode& C, const PlanStep& 
     }
 #pragma unroll
     for (int v = 0; v < V; ++v) {
-        const QCCol Cc(D, active[v] ? var[v] : 0);
+        const PlanCol Cc(D, l, active[v] ? tcol[v] : 0, active[v]);
         float b[DVMAX][FPL], L[FPL];
         sp_variable<DVMAX, FPL>(mu[v], a[v], b, L);
         if (!S.last) {
@@ -665,8 +705,9 @@ void build_table(ldpc_plan* P, const PlanBuffers& B, char* ws) {
         const int rows_per_wave = 64 / layout_g(l);
         T.vpw = layout_vpw(l);
         T.cpw = layout_cpw(l);
-        T.cn_wpt = (g->m + rows_per_wave * T.cpw - 1) / (rows_per_wave * T.cpw);
-        T.vn_wpt = (g->n + rows_per_wave * T.vpw - 1) / (rows_per_wave * T.vpw);
+        // waves per tile: per base row (column), enough waves for its p rows (variables)
+        T.cn_wpt = g->J * ((g->p + rows_per_wave * T.cpw - 1) / (rows_per_wave * T.cpw));
+        T.vn_wpt = g->L * ((g->p + rows_per_wave * T.vpw - 1) / (rows_per_wave * T.vpw));
         T.io_vchunks = (g->n + 63) / 64;
         T.io_fchunks = (R.tiles * R.Gt + 63) / 64;
         T.cn0 = cn;
