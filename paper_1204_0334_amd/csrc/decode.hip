@@ -162,6 +162,7 @@ struct BlockParams {
     uint64_t* frozen;        // [max_iters+1][tiles][FPL]
     int gamma, tiles, iter, last, early;
     const float* nms_w;      // learned min-sum: device [iters][J][2] (scale, offset); NULL = sum-product
+    uint64_t* badw;          // early stopping: [tiles * m][FPL] frames violating each row (per pass)
 };
 
 // Learned min-sum check rule for one frame (neural normalized-offset
@@ -195,33 +196,39 @@ __device__ __forceinline__ MinInfo row_minima(const float (&mag)[DC], const uint
     return r;
 }
 
+template <int FPL>
+__device__ __forceinline__ uint64_t pick_word(const uint64_t (&a)[FPL], int i);
+
 // Check-node pass with early stopping: false when every frame of the tile was
 // frozen by iteration iter-2 (the wave has nothing to do).
+// lane_live: false when every frame of the lane (frames FPL*lane .. +FPL-1:
+// bit `lane` of each word) is frozen; such lanes skip their loads, arithmetic
+// and stores (a frozen frame's messages are never used again).
 template <int FPL>
-__device__ __forceinline__ bool cn_tile_live(const BlockParams& P, int tile) {
+__device__ __forceinline__ bool cn_tile_live(const BlockParams& P, int tile, int lane, bool& lane_live) {
+    lane_live = true;
     if (!(P.early && P.iter >= 3)) return true;
     const uint64_t* fz = P.frozen + ((size_t)(P.iter - 2) * P.tiles + tile) * FPL;
-    bool all = true;
+    bool all = true, mine = true;
 #pragma unroll
-    for (int f = 0; f < FPL; ++f) all = all && (fz[f] == ~0ull);
+    for (int f = 0; f < FPL; ++f) {
+        const uint64_t w = fz[f];
+        all = all && (w == ~0ull);
+        mine = mine && ((w >> lane) & 1ull);
+    }
+    lane_live = !mine;
     return !all;
 }
 
-// OR the frames whose decisions of iteration iter-1 violate the row (bad,
-// already masked to valid frames) into unsat[iter-1]: lane f handles word f.
-// A stale read can only miss bits (the word only gains bits during the
-// pass), which costs a redundant atomic, never a missed one.
+// Record the frames whose decisions of iteration iter-1 violate the row (bad,
+// already masked to valid frames) in the row's own words of badw (lane f
+// writes word f); unsat_reduce_kernel ORs a tile's rows into unsat[iter-1].
+// Plain stores: every row of every tile would otherwise update the same few
+// flag words, and those updates serialise.
 template <int FPL>
-__device__ __forceinline__ void cn_publish_unsat(const BlockParams& P, int tile, int lane,
-                                                 const uint64_t (&bad)[FPL]) {
-    uint64_t* un = P.unsat + ((size_t)(P.iter - 1) * P.tiles + tile) * FPL;
-#pragma unroll
-    for (int f = 0; f < FPL; ++f) {
-        if (bad[f] && lane == f) {
-            if ((__atomic_load_n(un + f, __ATOMIC_RELAXED) & bad[f]) != bad[f])
-                atomicOr((unsigned long long*)(un + f), (unsigned long long)bad[f]);
-        }
-    }
+__device__ __forceinline__ void cn_record_bad(const BlockParams& P, int64_t wave, int lane,
+                                              const uint64_t (&bad)[FPL]) {
+    if (lane < FPL) P.badw[(size_t)wave * FPL + lane] = pick_word<FPL>(bad, lane);
 }
 
 // Horizontal step of iteration P.iter for the check row R and the 64*FPL
@@ -235,7 +242,7 @@ __device__ __forceinline__ void cn_publish_unsat(const BlockParams& P, int tile,
 template <int DCMAX, int FPL, int RULE, bool SYN = false>
 __device__ __forceinline__ void cn_row(const QCDesc& D, const BlockParams& P, const QCRow& R, int tile, int lane,
                                        const float* src, const float* mu, float* dst, bool from_mu,
-                                       int nvalid = 0) {
+                                       int nvalid = 0, int64_t wave = 0, bool lane_live = true) {
     constexpr int Gt = 64 * FPL;
     const size_t lane_off = (size_t)lane * FPL;
     const float* st = src + (size_t)tile * D.E * Gt + lane_off;
@@ -244,7 +251,7 @@ __device__ __forceinline__ void cn_row(const QCDesc& D, const BlockParams& P, co
     float in[DCMAX][FPL];
 #pragma unroll
     for (int k = 0; k < DCMAX; ++k) {
-        if (R.valid(D, k)) {
+        if (R.valid(D, k) && lane_live) {
             const float* s = from_mu ? ut + (size_t)R.var(D, k) * Gt : st + (size_t)R.pkg(D, k) * Gt;
             load_frames<FPL>(s, in[k]);
         } else {
@@ -291,13 +298,15 @@ __device__ __forceinline__ void cn_row(const QCDesc& D, const BlockParams& P, co
             }
         }
     }
+    if (lane_live) {
 #pragma unroll
-    for (int k = 0; k < DCMAX; ++k)
-        if (R.valid(D, k)) store_frames<FPL>(dt + (size_t)R.pkg(D, k) * Gt, outv[k]);
+        for (int k = 0; k < DCMAX; ++k)
+            if (R.valid(D, k)) store_frames<FPL>(dt + (size_t)R.pkg(D, k) * Gt, outv[k]);
+    }
     if (syn) {
 #pragma unroll
         for (int f = 0; f < FPL; ++f) par[f] &= valid_word<FPL>(nvalid, f);
-        cn_publish_unsat<FPL>(P, tile, lane, par);
+        cn_record_bad<FPL>(P, wave, lane, par);
     }
 }
 
@@ -313,8 +322,9 @@ __global__ void __launch_bounds__(kBlock) cn_block_kernel(const QCDesc D, const 
     if (tile >= P.tiles) return;
     const int nvalid = min(P.gamma - tile * Gt, Gt);
     const QCRow R(D, row);
-    if (!cn_tile_live<FPL>(P, tile)) return;
-    cn_row<DCMAX, FPL, RULE, true>(D, P, R, tile, lane, P.msg, P.mu, P.msg, P.iter == 1, nvalid);
+    bool lane_live;
+    if (!cn_tile_live<FPL>(P, tile, lane, lane_live)) return;
+    cn_row<DCMAX, FPL, RULE, true>(D, P, R, tile, lane, P.msg, P.mu, P.msg, P.iter == 1, nvalid, wave, lane_live);
 }
 
 // Frames of a tile frozen before iteration P.iter (bit set = frozen; padding
@@ -351,12 +361,18 @@ __device__ __forceinline__ void vn_column(const QCDesc& D, const BlockParams& P,
     const QCCol C(D, col);
     const size_t lane_off = (size_t)lane * FPL;
     float* mt = P.msg + (size_t)tile * D.E * Gt + lane_off;
+    // a lane whose frames are all frozen (or padding) skips its loads and stores
+    bool lane_live = false;
+#pragma unroll
+    for (int f = 0; f < FPL; ++f) lane_live = lane_live || !((frz[f] >> lane) & 1ull);
     float mu[FPL];
-    load_frames<FPL>(P.mu + ((size_t)tile * D.n + C.v) * Gt + lane_off, mu);
+#pragma unroll
+    for (int f = 0; f < FPL; ++f) mu[f] = 0.0f;
+    if (lane_live) load_frames<FPL>(P.mu + ((size_t)tile * D.n + C.v) * Gt + lane_off, mu);
     float a[DVMAX][FPL];
 #pragma unroll
     for (int k = 0; k < DVMAX; ++k) {
-        if (C.valid(D, k)) {
+        if (C.valid(D, k) && lane_live) {
             load_frames<FPL>(mt + (size_t)C.pkg(D, k) * Gt, a[k]);
         } else {
 #pragma unroll
@@ -365,7 +381,7 @@ __device__ __forceinline__ void vn_column(const QCDesc& D, const BlockParams& P,
     }
     float b[DVMAX][FPL];
     sp_variable<DVMAX, FPL>(mu, a, b, L);
-    if (!P.last) {
+    if (!P.last && lane_live) {
 #pragma unroll
         for (int k = 0; k < DVMAX; ++k)
             if (C.valid(D, k)) store_frames<FPL>(mt + (size_t)C.pkg(D, k) * Gt, b[k]);
@@ -473,6 +489,113 @@ __global__ void __launch_bounds__(kOutBlock) vn_block_out_kernel(const QCDesc D,
         const size_t o = (size_t)(tile * Gt + fr) * D.n + col;
         post[o] = clip30(L);
         bits_out[o] = (uint8_t)(L < 0.0f);
+    }
+}
+
+// Variable-node pass with early stopping: one variable per wave as in
+// vn_block_kernel, plus the packed decisions and the posterior of the frames
+// still running, the latter into the package-layout array postw
+// [tile][n][Gt] (coalesced like the betas; frozen frames keep the value of
+// their stopping iteration).  block_output_kernel turns postw and the
+// decision words into the caller's layout once, after the last iteration.
+template <int DVMAX, int FPL>
+__global__ void __launch_bounds__(kBlock) vn_block_early_kernel(const QCDesc D, const BlockParams P, float* postw) {
+    constexpr int Gt = 64 * FPL;
+    const int lane = threadIdx.x & 63;
+    const int wave = blockIdx.x * kWavesPerBlock + wave_in_block();
+    const int tile = wave / D.n;
+    const int col = wave - tile * D.n;
+    if (tile >= P.tiles) return;
+    const int nvalid = min(P.gamma - tile * Gt, Gt);
+    uint64_t frz[FPL];
+    bool any, all;
+    frozen_words<FPL>(P, tile, nvalid, frz, any, all);
+    if (col == 0) publish_frozen<FPL>(P, tile, lane, frz);
+    if (all) return;
+    float L[FPL];
+    vn_column<DVMAX, FPL>(D, P, tile, col, lane, any, frz, L);
+    float pv[FPL];
+#pragma unroll
+    for (int f = 0; f < FPL; ++f) pv[f] = clip30(L[f]);
+    float* pw = postw + ((size_t)tile * D.n + col) * Gt + (size_t)lane * FPL;
+    if (!any) {
+        store_frames<FPL>(pw, pv);
+    } else {
+        // frame lane*FPL + f: word f, bit lane
+#pragma unroll
+        for (int f = 0; f < FPL; ++f)
+            if (!((frz[f] >> lane) & 1ull)) pw[f] = pv[f];
+    }
+}
+
+// Posterior and decisions of every frame from the package layout (postw,
+// packed decision words) to the caller's [gamma][n] buffers, through LDS:
+// 64 variables x 64 frames per block.
+template <int FPL>
+__global__ void __launch_bounds__(256) block_output_kernel(const float* __restrict__ postw,
+                                                           const uint64_t* __restrict__ bitw, int n, int gamma,
+                                                           float* __restrict__ post, uint8_t* __restrict__ bits_out) {
+    constexpr int Gt = 64 * FPL;
+    __shared__ float Ps[64][65];
+    __shared__ uint8_t Bs[64][65];
+    const int c0 = blockIdx.x * 64, f0 = blockIdx.y * 64;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    for (int r = ty; r < 64; r += 4) {           // r: variable, tx: frame
+        const int c = c0 + r, g = f0 + tx;
+        if (c < n && g < gamma) {
+            const int tile = g / Gt, fl = g - tile * Gt;
+            Ps[r][tx] = postw[((size_t)tile * n + c) * Gt + fl];
+            const uint64_t w = bitw[((size_t)tile * n + c) * FPL + fl % FPL];
+            Bs[r][tx] = (uint8_t)((w >> (fl / FPL)) & 1ull);
+        }
+    }
+    __syncthreads();
+    for (int r = ty; r < 64; r += 4) {           // r: frame, tx: variable
+        const int c = c0 + tx, g = f0 + r;
+        if (c < n && g < gamma) {
+            const size_t o = (size_t)g * n + c;
+            post[o] = Ps[tx][r];
+            bits_out[o] = Bs[tx][r];
+        }
+    }
+}
+
+// unsat[iter-1][tile][f] = OR over the tile's rows of badw (one block per
+// tile); a tile whose frames were all frozen by iteration iter-2 skipped its
+// check-node pass and keeps a zero word.
+template <int FPL>
+__global__ void __launch_bounds__(256) unsat_reduce_kernel(const QCDesc D, const BlockParams P) {
+    __shared__ uint64_t part[4][FPL];
+    const int tile = blockIdx.x;
+    uint64_t* un = P.unsat + ((size_t)(P.iter - 1) * P.tiles + tile) * FPL;
+    if (P.iter >= 3) {
+        const uint64_t* fz = P.frozen + ((size_t)(P.iter - 2) * P.tiles + tile) * FPL;
+        bool all = true;
+#pragma unroll
+        for (int f = 0; f < FPL; ++f) all = all && (fz[f] == ~0ull);
+        if (all) return;
+    }
+    uint64_t acc[FPL];
+#pragma unroll
+    for (int f = 0; f < FPL; ++f) acc[f] = 0;
+    const uint64_t* bw = P.badw + (size_t)tile * D.m * FPL;
+    for (int r = threadIdx.x; r < D.m; r += 256) {
+#pragma unroll
+        for (int f = 0; f < FPL; ++f) acc[f] |= bw[(size_t)r * FPL + f];
+    }
+#pragma unroll
+    for (int f = 0; f < FPL; ++f) {
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) acc[f] |= __shfl_xor(acc[f], off);
+    }
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+        for (int f = 0; f < FPL; ++f) part[threadIdx.x >> 6][f] = acc[f];
+    }
+    __syncthreads();
+    if (threadIdx.x < FPL) {
+        const int f = threadIdx.x;
+        un[f] = part[0][f] | part[1][f] | part[2][f] | part[3][f];
     }
 }
 
@@ -1258,7 +1381,7 @@ static Tiling choose_tiling(int gamma, const ldpc_graph* g) {
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct BlockLayout {
-    size_t mu, msg, bits, flags, flag_words, total;   // flags: unsat words, then frozen words
+    size_t mu, msg, bits, postw, badw, flags, flag_words, total;   // flags: unsat words, then frozen words
 };
 
 static BlockLayout block_layout(const ldpc_graph* g, const Tiling& t, int max_iters) {
@@ -1268,6 +1391,8 @@ static BlockLayout block_layout(const ldpc_graph* g, const Tiling& t, int max_it
     L.mu = take((size_t)t.gpad * g->n * sizeof(float));
     L.msg = take((size_t)t.gpad * g->E * sizeof(float));
     L.bits = take((size_t)t.tiles * g->n * t.fpl * sizeof(uint64_t));
+    L.postw = take((size_t)t.gpad * g->n * sizeof(float));   // early stopping: posteriors [tile][n][Gt]
+    L.badw = take((size_t)t.tiles * g->m * t.fpl * sizeof(uint64_t));
     L.flag_words = (size_t)(max_iters + 1) * t.tiles * t.fpl;
     L.flags = take(2 * L.flag_words * sizeof(uint64_t));
     L.total = off;
@@ -1366,6 +1491,8 @@ static void run_block(const ldpc_graph* g, const float* llr, int gamma, int max_
     P.tiles = tl.tiles;
     P.early = early;
     P.nms_w = nms_w;
+    float* postw = reinterpret_cast<float*>(ws + lay.postw);
+    P.badw = reinterpret_cast<uint64_t*>(ws + lay.badw);
 
     {
         timing::Scope ts(0, st);
@@ -1390,14 +1517,25 @@ static void run_block(const ldpc_graph* g, const float* llr, int gamma, int max_
                     cn_block_kernel<DC, FPL, 0><<<cn_grid, kBlock, 0, st>>>(D, P);
             });
         }
+        if (early && it >= 2) {
+            timing::Scope ts(3, st);
+            unsat_reduce_kernel<FPL><<<tl.tiles, 256, 0, st>>>(D, P);
+        }
         {
             timing::Scope ts(2, st);
-            if (early || P.last) {
+            if (early) {
+                LDPC_DV_SWITCH(dvc, (vn_block_early_kernel<DV, FPL><<<vn_grid, kBlock, 0, st>>>(D, P, postw)));
+            } else if (P.last) {
                 LDPC_DV_SWITCH(dvc, (vn_block_out_kernel<DV, FPL><<<out_grid, kOutBlock, 0, st>>>(D, P, post, bits)));
             } else {
                 LDPC_DV_SWITCH(dvc, (vn_block_kernel<DV, FPL><<<vn_grid, kBlock, 0, st>>>(D, P)));
             }
         }
+    }
+    if (early) {
+        timing::Scope ts(4, st);
+        dim3 grid((D.n + 63) / 64, (gamma + 63) / 64);
+        block_output_kernel<FPL><<<grid, 256, 0, st>>>(postw, P.bits, D.n, gamma, post, bits);
     }
     P.iter = max_iters;
     {
