@@ -71,6 +71,8 @@ struct PlanCode {
     int64_t io0;          // first block in the ingest / output launches
     int vpw;              // variable-node launch: groups of R variables per wave (1, 2 or 4)
     int cpw;              // check-node launch: groups of R rows per wave (1, 2 or 4)
+    uint64_t* badw;       // early stopping: [tiles * cn_wpt][FPL] frames violating each check wave's rows
+    int64_t red0;         // first block in the flag-reduction launch (one block per tile)
 };
 
 struct PlanStep {
@@ -241,26 +243,19 @@ __device__ __forceinline__ void plan_cn_body(const PlanCode& C, const PlanStep& 
             if (k < d[v]) store_frames<FPL>(mt + (size_t)Rw.pkg(D, k) * Gt, out[k]);
     }
     if (syn) {
-        // a stale read of the flag word can only miss bits (it only gains bits
-        // during the pass): a redundant atomic at worst
-        uint64_t* un = C.unsat + ((size_t)(S.iter - 1) * C.tiles + tile) * FPL;
+        // the wave's violated frames go to its own words (plain stores; the
+        // flag word of the tile is formed by plan_unsat_kernel)
+        uint64_t* bw = C.badw + lw * FPL;
         if constexpr (G == 64) {
+            uint64_t bad[FPL];
 #pragma unroll
-            for (int i = 0; i < FPL; ++i) {
-                const uint64_t bad = par[i] & valid_word<FPL>(nvalid, i);
-                if (bad && lane == i) {
-                    if ((__atomic_load_n(un + i, __ATOMIC_RELAXED) & bad) != bad)
-                        atomicOr((unsigned long long*)(un + i), (unsigned long long)bad);
-                }
-            }
+            for (int i = 0; i < FPL; ++i) bad[i] = par[i] & valid_word<FPL>(nvalid, i);
+            if (lane < FPL) bw[lane] = plan_pick<FPL>(bad, lane);
         } else {
             uint64_t v = par[0] & valid_word<1>(nvalid, 0);
 #pragma unroll
             for (int off = 32; off >= 1; off >>= 1) v |= __shfl_xor(v, off);
-            if (lane == 0 && v) {
-                if ((__atomic_load_n(un, __ATOMIC_RELAXED) & v) != v)
-                    atomicOr((unsigned long long*)un, (unsigned long long)v);
-            }
+            if (lane == 0) bw[0] = v;
         }
     }
 }
@@ -411,6 +406,42 @@ __global__ void __launch_bounds__(kBlock) plan_vn_kernel(const PlanCode* __restr
         PLAN_LAYOUT_SWITCH(C.layout, PLAN_DV_SWITCH(C.dvc, if constexpr (FPL == 1 && DV <= 8) {
             plan_vn_body<DV, G, FPL, 4>(C, S, lw, lane);
         }));
+    }
+}
+
+// unsat[iter-1][tile] = OR of the tile's check-wave words (one block per
+// (code, tile)); a tile frozen by iteration iter-2 skipped its check pass and
+// keeps its zero word.
+__global__ void __launch_bounds__(256) plan_unsat_kernel(const PlanCode* __restrict__ codes, int ncodes,
+                                                         PlanStep S) {
+    __shared__ uint64_t part[4][4];
+    const PlanCode& C = codes[plan_find(codes, ncodes, blockIdx.x, &PlanCode::red0)];
+    const int tile = (int)(blockIdx.x - C.red0);
+    if (tile >= C.tiles) return;
+    const int fpl = C.fpl;
+    if (S.iter >= 3) {
+        const uint64_t* fz = C.frozen + ((size_t)(S.iter - 2) * C.tiles + tile) * fpl;
+        bool all = true;
+        for (int i = 0; i < fpl; ++i) all = all && (fz[i] == ~0ull);
+        if (all) return;
+    }
+    uint64_t acc[4] = {0, 0, 0, 0};
+    const uint64_t* bw = C.badw + (size_t)tile * C.cn_wpt * fpl;
+    for (int w = threadIdx.x; w < C.cn_wpt; w += 256)
+        for (int i = 0; i < fpl; ++i) acc[i] |= bw[(size_t)w * fpl + i];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) acc[i] |= __shfl_xor(acc[i], off);
+    }
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) part[threadIdx.x >> 6][i] = acc[i];
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < fpl) {
+        const int i = threadIdx.x;
+        C.unsat[((size_t)(S.iter - 1) * C.tiles + tile) * fpl + i] = part[0][i] | part[1][i] | part[2][i] | part[3][i];
     }
 }
 
@@ -593,10 +624,16 @@ bool layout_allowed(const ldpc_graph* g, int l) {
 }
 
 struct CodeRegion {
-    int tiles, Gt;
+    int tiles, Gt, cn_wpt;
     int64_t flag_words;
-    size_t mu, msg, postw, bits, flags, total;
+    size_t mu, msg, postw, bits, flags, badw, total;
 };
+
+// check-node waves per tile: per base row, enough waves for its p rows
+int plan_cn_wpt(const ldpc_graph* g, int l) {
+    const int rows = (64 / layout_g(l)) * layout_cpw(l);
+    return g->J * ((g->p + rows - 1) / rows);
+}
 
 CodeRegion code_region(const ldpc_graph* g, int gamma, int layout, int max_iters) {
     CodeRegion R{};
@@ -611,6 +648,8 @@ CodeRegion code_region(const ldpc_graph* g, int gamma, int layout, int max_iters
     R.postw = take(gpad * g->n * sizeof(float));
     R.bits = take((size_t)R.tiles * g->n * layout_fpl(layout) * sizeof(uint64_t));
     R.flags = take(2 * (size_t)R.flag_words * sizeof(uint64_t));
+    R.cn_wpt = plan_cn_wpt(g, layout);
+    R.badw = take((size_t)R.tiles * R.cn_wpt * layout_fpl(layout) * sizeof(uint64_t));
     R.total = off;
     return R;
 }
@@ -638,7 +677,7 @@ struct ldpc_plan {
     size_t table_bytes = 0, ws_bytes = 0;
     std::vector<PlanCode> table;          // host copy of the device table
     // launch geometry
-    int64_t cn_waves = 0, vn_waves = 0, syn_threads = 0, st_threads = 0, io_blocks = 0;
+    int64_t cn_waves = 0, vn_waves = 0, syn_threads = 0, st_threads = 0, io_blocks = 0, red_blocks = 0;
     // what the device table currently describes
     bool table_valid = false;
     const void* table_ws = nullptr;
@@ -675,7 +714,7 @@ ldpc_status check_buffers(const ldpc_plan* P, const PlanBuffers& B, const void* 
 // fill the host table for the current layouts and buffers
 void build_table(ldpc_plan* P, const PlanBuffers& B, char* ws) {
     P->table.assign(P->ncodes, PlanCode{});
-    int64_t cn = 0, vn = 0, syn = 0, st = 0, io = 0;
+    int64_t cn = 0, vn = 0, syn = 0, st = 0, io = 0, red = 0;
     for (int c = 0; c < P->ncodes; ++c) {
         const ldpc_graph* g = P->graphs[c];
         const int l = P->layouts[c];
@@ -688,6 +727,7 @@ void build_table(ldpc_plan* P, const PlanBuffers& B, char* ws) {
         T.postw = reinterpret_cast<float*>(base + R.postw);
         T.bits = reinterpret_cast<uint64_t*>(base + R.bits);
         T.unsat = reinterpret_cast<uint64_t*>(base + R.flags);
+        T.badw = reinterpret_cast<uint64_t*>(base + R.badw);
         T.frozen = T.unsat + R.flag_words;
         T.llr = B.llr[c];
         T.post = B.post[c];
@@ -706,7 +746,7 @@ void build_table(ldpc_plan* P, const PlanBuffers& B, char* ws) {
         T.vpw = layout_vpw(l);
         T.cpw = layout_cpw(l);
         // waves per tile: per base row (column), enough waves for its p rows (variables)
-        T.cn_wpt = g->J * ((g->p + rows_per_wave * T.cpw - 1) / (rows_per_wave * T.cpw));
+        T.cn_wpt = plan_cn_wpt(g, l);
         T.vn_wpt = g->L * ((g->p + rows_per_wave * T.vpw - 1) / (rows_per_wave * T.vpw));
         T.io_vchunks = (g->n + 63) / 64;
         T.io_fchunks = (R.tiles * R.Gt + 63) / 64;
@@ -715,12 +755,15 @@ void build_table(ldpc_plan* P, const PlanBuffers& B, char* ws) {
         T.syn0 = syn;
         T.st0 = st;
         T.io0 = io;
+        T.red0 = red;
         cn += (int64_t)T.tiles * T.cn_wpt;
         vn += (int64_t)T.tiles * T.vn_wpt;
         syn += ((int64_t)T.tiles * g->m + 63) / 64 * 64;
         st += ((int64_t)T.gamma + 63) / 64 * 64;
         io += (int64_t)T.io_vchunks * T.io_fchunks;
+        red += T.tiles;
     }
+    P->red_blocks = red;
     P->cn_waves = cn;
     P->vn_waves = vn;
     P->syn_threads = syn;
@@ -772,6 +815,10 @@ void enqueue(ldpc_plan* P, char* ws, hipStream_t st) {
         {
             timing::Scope ts(18, st);
             plan_cn_kernel<<<cn_grid, kBlock, 0, st>>>(T, nc, S);
+        }
+        if (P->early && it >= 2) {
+            timing::Scope ts(20, st);
+            plan_unsat_kernel<<<(unsigned)P->red_blocks, 256, 0, st>>>(T, nc, S);
         }
         {
             timing::Scope ts(19, st);
@@ -826,7 +873,7 @@ ldpc_status ldpc_plan_create(const ldpc_graph* const* graphs, const int32_t* gam
     for (int c = 0; c < ncodes; ++c) {
         P->layouts[c] = default_layout(graphs[c], gammas[c]);
         size_t most = 0;
-        for (int l = 0; l < kPlanLayouts; ++l)
+        for (int l = 0; l < 192; ++l)
             if (layout_allowed(graphs[c], l)) most = std::max(most, code_region(graphs[c], gammas[c], l, max_iters).total);
         P->region_off.push_back(off);
         off = align256(off + most);
