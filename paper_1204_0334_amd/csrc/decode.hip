@@ -220,25 +220,16 @@ __device__ __forceinline__ bool cn_tile_live(const BlockParams& P, int tile, int
     return !all;
 }
 
-// Record the frames whose decisions of iteration iter-1 violate the row (bad,
-// already masked to valid frames) in the row's own words of badw (lane f
-// writes word f); unsat_reduce_kernel ORs a tile's rows into unsat[iter-1].
-// Plain stores: every row of every tile would otherwise update the same few
-// flag words, and those updates serialise.
-template <int FPL>
-__device__ __forceinline__ void cn_record_bad(const BlockParams& P, int64_t wave, int lane,
-                                              const uint64_t (&bad)[FPL]) {
-    if (lane < FPL) P.badw[(size_t)wave * FPL + lane] = pick_word<FPL>(bad, lane);
-}
-
 // Horizontal step of iteration P.iter for the check row R and the 64*FPL
 // frames of the wave, reading beta from `src` (iteration 1: the channel LLRs
 // gathered from `mu`) and writing alpha to `dst` (which may be `src`: each
 // package belongs to one row).  RULE 0: sum-product (Eq. 3); RULE 1: learned
 // min-sum with the weights of P.nms_w.  SYN: with early stopping from
 // iteration 2 on, also test the row against iteration iter-1's packed
-// decisions; their loads are issued right after the message loads and the
-// flag update comes last, so the test adds no round trip before the work.
+// decisions and store the violated (valid) frames in the row's own words of
+// badw (lane f writes word f); unsat_reduce_kernel then ORs a tile's rows
+// into unsat[iter-1].  Plain stores: every row of every tile would otherwise
+// update the same few flag words, and those updates serialise.
 template <int DCMAX, int FPL, int RULE, bool SYN = false>
 __device__ __forceinline__ void cn_row(const QCDesc& D, const BlockParams& P, const QCRow& R, int tile, int lane,
                                        const float* src, const float* mu, float* dst, bool from_mu,
@@ -259,19 +250,17 @@ __device__ __forceinline__ void cn_row(const QCDesc& D, const BlockParams& P, co
             for (int f = 0; f < FPL; ++f) in[k][f] = 0.0f;
         }
     }
+    // syndrome: lane k*FPL + f loads decision word f of the row's variable k
+    // (one load instruction for the wave instead of d*FPL uniform ones), and
+    // an XOR butterfly over the lanes of equal f leaves parity word f in
+    // lane f
     const bool syn = SYN && P.early && P.iter >= 2;
-    uint64_t par[FPL];
-#pragma unroll
-    for (int f = 0; f < FPL; ++f) par[f] = 0;
+    uint64_t par = 0;
     if (syn) {
-        const uint64_t* bt = P.bits + (size_t)tile * D.n * FPL;
+        const int kk = lane / FPL, ff = lane - kk * FPL;
+        if (kk < R.d) par = P.bits[((size_t)tile * D.n + R.var(D, kk)) * FPL + ff];
 #pragma unroll
-        for (int k = 0; k < DCMAX; ++k) {
-            if (!R.valid(D, k)) continue;
-            const uint64_t* w = bt + (size_t)R.var(D, k) * FPL;
-#pragma unroll
-            for (int f = 0; f < FPL; ++f) par[f] ^= w[f];
-        }
+        for (int off = 32; off >= FPL; off >>= 1) par ^= __shfl_xor(par, off);
     }
     float outv[DCMAX][FPL];
     if constexpr (RULE == 0) {
@@ -303,11 +292,7 @@ __device__ __forceinline__ void cn_row(const QCDesc& D, const BlockParams& P, co
         for (int k = 0; k < DCMAX; ++k)
             if (R.valid(D, k)) store_frames<FPL>(dt + (size_t)R.pkg(D, k) * Gt, outv[k]);
     }
-    if (syn) {
-#pragma unroll
-        for (int f = 0; f < FPL; ++f) par[f] &= valid_word<FPL>(nvalid, f);
-        cn_record_bad<FPL>(P, wave, lane, par);
-    }
+    if (syn && lane < FPL) P.badw[(size_t)wave * FPL + lane] = par & valid_word<FPL>(nvalid, lane);
 }
 
 // Check-node pass of iteration P.iter (in place in P.msg; iteration 1 reads

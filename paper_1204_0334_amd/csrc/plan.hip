@@ -209,28 +209,38 @@ __device__ __forceinline__ void plan_cn_body(const PlanCode& C, const PlanStep& 
             }
         }
     }
-    // frames violating any of the wave's rows (OR over rows of each row's parity)
+    // frames violating any of the wave's rows: the decision words are spread
+    // over the lanes (one or a few loads per lane rather than d uniform ones)
+    // and combined by XOR butterflies (parity of a row) and OR (over rows)
     const bool syn = S.early && S.iter >= 2;
-    uint64_t par[FPL];
-#pragma unroll
-    for (int i = 0; i < FPL; ++i) par[i] = 0;
+    uint64_t par = 0;
     if (syn) {
         const uint64_t* bt = C.bits + (size_t)tile * D.n * FPL;
+        if constexpr (G == 64 && FPL > 1) {
+            // lane k*FPL + f: word f of variable k; lane f ends with parity word f
+            const int kk = lane / FPL, ff = lane - kk * FPL;
+            const PlanRow Rw(D, j, d[0] ? srow[0] : 0, d[0] > 0);
+            if (kk < d[0]) par = bt[(size_t)Rw.var(D, kk) * FPL + ff];
 #pragma unroll
-        for (int v = 0; v < V; ++v) {
-            const PlanRow Rw(D, j, d[v] ? srow[v] : 0, d[v] > 0);
-            uint64_t pr[FPL];
+            for (int off = 32; off >= FPL; off >>= 1) par ^= __shfl_xor(par, off);
+        } else {
+            // one frame per lane: lane f of a group of G lanes takes variables
+            // f, f + G, ... of its row; every lane ends with the wave's word
 #pragma unroll
-            for (int i = 0; i < FPL; ++i) pr[i] = 0;
+            for (int v = 0; v < V; ++v) {
+                const PlanRow Rw(D, j, d[v] ? srow[v] : 0, d[v] > 0);
+                uint64_t x = 0;
 #pragma unroll
-            for (int k = 0; k < DCMAX; ++k) {
-                if (k >= d[v]) continue;
-                const uint64_t* w = bt + (size_t)Rw.var(D, k) * FPL;
+                for (int q = 0; q < (DCMAX + G - 1) / G; ++q) {
+                    const int k = q * G + f;
+                    if (k < d[v]) x ^= bt[Rw.var(D, k)];
+                }
 #pragma unroll
-                for (int i = 0; i < FPL; ++i) pr[i] ^= w[i];
+                for (int off = G / 2; off >= 1; off >>= 1) x ^= __shfl_xor(x, off);
+                par |= x;
             }
 #pragma unroll
-            for (int i = 0; i < FPL; ++i) par[i] |= pr[i];
+            for (int off = 32; off >= G; off >>= 1) par |= __shfl_xor(par, off);
         }
     }
 #pragma unroll
@@ -242,22 +252,9 @@ __device__ __forceinline__ void plan_cn_body(const PlanCode& C, const PlanStep& 
         for (int k = 0; k < DCMAX; ++k)
             if (k < d[v]) store_frames<FPL>(mt + (size_t)Rw.pkg(D, k) * Gt, out[k]);
     }
-    if (syn) {
-        // the wave's violated frames go to its own words (plain stores; the
-        // flag word of the tile is formed by plan_unsat_kernel)
-        uint64_t* bw = C.badw + lw * FPL;
-        if constexpr (G == 64) {
-            uint64_t bad[FPL];
-#pragma unroll
-            for (int i = 0; i < FPL; ++i) bad[i] = par[i] & valid_word<FPL>(nvalid, i);
-            if (lane < FPL) bw[lane] = plan_pick<FPL>(bad, lane);
-        } else {
-            uint64_t v = par[0] & valid_word<1>(nvalid, 0);
-#pragma unroll
-            for (int off = 32; off >= 1; off >>= 1) v |= __shfl_xor(v, off);
-            if (lane == 0) bw[0] = v;
-        }
-    }
+    // the wave's violated frames go to its own words (plain stores; the flag
+    // word of the tile is formed by plan_unsat_kernel)
+    if (syn && lane < FPL) C.badw[lw * FPL + lane] = par & valid_word<FPL>(nvalid, lane);
 }
 
 // Variable-node pass of iteration S.iter for wave lw of code C: betas (not
