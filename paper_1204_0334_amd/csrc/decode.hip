@@ -545,14 +545,23 @@ __global__ void __launch_bounds__(256) block_output_kernel(const float* __restri
     }
 }
 
-// unsat[iter-1][tile][f] = OR over the tile's rows of badw (one block per
-// tile); a tile whose frames were all frozen by iteration iter-2 skipped its
-// check-node pass and keeps a zero word.
+// unsat[iter-1][tile][f] |= OR over the tile's rows of badw.  Block (tile,
+// chunk) reads kRedWords consecutive words of the tile (row r, word f at
+// r*FPL + f), each thread kRedPerThread independent ones, so the loads of a
+// block are in flight together instead of one round trip per row group.
+// 256 and kRedWords are multiples of FPL: a thread only meets words of
+// f = threadIdx.x % FPL.  The flag words are cleared at ingest and each
+// block adds its nonzero words with one atomicOr per f; a tile whose frames
+// were all frozen by iteration iter-2 skipped its check-node pass and keeps
+// a zero word.
+constexpr int kRedPerThread = 8;
+constexpr int kRedWords = 256 * kRedPerThread;
+
 template <int FPL>
-__global__ void __launch_bounds__(256) unsat_reduce_kernel(const QCDesc D, const BlockParams P) {
+__global__ void __launch_bounds__(256) unsat_reduce_kernel(const QCDesc D, const BlockParams P, int chunks) {
     __shared__ uint64_t part[4][FPL];
-    const int tile = blockIdx.x;
-    uint64_t* un = P.unsat + ((size_t)(P.iter - 1) * P.tiles + tile) * FPL;
+    const int tile = blockIdx.x / chunks;
+    const int chunk = blockIdx.x - tile * chunks;
     if (P.iter >= 3) {
         const uint64_t* fz = P.frozen + ((size_t)(P.iter - 2) * P.tiles + tile) * FPL;
         bool all = true;
@@ -560,27 +569,25 @@ __global__ void __launch_bounds__(256) unsat_reduce_kernel(const QCDesc D, const
         for (int f = 0; f < FPL; ++f) all = all && (fz[f] == ~0ull);
         if (all) return;
     }
-    uint64_t acc[FPL];
+    const int64_t nw = (int64_t)D.m * FPL;
+    const uint64_t* bw = P.badw + (size_t)tile * nw;
+    const int64_t w0 = (int64_t)chunk * kRedWords + threadIdx.x;
+    uint64_t acc = 0;
 #pragma unroll
-    for (int f = 0; f < FPL; ++f) acc[f] = 0;
-    const uint64_t* bw = P.badw + (size_t)tile * D.m * FPL;
-    for (int r = threadIdx.x; r < D.m; r += 256) {
-#pragma unroll
-        for (int f = 0; f < FPL; ++f) acc[f] |= bw[(size_t)r * FPL + f];
+    for (int k = 0; k < kRedPerThread; ++k) {
+        const int64_t w = w0 + (int64_t)k * 256;
+        if (w < nw) acc |= bw[w];
     }
 #pragma unroll
-    for (int f = 0; f < FPL; ++f) {
-#pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) acc[f] |= __shfl_xor(acc[f], off);
-    }
-    if ((threadIdx.x & 63) == 0) {
-#pragma unroll
-        for (int f = 0; f < FPL; ++f) part[threadIdx.x >> 6][f] = acc[f];
-    }
+    for (int off = 32; off >= FPL; off >>= 1) acc |= __shfl_xor(acc, off);
+    const int lane = threadIdx.x & 63;
+    if (lane < FPL) part[threadIdx.x >> 6][lane] = acc;
     __syncthreads();
     if (threadIdx.x < FPL) {
         const int f = threadIdx.x;
-        un[f] = part[0][f] | part[1][f] | part[2][f] | part[3][f];
+        const uint64_t v = part[0][f] | part[1][f] | part[2][f] | part[3][f];
+        if (v) atomicOr((unsigned long long*)(P.unsat + ((size_t)(P.iter - 1) * P.tiles + tile) * FPL + f),
+                        (unsigned long long)v);
     }
 }
 
@@ -1504,7 +1511,8 @@ static void run_block(const ldpc_graph* g, const float* llr, int gamma, int max_
         }
         if (early && it >= 2) {
             timing::Scope ts(3, st);
-            unsat_reduce_kernel<FPL><<<tl.tiles, 256, 0, st>>>(D, P);
+            const int chunks = (int)(((int64_t)D.m * FPL + kRedWords - 1) / kRedWords);
+            unsat_reduce_kernel<FPL><<<(unsigned)(tl.tiles * chunks), 256, 0, st>>>(D, P, chunks);
         }
         {
             timing::Scope ts(2, st);

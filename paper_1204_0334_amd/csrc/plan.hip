@@ -72,7 +72,8 @@ struct PlanCode {
     int vpw;              // variable-node launch: groups of R variables per wave (1, 2 or 4)
     int cpw;              // check-node launch: groups of R rows per wave (1, 2 or 4)
     uint64_t* badw;       // early stopping: [tiles * cn_wpt][FPL] frames violating each check wave's rows
-    int64_t red0;         // first block in the flag-reduction launch (one block per tile)
+    int64_t red0;         // first block in the flag-reduction launch (red_chunks blocks per tile)
+    int red_chunks;       // blocks per tile in the flag-reduction launch
 };
 
 struct PlanStep {
@@ -406,14 +407,23 @@ __global__ void __launch_bounds__(kBlock) plan_vn_kernel(const PlanCode* __restr
     }
 }
 
-// unsat[iter-1][tile] = OR of the tile's check-wave words (one block per
-// (code, tile)); a tile frozen by iteration iter-2 skipped its check pass and
-// keeps its zero word.
+// unsat[iter-1][tile] |= OR of the tile's check-wave words.  Block (code,
+// tile, chunk) reads kPlanRedWords consecutive words of the tile (wave w,
+// word i at w*fpl + i), kPlanRedPerThread independent loads per thread; 256
+// and kPlanRedWords are multiples of fpl, so a thread only meets words of
+// i = threadIdx.x % fpl.  The flag words are cleared at ingest and each block
+// adds its nonzero words with one atomicOr per i; a tile frozen by iteration
+// iter-2 skipped its check pass and keeps its zero word.
+constexpr int kPlanRedPerThread = 8;
+constexpr int kPlanRedWords = 256 * kPlanRedPerThread;
+
 __global__ void __launch_bounds__(256) plan_unsat_kernel(const PlanCode* __restrict__ codes, int ncodes,
                                                          PlanStep S) {
     __shared__ uint64_t part[4][4];
     const PlanCode& C = codes[plan_find(codes, ncodes, blockIdx.x, &PlanCode::red0)];
-    const int tile = (int)(blockIdx.x - C.red0);
+    const int64_t b = blockIdx.x - C.red0;
+    const int tile = (int)(b / C.red_chunks);
+    const int chunk = (int)(b - (int64_t)tile * C.red_chunks);
     if (tile >= C.tiles) return;
     const int fpl = C.fpl;
     if (S.iter >= 3) {
@@ -422,23 +432,24 @@ __global__ void __launch_bounds__(256) plan_unsat_kernel(const PlanCode* __restr
         for (int i = 0; i < fpl; ++i) all = all && (fz[i] == ~0ull);
         if (all) return;
     }
-    uint64_t acc[4] = {0, 0, 0, 0};
-    const uint64_t* bw = C.badw + (size_t)tile * C.cn_wpt * fpl;
-    for (int w = threadIdx.x; w < C.cn_wpt; w += 256)
-        for (int i = 0; i < fpl; ++i) acc[i] |= bw[(size_t)w * fpl + i];
+    const int64_t nw = (int64_t)C.cn_wpt * fpl;
+    const uint64_t* bw = C.badw + (size_t)tile * nw;
+    const int64_t w0 = (int64_t)chunk * kPlanRedWords + threadIdx.x;
+    uint64_t acc = 0;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-#pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) acc[i] |= __shfl_xor(acc[i], off);
+    for (int k = 0; k < kPlanRedPerThread; ++k) {
+        const int64_t w = w0 + (int64_t)k * 256;
+        if (w < nw) acc |= bw[w];
     }
-    if ((threadIdx.x & 63) == 0) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) part[threadIdx.x >> 6][i] = acc[i];
-    }
+    for (int off = 32; off >= fpl; off >>= 1) acc |= __shfl_xor(acc, off);
+    const int lane = threadIdx.x & 63;
+    if (lane < fpl) part[threadIdx.x >> 6][lane] = acc;
     __syncthreads();
     if ((int)threadIdx.x < fpl) {
         const int i = threadIdx.x;
-        C.unsat[((size_t)(S.iter - 1) * C.tiles + tile) * fpl + i] = part[0][i] | part[1][i] | part[2][i] | part[3][i];
+        const uint64_t v = part[0][i] | part[1][i] | part[2][i] | part[3][i];
+        if (v) atomicOr((unsigned long long*)(C.unsat + ((size_t)(S.iter - 1) * C.tiles + tile) * fpl + i),
+                        (unsigned long long)v);
     }
 }
 
@@ -753,12 +764,13 @@ void build_table(ldpc_plan* P, const PlanBuffers& B, char* ws) {
         T.st0 = st;
         T.io0 = io;
         T.red0 = red;
+        T.red_chunks = (int)(((int64_t)T.cn_wpt * T.fpl + kPlanRedWords - 1) / kPlanRedWords);
         cn += (int64_t)T.tiles * T.cn_wpt;
         vn += (int64_t)T.tiles * T.vn_wpt;
         syn += ((int64_t)T.tiles * g->m + 63) / 64 * 64;
         st += ((int64_t)T.gamma + 63) / 64 * 64;
         io += (int64_t)T.io_vchunks * T.io_fchunks;
-        red += T.tiles;
+        red += (int64_t)T.tiles * T.red_chunks;
     }
     P->red_blocks = red;
     P->cn_waves = cn;
