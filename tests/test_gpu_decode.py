@@ -287,7 +287,8 @@ def window_parity(gpu, ref, what):
 
 
 @pytest.mark.parametrize("p,positions,W,K,gamma,terminate", [(32, 16, 6, 10, 64, True), (17, 12, 3, 4, 100, True),
-                                                             (24, 9, 12, 5, 70, True), (16, 10, 4, 3, 65, False)])
+                                                             (24, 9, 12, 5, 70, True), (16, 10, 4, 3, 65, False),
+                                                             (16, 8, 3, 2, 1, True)])
 def test_window_decoder_small(p, positions, W, K, gamma, terminate):
     a = synth.draw_qc_shifts(3, 6, p, 2)
     Hc, info = oracle.unwrap_qc(a, p, positions, terminate=terminate)
@@ -336,7 +337,7 @@ def gpu_pipeline(g, llr, I):
 
 @pytest.mark.parametrize("p,positions,I,gamma,terminate", [(32, 16, 1, 64, True), (32, 16, 3, 70, True),
                                                            (17, 12, 8, 100, True), (24, 9, 20, 65, False),
-                                                           (16, 30, 12, 257, True)])
+                                                           (16, 30, 12, 257, True), (16, 8, 4, 1, True)])
 def test_pipeline_decoder_small(p, positions, I, gamma, terminate):
     a = synth.draw_qc_shifts(3, 6, p, 2)
     Hc, info = oracle.unwrap_qc(a, p, positions, terminate=terminate)

@@ -64,7 +64,7 @@ def check_decode(gpu, ref, what):
     assert err.max() <= TOL, f"{what}: posterior error {err.max():.3e}"
 
 
-@pytest.mark.parametrize("T,gamma", [(1, 64), (3, 64), (12, 64), (12, 200)])
+@pytest.mark.parametrize("T,gamma", [(1, 64), (3, 64), (12, 64), (12, 200), (4, 1), (5, 65)])
 def test_nms_decode_matches_reference(T, gamma):
     a, llr = case(3, 6, 64, 1, gamma, 2.0, 101)
     w = rand_weights(T, 3, T)

@@ -158,3 +158,36 @@ def test_autotune_keeps_results():
         assert (l >> 4) == 0 or base in (0, 1, 2, 3)
         assert (l >> 6) == 0 or g.info["dc_max"] <= 8
     assert_same(plan.decode(llrs, outs=outs, ws=ws), single_code(graphs, llrs, 20, True), "after autotune")
+
+
+def test_plan_at_the_code_limit_with_irregular_and_degenerate_codes():
+    # LDPC_PLAN_MAX_CODES codes: regular ones, an irregular code with zero
+    # blocks, a code with an unchecked variable and weight-1 checks, rows of
+    # weight 18 and 24, and batches of 1 .. 300 frames
+    irregular = np.array([[0, 5, -1, 7, 2, -1, 11, 3], [9, -1, 4, 1, -1, 6, 0, -1],
+                          [-1, 2, 8, -1, 10, 12, -1, 5], [3, 7, -1, -1, 1, -1, 9, 0]])
+    degenerate = np.array([[0, -1], [3, -1]])
+    tables = [(irregular, 13), (degenerate, 5),
+              (np.random.default_rng(54).integers(0, 17, size=(3, 18)), 17),
+              (np.random.default_rng(96).integers(0, 13, size=(4, 24)), 13)]
+    for i, c in enumerate(RAGGED + synth.MIXED_CODES[:5]):
+        tables.append((synth.draw_qc_shifts(c["J"], c["L"], c["p"], 70 + i), c["p"]))
+    assert len(tables) == 16
+    gammas = [1, 70, 300, 2, 64, 65, 3, 129, 31, 256, 5, 1, 200, 17, 8, 97]
+    graphs = [ldpc.Graph.qc(a, p) for a, p in tables]
+    llrs = []
+    for i, (g, n_frames) in enumerate(zip(graphs, gammas)):
+        s2 = synth.ebn0_to_sigma2(3.0, 0.5)
+        x = ldpc.awgn_llr(g.n, n_frames, s2, 3000 + i, 0, device=DEV)
+        if i == 1:
+            x[1] = 100.0
+            x[2] = -100.0
+            x[3] = 0.0
+        llrs.append(x)
+    for early in (True, False):
+        print(f"[gpu] 16-code plan early={early}", flush=True)
+        plan = ldpc.Plan(graphs, gammas, 12, early_stop=early)
+        outs = plan.decode(llrs)
+        assert_same(outs, single_code(graphs, llrs, 12, early), f"16 codes early={early}")
+    with pytest.raises(Exception):
+        ldpc.Plan(graphs + graphs[:1], gammas + [1], 12)
