@@ -1119,26 +1119,42 @@ __global__ void __launch_bounds__(kBlock) conv_vn_kernel(const ConvDesc D, const
 }
 
 // Variable-node launch that also returns the posterior and decisions of unit
-// U.out_unit in the caller's frame-major layout [gamma][positions * c], through
-// LDS as in the block decoder: 16 waves cover 64 consecutive columns.
+// U.out_unit in the caller's frame-major layout [gamma][positions * c].  The
+// first out_blocks blocks take the output unit's columns through LDS as in
+// the block decoder (16 waves cover 64 consecutive columns); the blocks after
+// them update the other units' columns, one column per wave, as
+// conv_vn_kernel does.
 template <int DVMAX, int FPL>
 __global__ void __launch_bounds__(kOutBlock) conv_vn_out_kernel(const ConvDesc D, const ConvSlots S,
                                                                 const ConvUnits U, const ConvParams P, float* post,
-                                                                uint8_t* bits_out) {
+                                                                uint8_t* bits_out, int out_blocks) {
     constexpr int Gt = 64 * FPL;
     __shared__ float Ls[kOutVars][Gt + 1];
     const int lane = threadIdx.x & 63;
     const int wv = wave_in_block();
-    const int nchunks = (P.rows + kOutVars - 1) / kOutVars;
+    if ((int)blockIdx.x >= out_blocks) {
+        // plain columns: every unit but the output one
+        const int plain = P.rows - D.c;
+        const int64_t w = (int64_t)(blockIdx.x - out_blocks) * (kOutBlock / 64) + wv;
+        const int tile = (int)(w / plain);
+        if (tile >= P.tiles) return;
+        const int idx = (int)(w - (int64_t)tile * plain);
+        const int col = idx < U.out_unit * D.c ? idx : idx + D.c;
+        const ConvCol C(D, U, col);
+        float L[FPL];
+        conv_vn_column<DVMAX, FPL>(D, S, U, P, C, tile, lane, L);
+        return;
+    }
+    const int nchunks = (D.c + kOutVars - 1) / kOutVars;
     const int tile = blockIdx.x / nchunks;
-    const int c0 = (blockIdx.x - tile * nchunks) * kOutVars;
+    const int u0 = U.out_unit * D.c;
+    const int c0 = (blockIdx.x - tile * nchunks) * kOutVars;      // column within the output unit
     constexpr int per_wave = kOutVars / (kOutBlock / 64);
 #pragma unroll 1
     for (int i = 0; i < per_wave; ++i) {
         const int vs = wv * per_wave + i;
-        const int col = c0 + vs;
-        if (col >= P.rows) break;
-        const ConvCol C(D, U, col);
+        if (c0 + vs >= D.c) break;
+        const ConvCol C(D, U, u0 + c0 + vs);
         float L[FPL];
         conv_vn_column<DVMAX, FPL>(D, S, U, P, C, tile, lane, L);
 #pragma unroll
@@ -1146,10 +1162,9 @@ __global__ void __launch_bounds__(kOutBlock) conv_vn_out_kernel(const ConvDesc D
     }
     __syncthreads();
     const int var = threadIdx.x & (kOutVars - 1);
-    const int col = c0 + var;
-    if (col >= P.rows || col / D.c != U.out_unit) return;
+    if (c0 + var >= D.c) return;
     const int64_t ld = (int64_t)D.positions * D.c;
-    const int64_t oc = (int64_t)U.pos[U.out_unit] * D.c + (col - U.out_unit * D.c);
+    const int64_t oc = (int64_t)U.pos[U.out_unit] * D.c + c0 + var;
     const int nvalid = min(P.gamma - tile * Gt, Gt);
     for (int fr = threadIdx.x / kOutVars; fr < nvalid; fr += kOutBlock / kOutVars) {
         const float L = Ls[var][fr];
@@ -1769,8 +1784,11 @@ struct ConvRun {
         ConvParams Pv = P;
         Pv.rows = U.n * D.c;
         if (U.out_unit >= 0) {
-            const unsigned grid = (unsigned)(((Pv.rows + kOutVars - 1) / kOutVars) * tl.tiles);
-            LDPC_DV_SWITCH(dvc, (conv_vn_out_kernel<DV, FPL><<<grid, kOutBlock, 0, st>>>(D, S, U, Pv, post, bits)));
+            const int out_blocks = ((D.c + kOutVars - 1) / kOutVars) * tl.tiles;
+            const int64_t plain_waves = (int64_t)(Pv.rows - D.c) * tl.tiles;
+            const unsigned grid = (unsigned)(out_blocks + (plain_waves + kOutBlock / 64 - 1) / (kOutBlock / 64));
+            LDPC_DV_SWITCH(dvc, (conv_vn_out_kernel<DV, FPL>
+                                 <<<grid, kOutBlock, 0, st>>>(D, S, U, Pv, post, bits, out_blocks)));
         } else {
             LDPC_DV_SWITCH(dvc, (conv_vn_kernel<DV, FPL>
                                  <<<grid_for_waves((int64_t)Pv.rows * tl.tiles), kBlock, 0, st>>>(D, S, U, Pv)));
