@@ -591,19 +591,21 @@ __global__ void __launch_bounds__(256) unsat_reduce_kernel(const QCDesc D, const
     }
 }
 
-// Syndrome of the decisions in P.bits for iteration P.iter (one thread per
-// check row and tile; the wave ORs its rows before one atomic per word).
+// Syndrome of the decisions in P.bits for iteration P.iter: block b covers
+// rows (b % bpt)*256 .. +255 of tile b / bpt (bpt blocks per tile, so a block
+// never straddles two tiles); the block ORs its rows' violated frames through
+// LDS and adds them with one atomicOr per word (the flag words are cleared at
+// ingest).
 template <int FPL>
-__global__ void __launch_bounds__(kBlock) syndrome_kernel(const QCDesc D, const BlockParams P) {
+__global__ void __launch_bounds__(kBlock) syndrome_kernel(const QCDesc D, const BlockParams P, int bpt) {
     constexpr int Gt = 64 * FPL;
-    const int gid = blockIdx.x * kBlock + threadIdx.x;
-    const int tile = gid / D.m;
-    const int row = gid - tile * D.m;
+    __shared__ uint64_t part[kWavesPerBlock][FPL];
+    const int tile = blockIdx.x / bpt;
+    const int row = (blockIdx.x - tile * bpt) * kBlock + threadIdx.x;
     uint64_t par[FPL];
 #pragma unroll
     for (int f = 0; f < FPL; ++f) par[f] = 0;
-    const bool live = tile < P.tiles;
-    if (live) {
+    if (row < D.m) {
         const QCRow R(D, row);
         const uint64_t* bt = P.bits + (size_t)tile * D.n * FPL;
         const int nvalid = min(P.gamma - tile * Gt, Gt);
@@ -615,23 +617,22 @@ __global__ void __launch_bounds__(kBlock) syndrome_kernel(const QCDesc D, const 
 #pragma unroll
         for (int f = 0; f < FPL; ++f) par[f] &= valid_word<FPL>(nvalid, f);
     }
-    // rows of one wave may straddle two tiles: reduce per tile of lane 0 and
-    // let lanes of another tile issue their own atomics
-    const int tile0 = __shfl(tile, 0);
-    const bool same = (tile == tile0);
+    const int lane = threadIdx.x & 63;
 #pragma unroll
     for (int f = 0; f < FPL; ++f) {
-        uint64_t v = same ? par[f] : 0;
+        uint64_t v = par[f];
 #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) v |= __shfl_xor(v, off);
-        if (live) {
-            uint64_t* un = P.unsat + ((size_t)P.iter * P.tiles + tile) * FPL + f;
-            if (same) {
-                if ((threadIdx.x & 63) == 0 && v) atomicOr((unsigned long long*)un, (unsigned long long)v);
-            } else if (par[f]) {
-                atomicOr((unsigned long long*)un, (unsigned long long)par[f]);
-            }
-        }
+        if (lane == 0) part[threadIdx.x >> 6][f] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < FPL) {
+        const int f = threadIdx.x;
+        uint64_t v = 0;
+#pragma unroll
+        for (int w = 0; w < kWavesPerBlock; ++w) v |= part[w][f];
+        if (v) atomicOr((unsigned long long*)(P.unsat + ((size_t)P.iter * P.tiles + tile) * FPL + f),
+                        (unsigned long long)v);
     }
 }
 
@@ -1548,8 +1549,8 @@ static void run_block(const ldpc_graph* g, const float* llr, int gamma, int max_
     P.iter = max_iters;
     {
         timing::Scope ts(3, st);
-        const int64_t threads = (int64_t)D.m * tl.tiles;
-        syndrome_kernel<FPL><<<(unsigned)((threads + kBlock - 1) / kBlock), kBlock, 0, st>>>(D, P);
+        const int bpt = (D.m + kBlock - 1) / kBlock;
+        syndrome_kernel<FPL><<<(unsigned)((int64_t)bpt * tl.tiles), kBlock, 0, st>>>(D, P, bpt);
     }
     if (iters || converged) {
         timing::Scope ts(5, st);
