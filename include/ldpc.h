@@ -320,6 +320,13 @@ ldpc_status ldpc_plan_autotune(ldpc_plan* plan, const float* const* llr, float* 
  *   post  device, float [gamma][positions * c]: clip(posterior, +-30)
  *   bits  device, uint8 [gamma][positions * c]
  *   W     window length in positions, ms + 1 <= W <= 64
+ * Execution: when one stream's ring (the messages and channel LLRs of the
+ * W + ms positions a window holds) fits the device's LDS per workgroup, each
+ * stream is decoded from start to end by one workgroup out of LDS (one
+ * launch); otherwise every phase is a launch over all streams, with the
+ * ring in the workspace.  Both give the same results bit for bit; the
+ * environment variable LDPC_WINDOW_PATH=launch (or =lds) selects one.  The
+ * workspace size is that of the launch-per-phase form in either case.
  * Errors: EINVAL (QC graph, W < ms+1, iters_per_window < 1, NULL pointers),
  * EWORKSPACE, EHIP.
  */
@@ -388,10 +395,11 @@ const char* ldpc_status_str(ldpc_status s);
  *   variable-node, 14 training variable-node backward, 15 training
  *   check-node backward, 16 training loss and gradient reductions,
  *   17 plan ingest, 18 plan check-node, 19 plan variable-node, 20 plan
- *   final syndrome, frame status and output.
+ *   final syndrome, frame status and output, 21 window decoding with the
+ *   ring in LDS (one launch per call).
  * ldpc_kernel_class_name returns a static name for a class index.
  */
-#define LDPC_TIMING_CLASSES 21
+#define LDPC_TIMING_CLASSES 22
 ldpc_status ldpc_timing_enable(int32_t enable);
 ldpc_status ldpc_timing_read(int64_t* launches, double* total_ms, int32_t capacity);
 const char* ldpc_kernel_class_name(int32_t cls);

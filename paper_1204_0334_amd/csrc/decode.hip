@@ -40,6 +40,7 @@
 
 #include <algorithm>
 #include <cstdlib>
+#include <cstring>
 #include <mutex>
 #include <vector>
 
@@ -1227,6 +1228,220 @@ __global__ void __launch_bounds__(kIngestBlock) conv_ingest_kernel(const ConvDes
     }
 }
 
+// Sliding-window decoding with one workgroup per frame and the frame's ring
+// in LDS: msg [R][eps] (the edge messages of the R = W + ms positions the
+// window holds, in the ring layout of the launch-per-phase kernels with one
+// frame per package) and mu [R][c].  A workgroup runs every slide of its
+// frame: the entering positions are read from the caller's LLRs (mu, and
+// beta = clip(mu) on their edges), then K flooding iterations (check rows of
+// layers s..s+W-1, barrier, variable columns of positions s..s+W-1,
+// barrier), and the last one writes position s to the caller's buffers.
+// Everything about an edge except the row's (column's) offset within its
+// circulant is shared by the p rows (columns) of that circulant, so it is
+// worked out once per slide into small LDS tables: for check unit u and
+// circulant row rr, the ring offset of edge slot e (or -1 where the edge
+// does not exist); for variable unit u and circulant column q, the ring
+// offset and shift of slot e.  The per-row and per-column arithmetic is that
+// of conv_cn_kernel and conv_vn_column, in the same order, so the results
+// are the same bit for bit.  Frames never interact and no workgroup waits
+// for another.
+constexpr int kWinBlock = 1024;
+
+template <int DCMAX, int DVMAX>
+__host__ __device__ constexpr size_t window_lds_tables(int W, int Jb, int Lb) {
+    return (size_t)W * Jb * DCMAX + 2 * (size_t)W * Lb * DVMAX;
+}
+
+// a / b for 0 <= a < 2^22 and 0 < b: the float quotient is within one of
+// the exact one, and one integer step corrects it
+__device__ __forceinline__ int div_small(int a, int b, float inv_b) {
+    int q = (int)((float)a * inv_b);
+    const int r = a - q * b;
+    q = r < 0 ? q - 1 : (r >= b ? q + 1 : q);
+    return q;
+}
+
+template <int DCMAX, int DVMAX>
+__global__ void __launch_bounds__(kWinBlock) window_lds_kernel(const ConvDesc D, const ConvSlots S, int R, int W,
+                                                               int K, const float* __restrict__ llr,
+                                                               float* __restrict__ post, uint8_t* __restrict__ bits_out) {
+    extern __shared__ float lds[];
+    // the shift table, indexed per lane below: from LDS, not from the
+    // kernel arguments (a per-lane index into those becomes a memory load)
+    __shared__ int sfl[LDPC_MAX_BLOCKS];
+    const int nsf = D.T * (D.ms + 1) * D.Jb * D.Lb;
+    for (int i = threadIdx.x; i < nsf; i += kWinBlock) sfl[i] = D.sf[i];
+    auto sf = [&](int cls, int dd, int rr, int q) { return sfl[((cls * (D.ms + 1) + dd) * D.Jb + rr) * D.Lb + q]; };
+    const int eps = (D.ms + 1) * D.Jb * D.Lb * D.p;
+    float* msg = lds;
+    float* mu = msg + (size_t)R * eps;
+    int* ctab = reinterpret_cast<int*>(mu + (size_t)R * D.c);    // [W][Jb][DCMAX]
+    int* vtab = ctab + (size_t)W * D.Jb * DCMAX;                  // [W][Lb][DVMAX]
+    int* vsh = vtab + (size_t)W * D.Lb * DVMAX;                   // [W][Lb][DVMAX]
+    const int64_t ld = (int64_t)D.positions * D.c;
+    const size_t frame_off = (size_t)blockIdx.x * ld;
+    const float* x = llr + frame_off;
+    const int ncs = (D.ms + 1) * D.Lb;      // edge slots of a check row
+    const int nvs = (D.ms + 1) * D.Jb;      // edge slots of a variable column
+    const int per = D.Jb * D.p;             // check rows per layer
+    int cdd[DCMAX], vdd[DVMAX];
+#pragma unroll
+    for (int e = 0; e < DCMAX; ++e) cdd[e] = S.cn_dd[e < ncs ? e : 0];
+#pragma unroll
+    for (int e = 0; e < DVMAX; ++e) vdd[e] = S.vn_dd[e < nvs ? e : 0];
+    const float inv_per = 1.0f / (float)per, inv_p = 1.0f / (float)D.p, inv_c = 1.0f / (float)D.c;
+    __syncthreads();
+    for (int s = 0; s < D.positions; ++s) {
+        const int lay_hi = min(s + W - 1, D.layers - 1);
+        const int pos_hi = min(s + W - 1, D.positions - 1);
+        const int in_lo = (s == 0) ? 0 : s + W - 1;
+        const int ncu = lay_hi - s + 1, nvu = pos_hi - s + 1;
+        if (in_lo <= pos_hi) {
+            const int ncols = (pos_hi - in_lo + 1) * D.c;
+            for (int i = threadIdx.x; i < ncols; i += kWinBlock) {
+                const int pu = i / D.c;
+                const int rem = i - pu * D.c;
+                const int t = in_lo + pu;
+                const int q = rem / D.p, uu = rem - q * D.p;
+                const int slot = t % R;
+                const float m = x[(int64_t)t * D.c + rem];
+                mu[slot * D.c + rem] = m;
+                const float b = clip30(m);
+                const int jc = t % D.T;
+                for (int k = 0; k < nvs; ++k) {
+                    const int dd = S.vn_dd[k], rr = S.vn_rr[k];
+                    if (t + dd >= D.layers) continue;
+                    int ic = jc + dd;
+                    while (ic >= D.T) ic -= D.T;
+                    const int a = sf(ic, dd, rr, q);
+                    if (a < 0) continue;
+                    int sidx = uu - a;
+                    if (sidx < 0) sidx += D.p;
+                    msg[slot * eps + ((dd * D.Jb + rr) * D.Lb + q) * D.p + sidx] = b;
+                }
+            }
+        }
+        // this slide's edge tables
+        for (int i = threadIdx.x; i < ncu * D.Jb * DCMAX; i += kWinBlock) {
+            const int e = i % DCMAX, ur = i / DCMAX;
+            const int u = ur / D.Jb, rr = ur - u * D.Jb;
+            int v = -1;
+            if (e < ncs) {
+                const int tau = s + u, dd = S.cn_dd[e], q = S.cn_q[e];
+                const int tp = tau - dd;
+                if (tp >= 0 && tp < D.positions && sf(tau % D.T, dd, rr, q) >= 0) {
+                    int sl = tau % R - dd;
+                    if (sl < 0) sl += R;
+                    v = sl * eps + ((dd * D.Jb + rr) * D.Lb + q) * D.p;
+                }
+            }
+            ctab[i] = v;
+        }
+        for (int i = threadIdx.x; i < nvu * D.Lb * DVMAX; i += kWinBlock) {
+            const int e = i % DVMAX, uq = i / DVMAX;
+            const int u = uq / D.Lb, q = uq - u * D.Lb;
+            int v = -1, sh = 0;
+            if (e < nvs) {
+                const int tpos = s + u, dd = S.vn_dd[e], rr = S.vn_rr[e];
+                int ic = tpos % D.T + dd;
+                while (ic >= D.T) ic -= D.T;
+                const int a = sf(ic, dd, rr, q);
+                if (tpos + dd < D.layers && a >= 0) {
+                    v = (tpos % R) * eps + ((dd * D.Jb + rr) * D.Lb + q) * D.p;
+                    sh = a;
+                }
+            }
+            vtab[i] = v;
+            vsh[i] = sh;
+        }
+        __syncthreads();
+        const int rows = ncu * per;
+        const int cols = nvu * D.c;
+        const int sR = s % R;
+        for (int k = 1; k <= K; ++k) {
+            // check rows: unit u = layer s + u, circulant row rr, offset so
+            for (int r = threadIdx.x; r < rows; r += kWinBlock) {
+                const int u = div_small(r, per, inv_per);
+                const int rem = r - u * per;
+                const int rr = div_small(rem, D.p, inv_p), so = rem - rr * D.p;
+                const int* tb = ctab + (u * D.Jb + rr) * DCMAX;
+                float in[DCMAX], t[DCMAX], q[DCMAX];
+                int idx[DCMAX];
+                uint32_t sgn = 0;
+#pragma unroll
+                for (int e = 0; e < DCMAX; ++e) {
+                    const int o = tb[e];
+                    idx[e] = o < 0 ? -1 : o + so;
+                    in[e] = o < 0 ? 0.0f : msg[o + so];
+                }
+#pragma unroll
+                for (int e = 0; e < DCMAX; ++e) {
+                    if (idx[e] >= 0) {
+                        tq_of(in[e], t[e], q[e]);
+                        sgn ^= __float_as_uint(in[e]) & 0x80000000u;
+                    } else {
+                        t[e] = 1.0f;
+                        q[e] = 0.0f;
+                    }
+                }
+                float mag[DCMAX];
+                boxplus_fb<DCMAX>(t, q, mag);
+#pragma unroll
+                for (int e = 0; e < DCMAX; ++e) {
+                    if (idx[e] >= 0 && u >= cdd[e]) {     // position s + u - dd is not frozen
+                        const uint32_t sg = sgn ^ (__float_as_uint(in[e]) & 0x80000000u);
+                        msg[idx[e]] = __uint_as_float(__float_as_uint(mag[e]) | sg);
+                    }
+                }
+            }
+            __syncthreads();
+            // variable columns: unit u = position s + u, circulant column q, offset uu
+            for (int cidx = threadIdx.x; cidx < cols; cidx += kWinBlock) {
+                const int u = div_small(cidx, D.c, inv_c);
+                const int rem = cidx - u * D.c;
+                const int q = div_small(rem, D.p, inv_p), uu = rem - q * D.p;
+                int slot = sR + u;
+                if (slot >= R) slot -= R;
+                const float m = mu[slot * D.c + rem];
+                const int* tb = vtab + (u * D.Lb + q) * DVMAX;
+                const int* shb = vsh + (u * D.Lb + q) * DVMAX;
+                float a[DVMAX];
+                int idx[DVMAX];
+#pragma unroll
+                for (int e = 0; e < DVMAX; ++e) {
+                    const int o = tb[e];
+                    int so = uu - shb[e];
+                    if (so < 0) so += D.p;
+                    idx[e] = o < 0 ? -1 : o + so;
+                    // only messages from window layers (s + u + dd <= lay_hi) are summed
+                    a[e] = (o >= 0 && u + vdd[e] <= lay_hi - s) ? msg[o + so] : 0.0f;
+                }
+                float suf[DVMAX];
+                float Ssum = 0.0f;
+#pragma unroll
+                for (int e = DVMAX - 1; e >= 0; --e) {
+                    suf[e] = Ssum;
+                    Ssum += a[e];
+                }
+                float pre = 0.0f;
+#pragma unroll
+                for (int e = 0; e < DVMAX; ++e) {
+                    const float b = clip30(m + (pre + suf[e]));
+                    pre += a[e];
+                    if (idx[e] >= 0) msg[idx[e]] = b;
+                }
+                if (k == K && u == 0) {
+                    const float L = m + pre;
+                    const size_t o = frame_off + (size_t)s * D.c + rem;
+                    post[o] = clip30(L);
+                    bits_out[o] = (uint8_t)(L < 0.0f);
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // kernels: simulation (channel LLRs and error counts on the GPU, Sec. V-B)
 // ---------------------------------------------------------------------------
@@ -1873,6 +2088,61 @@ static void run_pipeline(ConvRun& r, int I) {
     }
 }
 
+// The window decoder with one workgroup per stream and its ring in LDS
+// (window_lds_kernel), when the ring fits the device's LDS per workgroup and
+// the row / column weights have an instantiation; false if the caller must
+// use the launch-per-phase form (nothing enqueued then).
+template <int DC, int DV>
+static bool launch_window_lds(const ldpc_graph* g, const float* llr, int gamma, int W, int K, float* post,
+                              uint8_t* bits, int R, size_t bytes, hipStream_t st) {
+    // bytes: the ring; the edge tables are added here
+    bytes += window_lds_tables<DC, DV>(W, g->Jb, g->Lb) * sizeof(int);
+    int dev = 0, limit = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&limit, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    if (bytes + LDPC_MAX_BLOCKS * sizeof(int) > (size_t)limit) return false;
+    // row and column indices of a window stay below 2^22 (div_small)
+    const int wl = std::min(W, g->positions + g->ms);
+    if ((int64_t)wl * std::max(g->Jb, g->Lb) * g->p >= ((int64_t)1 << 22)) return false;
+    const void* fn = reinterpret_cast<const void*>(&window_lds_kernel<DC, DV>);
+    if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    timing::Scope ts(21, st);
+    window_lds_kernel<DC, DV><<<(unsigned)gamma, kWinBlock, bytes, st>>>(g->cv, conv_slots(g), R, W, K, llr, post,
+                                                                         bits);
+    return true;
+}
+
+static bool window_lds(const ldpc_graph* g, const float* llr, int gamma, int W, int K, float* post, uint8_t* bits,
+                       hipStream_t st) {
+    const char* env = std::getenv("LDPC_WINDOW_PATH");
+    if (env && std::strcmp(env, "launch") == 0) return false;
+    const int R = window_ring(g, W);
+    const size_t eps = (size_t)(g->ms + 1) * g->Jb * g->Lb * g->p;
+    const size_t c = (size_t)g->Lb * g->p;
+    const size_t bytes = (size_t)R * (eps + c) * sizeof(float);
+    const int dcc = dc_class((g->ms + 1) * g->Lb), dvc = dv_class((g->ms + 1) * g->Jb);
+    if (dcc > 8 || dvc > 4) return false;
+    bool done = false;
+    switch (dcc) {
+        case 4: LDPC_DV_SWITCH(dvc, if constexpr (DV <= 4) {
+                    done = launch_window_lds<4, DV>(g, llr, gamma, W, K, post, bits, R, bytes, st);
+                }); break;
+        case 6: LDPC_DV_SWITCH(dvc, if constexpr (DV <= 4) {
+                    done = launch_window_lds<6, DV>(g, llr, gamma, W, K, post, bits, R, bytes, st);
+                }); break;
+        default: LDPC_DV_SWITCH(dvc, if constexpr (DV <= 4) {
+                    done = launch_window_lds<8, DV>(g, llr, gamma, W, K, post, bits, R, bytes, st);
+                }); break;
+    }
+    return done;
+}
+
 }  // namespace ldpc
 
 using namespace ldpc;
@@ -2021,8 +2291,10 @@ ldpc_status ldpc_decode_window(const ldpc_graph* g, const float* llr, int32_t ga
     if (!workspace || workspace_bytes < lay.total) return LDPC_EWORKSPACE;
     if (reinterpret_cast<uintptr_t>(workspace) & 255) return LDPC_EINVAL;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    ConvRun r = make_conv_run(g, llr, gamma, post, bits, reinterpret_cast<char*>(workspace), lay, tl, st);
     (void)hipGetLastError();
+    if (window_lds(g, llr, gamma, W, iters_per_window, post, bits, st))
+        return hipGetLastError() == hipSuccess ? LDPC_OK : LDPC_EHIP;
+    ConvRun r = make_conv_run(g, llr, gamma, post, bits, reinterpret_cast<char*>(workspace), lay, tl, st);
     switch (tl.fpl) {
         case 4: run_window<4>(r, W, iters_per_window); break;
         case 2: run_window<2>(r, W, iters_per_window); break;
@@ -2110,7 +2382,8 @@ const char* ldpc_kernel_class_name(int32_t cls) {
         "output",          "frame_status",      "window_ingest",        "window_check_node",
         "window_variable_node", "pipeline_ingest", "pipeline_check_node", "pipeline_variable_node",
         "train_check_node", "train_variable_node", "train_variable_node_backward", "train_check_node_backward",
-        "train_reduce", "plan_ingest", "plan_check_node", "plan_variable_node", "plan_finish"};
+        "train_reduce", "plan_ingest", "plan_check_node", "plan_variable_node", "plan_finish",
+        "window_lds"};
     if (cls < 0 || cls >= LDPC_TIMING_CLASSES) return "unknown";
     return names[cls];
 }

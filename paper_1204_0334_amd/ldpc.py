@@ -38,7 +38,7 @@ def layout_name(layout: int) -> str:
     v, c = (layout >> 4) & 3, (layout >> 6) & 3
     return LAYOUT_NAMES[layout & 15] + ("" if v == 0 else f"/VN{1 << v}") + ("" if c == 0 else f"/CN{1 << c}")
 PLAN_MAX_CODES = 16
-TIMING_CLASSES = 21
+TIMING_CLASSES = 22
 MAX_ITERS = 100000
 
 

@@ -6,6 +6,8 @@ Tolerance (FP32 GPU vs FP64 reference, LLRs clipped at 30):
 iteration counts are compared exactly except on frames where the reference
 met some |L| < 1e-3 at a decision (there the sign is decided by rounding).
 """
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -321,6 +323,44 @@ def test_window_decoder_paper_scale_sampled_streams():
     # a 6-position window leaves residual errors at 1.5 dB (the full chain
     # decodes under flooding BP); the bit error rate stays low
     assert gpu["bits"].mean() < 1e-2
+
+
+def window_path(path, g, x, W, K):
+    # LDPC_WINDOW_PATH is read by ldpc_decode_window at every call
+    old = os.environ.get("LDPC_WINDOW_PATH")
+    os.environ["LDPC_WINDOW_PATH"] = path
+    try:
+        ldpc.timing_read()
+        ldpc.timing_enable(True)
+        post, bits = ldpc.decode_window(g, x, W, K)
+        torch.cuda.synchronize()
+        ldpc.timing_enable(False)
+        t = ldpc.timing_read()
+    finally:
+        if old is None:
+            del os.environ["LDPC_WINDOW_PATH"]
+        else:
+            os.environ["LDPC_WINDOW_PATH"] = old
+    return post, bits, t
+
+
+@pytest.mark.parametrize("p,positions,W,K,gamma,terminate", [(32, 16, 6, 10, 64, True), (17, 12, 3, 4, 100, True),
+                                                             (24, 9, 12, 5, 70, True), (16, 10, 4, 3, 65, False),
+                                                             (16, 8, 3, 2, 1, True), (512, 128, 6, 10, 512, True)])
+def test_window_lds_and_launch_paths_agree_bit_for_bit(p, positions, W, K, gamma, terminate):
+    # one workgroup per stream with the ring in LDS vs one launch per phase
+    # with the ring in the workspace: same arithmetic in the same order
+    a = synth.draw_qc_shifts(3, 6, p, 2)
+    g = ldpc.Graph.ldpccc_from_qc(a, p, positions, terminate)
+    print(f"[gpu] window paths n={g.n} gamma={gamma} W={W} K={K}", flush=True)
+    s2 = synth.ebn0_to_sigma2(1.5, 0.5)
+    x = ldpc.awgn_llr(g.n, gamma, s2, 7 + p, 0, device=DEV)
+    post_l, bits_l, t_l = window_path("lds", g, x, W, K)
+    post_m, bits_m, t_m = window_path("launch", g, x, W, K)
+    assert t_l["window_lds"][0] == 1 and t_l["window_check_node"][0] == 0, t_l
+    assert t_m["window_lds"][0] == 0 and t_m["window_check_node"][0] > 0, t_m
+    assert torch.equal(bits_l, bits_m)
+    assert torch.equal(post_l, post_m)
 
 
 # ----------------------------------------------------------------------------
