@@ -1246,6 +1246,7 @@ __global__ void __launch_bounds__(kIngestBlock) conv_ingest_kernel(const ConvDes
 // are the same bit for bit.  Frames never interact and no workgroup waits
 // for another.
 constexpr int kWinBlock = 1024;
+constexpr int kNoEdge = -(1 << 30);     // variable-edge table: no such edge
 
 template <int DCMAX, int DVMAX>
 __host__ __device__ constexpr size_t window_lds_tables(int W, int Jb, int Lb) {
@@ -1290,6 +1291,16 @@ __global__ void __launch_bounds__(kWinBlock) window_lds_kernel(const ConvDesc D,
 #pragma unroll
     for (int e = 0; e < DVMAX; ++e) vdd[e] = S.vn_dd[e < nvs ? e : 0];
     const float inv_per = 1.0f / (float)per, inv_p = 1.0f / (float)D.p, inv_c = 1.0f / (float)D.c;
+    // When the block size is a multiple of the rows per layer (columns per
+    // position), a thread's rows (columns) r = threadIdx.x + j * kWinBlock
+    // all have the same offset within their layer (position) and consecutive
+    // units kWinBlock / per apart: split once here.
+    const bool rows_fixed = kWinBlock % per == 0, cols_fixed = kWinBlock % D.c == 0;
+    const int rstep = rows_fixed ? kWinBlock / per : 1, cstep = cols_fixed ? kWinBlock / D.c : 1;
+    const int ru0 = threadIdx.x / per, rrem0 = threadIdx.x - ru0 * per;
+    const int rr0 = rrem0 / D.p, so0 = rrem0 - rr0 * D.p;
+    const int cu0 = threadIdx.x / D.c, crem0 = threadIdx.x - cu0 * D.c;
+    const int cq0 = crem0 / D.p, cuu0 = crem0 - cq0 * D.p;
     __syncthreads();
     for (int s = 0; s < D.positions; ++s) {
         const int lay_hi = min(s + W - 1, D.layers - 1);
@@ -1340,14 +1351,14 @@ __global__ void __launch_bounds__(kWinBlock) window_lds_kernel(const ConvDesc D,
         for (int i = threadIdx.x; i < nvu * D.Lb * DVMAX; i += kWinBlock) {
             const int e = i % DVMAX, uq = i / DVMAX;
             const int u = uq / D.Lb, q = uq - u * D.Lb;
-            int v = -1, sh = 0;
+            int v = kNoEdge, sh = 0;
             if (e < nvs) {
                 const int tpos = s + u, dd = S.vn_dd[e], rr = S.vn_rr[e];
                 int ic = tpos % D.T + dd;
                 while (ic >= D.T) ic -= D.T;
                 const int a = sf(ic, dd, rr, q);
                 if (tpos + dd < D.layers && a >= 0) {
-                    v = (tpos % R) * eps + ((dd * D.Jb + rr) * D.Lb + q) * D.p;
+                    v = (tpos % R) * eps + ((dd * D.Jb + rr) * D.Lb + q) * D.p - a;
                     sh = a;
                 }
             }
@@ -1355,86 +1366,99 @@ __global__ void __launch_bounds__(kWinBlock) window_lds_kernel(const ConvDesc D,
             vsh[i] = sh;
         }
         __syncthreads();
-        const int rows = ncu * per;
-        const int cols = nvu * D.c;
-        const int sR = s % R;
+        const int sR = s % R, span = lay_hi - s;
+        // check row (unit u = layer s + u, circulant row rr, offset so)
+        auto check_row = [&](int u, int rr, int so) {
+            const int* tb = ctab + (u * D.Jb + rr) * DCMAX;
+            float in[DCMAX], t[DCMAX], q[DCMAX];
+            int idx[DCMAX];
+            uint32_t sgn = 0;
+#pragma unroll
+            for (int e = 0; e < DCMAX; ++e) {
+                const int o = tb[e];
+                idx[e] = o < 0 ? -1 : o + so;
+                in[e] = o < 0 ? 0.0f : msg[o + so];
+            }
+#pragma unroll
+            for (int e = 0; e < DCMAX; ++e) {
+                if (idx[e] >= 0) {
+                    tq_of(in[e], t[e], q[e]);
+                    sgn ^= __float_as_uint(in[e]) & 0x80000000u;
+                } else {
+                    t[e] = 1.0f;
+                    q[e] = 0.0f;
+                }
+            }
+            float mag[DCMAX];
+            boxplus_fb<DCMAX>(t, q, mag);
+#pragma unroll
+            for (int e = 0; e < DCMAX; ++e) {
+                if (idx[e] >= 0 && u >= cdd[e]) {     // position s + u - dd is not frozen
+                    const uint32_t sg = sgn ^ (__float_as_uint(in[e]) & 0x80000000u);
+                    msg[idx[e]] = __uint_as_float(__float_as_uint(mag[e]) | sg);
+                }
+            }
+        };
+        // variable column (unit u = position s + u, circulant column q,
+        // offset uu; rem = q * p + uu); the table holds the edge's ring
+        // offset minus its shift, so the package is base + uu (+ p on wrap)
+        auto variable_col = [&](int u, int q, int uu, int rem, bool out) {
+            int slot = sR + u;
+            if (slot >= R) slot -= R;
+            const float m = mu[slot * D.c + rem];
+            const int* tb = vtab + (u * D.Lb + q) * DVMAX;
+            const int* shb = vsh + (u * D.Lb + q) * DVMAX;
+            float a[DVMAX];
+            int idx[DVMAX];
+#pragma unroll
+            for (int e = 0; e < DVMAX; ++e) {
+                const int o = tb[e];
+                const int i = o + uu + (uu < shb[e] ? D.p : 0);
+                idx[e] = o == kNoEdge ? -1 : i;
+                // only messages from window layers (s + u + dd <= lay_hi) are summed
+                a[e] = (o != kNoEdge && u + vdd[e] <= span) ? msg[i] : 0.0f;
+            }
+            float suf[DVMAX];
+            float Ssum = 0.0f;
+#pragma unroll
+            for (int e = DVMAX - 1; e >= 0; --e) {
+                suf[e] = Ssum;
+                Ssum += a[e];
+            }
+            float pre = 0.0f;
+#pragma unroll
+            for (int e = 0; e < DVMAX; ++e) {
+                const float b = clip30(m + (pre + suf[e]));
+                pre += a[e];
+                if (idx[e] >= 0) msg[idx[e]] = b;
+            }
+            if (out && u == 0) {
+                const float L = m + pre;
+                const size_t o = frame_off + (size_t)s * D.c + rem;
+                post[o] = clip30(L);
+                bits_out[o] = (uint8_t)(L < 0.0f);
+            }
+        };
         for (int k = 1; k <= K; ++k) {
-            // check rows: unit u = layer s + u, circulant row rr, offset so
-            for (int r = threadIdx.x; r < rows; r += kWinBlock) {
-                const int u = div_small(r, per, inv_per);
-                const int rem = r - u * per;
-                const int rr = div_small(rem, D.p, inv_p), so = rem - rr * D.p;
-                const int* tb = ctab + (u * D.Jb + rr) * DCMAX;
-                float in[DCMAX], t[DCMAX], q[DCMAX];
-                int idx[DCMAX];
-                uint32_t sgn = 0;
-#pragma unroll
-                for (int e = 0; e < DCMAX; ++e) {
-                    const int o = tb[e];
-                    idx[e] = o < 0 ? -1 : o + so;
-                    in[e] = o < 0 ? 0.0f : msg[o + so];
-                }
-#pragma unroll
-                for (int e = 0; e < DCMAX; ++e) {
-                    if (idx[e] >= 0) {
-                        tq_of(in[e], t[e], q[e]);
-                        sgn ^= __float_as_uint(in[e]) & 0x80000000u;
-                    } else {
-                        t[e] = 1.0f;
-                        q[e] = 0.0f;
-                    }
-                }
-                float mag[DCMAX];
-                boxplus_fb<DCMAX>(t, q, mag);
-#pragma unroll
-                for (int e = 0; e < DCMAX; ++e) {
-                    if (idx[e] >= 0 && u >= cdd[e]) {     // position s + u - dd is not frozen
-                        const uint32_t sg = sgn ^ (__float_as_uint(in[e]) & 0x80000000u);
-                        msg[idx[e]] = __uint_as_float(__float_as_uint(mag[e]) | sg);
-                    }
+            if (rows_fixed) {
+                for (int u = ru0; u < ncu; u += rstep) check_row(u, rr0, so0);
+            } else {
+                for (int r = threadIdx.x; r < ncu * per; r += kWinBlock) {
+                    const int u = div_small(r, per, inv_per);
+                    const int rem = r - u * per;
+                    const int rr = div_small(rem, D.p, inv_p);
+                    check_row(u, rr, rem - rr * D.p);
                 }
             }
             __syncthreads();
-            // variable columns: unit u = position s + u, circulant column q, offset uu
-            for (int cidx = threadIdx.x; cidx < cols; cidx += kWinBlock) {
-                const int u = div_small(cidx, D.c, inv_c);
-                const int rem = cidx - u * D.c;
-                const int q = div_small(rem, D.p, inv_p), uu = rem - q * D.p;
-                int slot = sR + u;
-                if (slot >= R) slot -= R;
-                const float m = mu[slot * D.c + rem];
-                const int* tb = vtab + (u * D.Lb + q) * DVMAX;
-                const int* shb = vsh + (u * D.Lb + q) * DVMAX;
-                float a[DVMAX];
-                int idx[DVMAX];
-#pragma unroll
-                for (int e = 0; e < DVMAX; ++e) {
-                    const int o = tb[e];
-                    int so = uu - shb[e];
-                    if (so < 0) so += D.p;
-                    idx[e] = o < 0 ? -1 : o + so;
-                    // only messages from window layers (s + u + dd <= lay_hi) are summed
-                    a[e] = (o >= 0 && u + vdd[e] <= lay_hi - s) ? msg[o + so] : 0.0f;
-                }
-                float suf[DVMAX];
-                float Ssum = 0.0f;
-#pragma unroll
-                for (int e = DVMAX - 1; e >= 0; --e) {
-                    suf[e] = Ssum;
-                    Ssum += a[e];
-                }
-                float pre = 0.0f;
-#pragma unroll
-                for (int e = 0; e < DVMAX; ++e) {
-                    const float b = clip30(m + (pre + suf[e]));
-                    pre += a[e];
-                    if (idx[e] >= 0) msg[idx[e]] = b;
-                }
-                if (k == K && u == 0) {
-                    const float L = m + pre;
-                    const size_t o = frame_off + (size_t)s * D.c + rem;
-                    post[o] = clip30(L);
-                    bits_out[o] = (uint8_t)(L < 0.0f);
+            if (cols_fixed) {
+                for (int u = cu0; u < nvu; u += cstep) variable_col(u, cq0, cuu0, crem0, k == K);
+            } else {
+                for (int cidx = threadIdx.x; cidx < nvu * D.c; cidx += kWinBlock) {
+                    const int u = div_small(cidx, D.c, inv_c);
+                    const int rem = cidx - u * D.c;
+                    const int q = div_small(rem, D.p, inv_p);
+                    variable_col(u, q, rem - q * D.p, rem, k == K);
                 }
             }
             __syncthreads();
