@@ -1370,6 +1370,35 @@ __global__ void __launch_bounds__(kWinBlock) window_lds_kernel(const ConvDesc D,
         // check row (unit u = layer s + u, circulant row rr, offset so)
         auto check_row = [&](int u, int rr, int so) {
             const int* tb = ctab + (u * D.Jb + rr) * DCMAX;
+            if (DCMAX == ncs && u >= D.ms) {
+                // every slot is an edge and none leads to a frozen position
+                // (the row's circulants all exist): no per-edge tests
+                int o[DCMAX];
+                bool full = true;
+#pragma unroll
+                for (int e = 0; e < DCMAX; ++e) {
+                    o[e] = tb[e];
+                    full = full && o[e] >= 0;
+                }
+                if (full) {
+                    float in[DCMAX], t[DCMAX], q[DCMAX], mag[DCMAX];
+                    uint32_t sgn = 0;
+#pragma unroll
+                    for (int e = 0; e < DCMAX; ++e) in[e] = msg[o[e] + so];
+#pragma unroll
+                    for (int e = 0; e < DCMAX; ++e) {
+                        tq_of(in[e], t[e], q[e]);
+                        sgn ^= __float_as_uint(in[e]) & 0x80000000u;
+                    }
+                    boxplus_fb<DCMAX>(t, q, mag);
+#pragma unroll
+                    for (int e = 0; e < DCMAX; ++e) {
+                        const uint32_t sg = sgn ^ (__float_as_uint(in[e]) & 0x80000000u);
+                        msg[o[e] + so] = __uint_as_float(__float_as_uint(mag[e]) | sg);
+                    }
+                    return;
+                }
+            }
             float in[DCMAX], t[DCMAX], q[DCMAX];
             int idx[DCMAX];
             uint32_t sgn = 0;
