@@ -1439,6 +1439,41 @@ __global__ void __launch_bounds__(kWinBlock) window_lds_kernel(const ConvDesc D,
             const int* shb = vsh + (u * D.Lb + q) * DVMAX;
             float a[DVMAX];
             int idx[DVMAX];
+            if (DVMAX == nvs && u + D.ms <= span) {
+                // every slot is an edge to a window layer: no per-edge tests
+                bool full = true;
+#pragma unroll
+                for (int e = 0; e < DVMAX; ++e) {
+                    const int o = tb[e];
+                    idx[e] = o + uu + (uu < shb[e] ? D.p : 0);
+                    full = full && o != kNoEdge;
+                }
+                if (full) {
+#pragma unroll
+                    for (int e = 0; e < DVMAX; ++e) a[e] = msg[idx[e]];
+                    float suf[DVMAX];
+                    float Ssum = 0.0f;
+#pragma unroll
+                    for (int e = DVMAX - 1; e >= 0; --e) {
+                        suf[e] = Ssum;
+                        Ssum += a[e];
+                    }
+                    float pre = 0.0f;
+#pragma unroll
+                    for (int e = 0; e < DVMAX; ++e) {
+                        const float b = clip30(m + (pre + suf[e]));
+                        pre += a[e];
+                        msg[idx[e]] = b;
+                    }
+                    if (out && u == 0) {
+                        const float L = m + pre;
+                        const size_t o = frame_off + (size_t)s * D.c + rem;
+                        post[o] = clip30(L);
+                        bits_out[o] = (uint8_t)(L < 0.0f);
+                    }
+                    return;
+                }
+            }
 #pragma unroll
             for (int e = 0; e < DVMAX; ++e) {
                 const int o = tb[e];
