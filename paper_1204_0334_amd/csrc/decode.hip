@@ -1374,12 +1374,12 @@ __global__ void __launch_bounds__(kWinBlock) window_lds_kernel(const ConvDesc D,
                 // every slot is an edge and none leads to a frozen position
                 // (the row's circulants all exist): no per-edge tests
                 int o[DCMAX];
-                bool full = true;
 #pragma unroll
-                for (int e = 0; e < DCMAX; ++e) {
-                    o[e] = tb[e];
-                    full = full && o[e] >= 0;
-                }
+                for (int e = 0; e < DCMAX; ++e) o[e] = tb[e];
+                int any_missing = 0;      // all table reads first, then one test
+#pragma unroll
+                for (int e = 0; e < DCMAX; ++e) any_missing |= o[e];
+                const bool full = any_missing >= 0;
                 if (full) {
                     float in[DCMAX], t[DCMAX], q[DCMAX], mag[DCMAX];
                     uint32_t sgn = 0;
@@ -1441,12 +1441,17 @@ __global__ void __launch_bounds__(kWinBlock) window_lds_kernel(const ConvDesc D,
             int idx[DVMAX];
             if (DVMAX == nvs && u + D.ms <= span) {
                 // every slot is an edge to a window layer: no per-edge tests
-                bool full = true;
+                int o[DVMAX], sh[DVMAX];
 #pragma unroll
                 for (int e = 0; e < DVMAX; ++e) {
-                    const int o = tb[e];
-                    idx[e] = o + uu + (uu < shb[e] ? D.p : 0);
-                    full = full && o != kNoEdge;
+                    o[e] = tb[e];
+                    sh[e] = shb[e];
+                }
+                bool full = true;         // all table reads first, then one test
+#pragma unroll
+                for (int e = 0; e < DVMAX; ++e) {
+                    idx[e] = o[e] + uu + (uu < sh[e] ? D.p : 0);
+                    full = full & (o[e] != kNoEdge);
                 }
                 if (full) {
 #pragma unroll
