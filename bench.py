@@ -396,6 +396,37 @@ def bench_train(args):
     torch.cuda.synchronize()
     ldpc.timing_enable(False)
     per_kernel = ldpc.timing_read()
+    no_recompute = None
+    if args.extras:
+        # the same step keeping every iteration's messages (one segment of
+        # T): no recomputation in the backward pass, at the cost of a larger
+        # workspace; the gradient does not depend on the checkpoint interval
+        kk = T
+        ws_all = ldpc.nms_train_workspace(g, gamma, T, kk, dev)
+
+        def step_all():
+            per = nnms.iteration_losses(W, g, llr, kk, ws_all)
+            loss = per.mean()
+            opt.zero_grad(set_to_none=True)
+            loss.backward()
+            opt.step()
+            with torch.no_grad():
+                W.clamp_(min=0.0)
+
+        for _ in range(args.warmup):
+            step_all()
+        torch.cuda.synchronize()
+        start.record()
+        for _ in range(args.steps):
+            step_all()
+        stop.record()
+        torch.cuda.synchronize()
+        ms_all = start.elapsed_time(stop) / args.steps
+        no_recompute = {"ckpt_every": kk, "ms_per_step": round(ms_all, 4),
+                        "frames_per_s": round(gamma / (ms_all * 1e-3), 1),
+                        "workspace_gb": round(ws_all.numel() * ws_all.element_size() / 1e9, 2),
+                        "workspace_gb_ckpt4": round(ws.numel() * ws.element_size() / 1e9, 2)}
+        del ws_all
     algo = train_algorithmic_bytes(n, E, gamma, T)
     dom = max(algo, key=lambda c: per_kernel[c][1])
     launches, ms = per_kernel[dom]
@@ -418,6 +449,7 @@ def bench_train(args):
         "cpu_baseline": None,
         "kernels": {c: {"launches": v[0], "avg_us": round(v[1] / v[0] * 1e3, 2)} for c, v in per_kernel.items()
                     if v[0]},
+        "without_recompute": no_recompute,
     }
     print(json.dumps(line), flush=True)
 
@@ -535,12 +567,13 @@ def bench_plan(args):
     print(json.dumps(line), flush=True)
 
 
-def learned_vs_plain(g, points, *, train_frames: int, eval_frames: int, T: int = 12, ckpt_every: int = 4,
+def learned_vs_plain(g, points, *, train_frames: int, eval_frames: int, T: int = 12, ckpt_every=None,
                      extra: bool = False, log=None):
     """Train the learned min-sum decoder (T iterations, scale and offset per
     iteration and base row, Adam on `train_frames` GPU-generated frames at
     Eb/N0 uniform in 1.0-2.5 dB, BCE on every iteration's posterior,
-    checkpoints every `ckpt_every` iterations), then decode the same fresh
+    checkpoints every `ckpt_every` iterations, None: nnms.choose_ckpt_every),
+    then decode the same fresh
     frames at each Eb/N0 with it and with plain sum-product (up to 30
     iterations, early stop).  `extra` adds sum-product with T iterations and
     the untrained normalised min-sum (scale 0.8) for context."""
@@ -549,6 +582,8 @@ def learned_vs_plain(g, points, *, train_frames: int, eval_frames: int, T: int =
     from paper_1204_0334_amd import fer, nnms
     dev = torch.device("cuda:0")
     t0 = time.perf_counter()
+    if ckpt_every is None:
+        ckpt_every = nnms.choose_ckpt_every(g, 1024, T, dev)
     W, hist = nnms.train(g, T=T, ckpt_every=ckpt_every, frames=train_frames, batch=1024, lr=0.01, seed=7,
                          init=nnms.initial_weights(T, g.info["J"], 0.8, 0.0, device=dev), log_every=128)
     torch.cuda.synchronize()

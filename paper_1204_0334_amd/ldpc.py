@@ -263,11 +263,16 @@ def nms_decode(g: Graph, llr, weights, early_stop: bool = False, out=None, ws=No
     return post, bits, iters, conv
 
 
-def nms_train_workspace(g: Graph, gamma: int, iters: int, ckpt_every: int, device=None):
+def nms_train_workspace_size(g: Graph, gamma: int, iters: int, ckpt_every: int) -> int:
     out = _sz()
     _check(_nms_ws_size(g.handle, int(gamma), int(iters), int(ckpt_every), ctypes.byref(out)),
            "ldpc_nms_train_workspace_size")
-    return torch.empty(max(int(out.value), 1), dtype=torch.uint8, device=device or "cuda")
+    return int(out.value)
+
+
+def nms_train_workspace(g: Graph, gamma: int, iters: int, ckpt_every: int, device=None):
+    size = nms_train_workspace_size(g, gamma, iters, ckpt_every)
+    return torch.empty(max(size, 1), dtype=torch.uint8, device=device or "cuda")
 
 
 def nms_train_forward(g: Graph, llr, weights, ckpt_every: int, ws, loss=None, stream=None):

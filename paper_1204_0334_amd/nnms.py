@@ -52,7 +52,16 @@ def initial_weights(T: int, J: int, scale: float = 0.8, offset: float = 0.0, dev
     return w
 
 
-def train(g: ldpc.Graph, T: int = 12, ckpt_every: int = 4, frames: int = 1 << 20, batch: int = 1024,
+def choose_ckpt_every(g: ldpc.Graph, batch: int, T: int, device=None) -> int:
+    """T (every iteration's messages kept: no recomputation in the backward
+    pass) when that workspace takes at most half the free device memory,
+    else 4 (the last segment kept, earlier ones recomputed from checkpoints).
+    The gradient is the same either way."""
+    free, _ = torch.cuda.mem_get_info(torch.device(device or "cuda:0"))
+    return T if ldpc.nms_train_workspace_size(g, batch, T, T) <= free // 2 else min(4, T)
+
+
+def train(g: ldpc.Graph, T: int = 12, ckpt_every: int | None = None, frames: int = 1 << 20, batch: int = 1024,
           ebn0_range=(1.0, 2.5), chunk: int = 64, lr: float = 0.01, seed: int = 7, init=None,
           loss_weights=None, log_every: int = 0, device=None, checkpoint_path: str | None = None,
           checkpoint_every: int = 64):
@@ -60,7 +69,7 @@ def train(g: ldpc.Graph, T: int = 12, ckpt_every: int = 4, frames: int = 1 << 20
     mean over iterations), batches of `batch` fresh frames, each run of
     `chunk` frames at an Eb/N0 drawn uniformly from `ebn0_range`.  Scales and
     offsets are kept >= 0 after every step.  Returns (weights [T, J, 2],
-    history of (frames, loss)).
+    history of (frames, loss)).  `ckpt_every` None: choose_ckpt_every.
 
     With `checkpoint_path`, the weights, the Adam state, the step count, the
     Eb/N0 generator's state and the history are saved there every
@@ -74,6 +83,8 @@ def train(g: ldpc.Graph, T: int = 12, ckpt_every: int = 4, frames: int = 1 << 20
         raise ValueError("batch must be a multiple of chunk")
     W = (init.clone() if init is not None else initial_weights(T, J, device=dev)).requires_grad_(True)
     opt = torch.optim.Adam([W], lr=lr)
+    if ckpt_every is None:
+        ckpt_every = choose_ckpt_every(g, batch, T, dev)
     ws = ldpc.nms_train_workspace(g, batch, T, ckpt_every, dev)
     llr = torch.empty((batch, n), dtype=torch.float32, device=dev)
     rng = np.random.default_rng(seed)

@@ -233,3 +233,19 @@ def test_training_resumes_from_checkpoint(tmp_path):
                               checkpoint_path=path, checkpoint_every=2)
     assert torch.equal(W_full, W_res)
     assert h_full == h_res
+
+
+def test_default_keeps_every_iteration_and_trains_identically():
+    # with room on the device the default keeps every iteration's messages
+    # (no recomputation); the trained weights are those of checkpointing
+    # every 2 iterations, bit for bit
+    a = synth.draw_qc_shifts(3, 6, 64, 1)
+    g = ldpc.Graph.qc(a, 64)
+    T = 5
+    assert nnms.choose_ckpt_every(g, 512, T, DEV) == T
+    init = nnms.initial_weights(T, 3, 0.8, 0.1, device=DEV)
+    print("[gpu] nnms.train default checkpoint interval", flush=True)
+    W_all, h_all = nnms.train(g, T=T, frames=3 * 512, batch=512, lr=0.02, init=init, log_every=1)
+    W_ck, h_ck = nnms.train(g, T=T, ckpt_every=2, frames=3 * 512, batch=512, lr=0.02, init=init, log_every=1)
+    assert torch.equal(W_all, W_ck)
+    assert h_all == h_ck
