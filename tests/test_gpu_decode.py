@@ -363,6 +363,24 @@ def test_window_lds_and_launch_paths_agree_bit_for_bit(p, positions, W, K, gamma
     assert torch.equal(post_l, post_m)
 
 
+def test_window_ring_too_big_for_lds_takes_the_launch_path():
+    # p = 1024: a stream's ring is 8 x (6144 + 2048) floats = 256 KiB, more
+    # than a workgroup's LDS, so every phase is a launch; results against
+    # the FP64 reference as for the other windows
+    p, positions, W, K, gamma = 1024, 6, 4, 3, 4
+    a = synth.draw_qc_shifts(3, 6, p, 2)
+    Hc, _ = oracle.unwrap_qc(a, p, positions)
+    llr = synth.bpsk_awgn_llr(None, synth.ebn0_to_sigma2(1.5, 0.5), 17, gamma=gamma, n=Hc.n)
+    g = ldpc.Graph.ldpccc_from_qc(a, p, positions, True)
+    ldpc.timing_read()
+    ldpc.timing_enable(True)
+    gpu = gpu_window(g, llr, W, K)
+    ldpc.timing_enable(False)
+    t = ldpc.timing_read()
+    assert t["window_lds"][0] == 0 and t["window_check_node"][0] > 0, t
+    window_parity(gpu, oracle.decode_window(Hc, llr, W, K), "window p=1024")
+
+
 # ----------------------------------------------------------------------------
 # convolutional code, pipelined decoder (Algorithm 2)
 # ----------------------------------------------------------------------------
