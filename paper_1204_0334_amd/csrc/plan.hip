@@ -385,8 +385,11 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))
     }
 }
 
-__global__ void __launch_bounds__(kBlock) plan_vn_kernel(const PlanCode* __restrict__ codes, int ncodes,
-                                                         PlanStep S) {
+// 8 waves per SIMD (64 VGPRs; a few values the wave keeps for its whole life
+// are spilled): the launch is latency-bound, and the extra waves hide more
+// of it than the spills cost.
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8)))
+plan_vn_kernel(const PlanCode* __restrict__ codes, int ncodes, PlanStep S) {
     const int lane = threadIdx.x & 63;
     const int64_t wave = (int64_t)blockIdx.x * kWavesPerBlock + wave_in_block();
     const PlanCode& C = codes[plan_find(codes, ncodes, wave, &PlanCode::vn0)];
