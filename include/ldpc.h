@@ -344,7 +344,8 @@ ldpc_status ldpc_decode_window(const ldpc_graph* conv, const float* llr, int32_t
  * last frame has left.  Every check layer and every frame is thereby updated
  * exactly `iters` times, in flooding order, so the result equals `iters`
  * flooding iterations on the whole terminated chain while the decoder holds
- * only iters * (ms+1) frames (workspace from
+ * only iters * (ms+1) frames, plus 7 it reads in ahead so that one launch
+ * brings in 8 entering frames (workspace from
  * ldpc_workspace_size(conv, gamma, iters, 0)).
  *   llr, post, bits as for ldpc_decode_window; 1 <= iters <= 64.
  * Errors: EINVAL (QC graph, iters < 1, NULL pointers), EUNSUPPORTED

@@ -1736,8 +1736,15 @@ static ConvLayout conv_layout(const ldpc_graph* g, const Tiling& t, int ring) {
     return L;
 }
 
+// The pipelined decoder ingests kPipeAhead positions per ingest launch (one
+// launch every kPipeAhead slots instead of one per slot).  Position x is
+// decided at slot x + I(ms+1) - 1 and its ring slot is free from the next
+// one, so a position ingested up to kPipeAhead - 1 slots early needs
+// kPipeAhead - 1 extra ring slots.
+constexpr int kPipeAhead = 8;
+
 static int window_ring(const ldpc_graph* g, int W) { return std::min(W, g->positions) + g->ms; }
-static int pipeline_ring(const ldpc_graph* g, int I) { return I * (g->ms + 1); }
+static int pipeline_ring(const ldpc_graph* g, int I) { return I * (g->ms + 1) + kPipeAhead - 1; }
 
 static ConvSlots conv_slots(const ldpc_graph* g) {
     ConvSlots S{};
@@ -2154,8 +2161,9 @@ static void run_window(ConvRun& r, int Wlen, int K) {
 }
 
 // Pipelined decoder of Algorithm 2 with I processors: at slot t, frame t
-// enters; processor i updates check layer t - (i-1)(ms+1), then frame
-// t - (i-1)(ms+1) - ms; the frame leaving processor I is decided.
+// enters (ingested with the next kPipeAhead - 1 at slots that are multiples
+// of kPipeAhead); processor i updates check layer t - (i-1)(ms+1), then
+// frame t - (i-1)(ms+1) - ms; the frame leaving processor I is decided.
 template <int FPL>
 static void run_pipeline(ConvRun& r, int I) {
     const ConvDesc& D = r.D;
@@ -2164,7 +2172,7 @@ static void run_pipeline(ConvRun& r, int I) {
     r.cls_vn = 11;
     const int last_slot = D.positions - 1 + D.ms + (I - 1) * (D.ms + 1);
     for (int t = 0; t <= last_slot; ++t) {
-        if (t < D.positions) r.ingest<FPL>(t, 1);
+        if (t < D.positions && t % kPipeAhead == 0) r.ingest<FPL>(t, std::min(kPipeAhead, D.positions - t));
         ConvUnits Uc = r.units();
         ConvUnits Uv = r.units();
         for (int i = 1; i <= I; ++i) {
