@@ -624,15 +624,16 @@ def nnms_report(args):
     spec = synth.WORKLOADS["qc36_p3060"]
     g = ldpc.Graph.qc(synth.draw_qc_shifts(3, 6, spec["p"], spec["shift_seed"]), spec["p"])
     points = [1.0, 1.25, 1.5, 1.75, 2.0, 2.25, 2.5]
-    res = learned_vs_plain(g, points, train_frames=args.train_frames, eval_frames=args.eval_frames, extra=True,
-                           log=lambda r: print(json.dumps(r), flush=True))
+    T = args.nnms_iters
+    res = learned_vs_plain(g, points, train_frames=args.train_frames, eval_frames=args.eval_frames, T=T,
+                           extra=True, log=lambda r: print(json.dumps(r), flush=True))
     print(json.dumps({k: v for k, v in res.items() if k != "points"}), flush=True)
     print()
     print(f"Learned min-sum (T = {res['T']}, trained on {res['train_frames']} frames in {res['train_s']} s) "
           f"against sum-product, n = 18360, {res['eval_frames_per_point']} frames per point, early stop")
     print()
-    print("| Eb/N0 (dB) | SP-30 FER | SP-30 avg iters | learned NMS-12 FER | NMS-12 avg iters | SP-12 FER | "
-          "untrained NMS-12 FER |")
+    print(f"| Eb/N0 (dB) | SP-30 FER | SP-30 avg iters | learned NMS-{T} FER | NMS-{T} avg iters | SP-{T} FER | "
+          f"untrained NMS-{T} FER |")
     print("|---|---|---|---|---|---|---|")
     for r in res["points"]:
         print(f"| {r['ebn0_db']} | {r['sp30']['fer']:.3e} | {r['sp30']['avg_iters']:.2f} | "
@@ -762,6 +763,7 @@ def main():
                     help="run the learned min-sum against sum-product FER comparison instead of the benchmark line")
     ap.add_argument("--train-frames", type=int, default=1 << 20, help="learned min-sum: training frames")
     ap.add_argument("--eval-frames", type=int, default=1_000_000, help="--nnms: frames per Eb/N0 point")
+    ap.add_argument("--nnms-iters", type=int, default=12, help="--nnms: unrolled iterations T of the learned decoder")
     ap.add_argument("--fer-frames", type=int, default=1 << 17,
                     help="benchmark line: frames per Eb/N0 point of its learned-vs-plain FER check (0: skip)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
