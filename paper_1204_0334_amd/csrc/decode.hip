@@ -1247,6 +1247,7 @@ __global__ void __launch_bounds__(kIngestBlock) conv_ingest_kernel(const ConvDes
 // for another.
 constexpr int kWinBlock = 1024;
 constexpr int kNoEdge = -(1 << 30);     // variable-edge table: no such edge
+constexpr int kWinPre = 6;              // columns per thread whose packages are kept per slide
 
 template <int DCMAX, int DVMAX>
 __host__ __device__ constexpr size_t window_lds_tables(int W, int Jb, int Lb) {
@@ -1508,6 +1509,38 @@ __global__ void __launch_bounds__(kWinBlock) window_lds_kernel(const ConvDesc D,
                 bits_out[o] = (uint8_t)(L < 0.0f);
             }
         };
+        // fixed columns (at most kWinPre per thread): each edge's package for
+        // this slide, worked out once for the K iterations: >= 0 summed
+        // (window layer), <= -2 written only (package -2 - v), -1 no edge
+        // (compiled only for light rows and columns: the kept packages live
+        // in registers through the check half too)
+        constexpr bool kKeep = DVMAX <= 3 && DCMAX <= 6;
+        const int ncol = cols_fixed ? (nvu - cu0 + cstep - 1) / cstep : 0;
+        const bool pre = kKeep && cols_fixed && ncol <= kWinPre;
+        int vix[kWinPre][DVMAX], mix[kWinPre];
+        if constexpr (kKeep) {
+            if (pre) {
+#pragma unroll
+                for (int j = 0; j < kWinPre; ++j) {
+                    const int u = cu0 + j * cstep;
+                    int slot = sR + u;
+                    if (slot >= R) slot -= R;
+                    mix[j] = slot * D.c + crem0;
+                    const int* tb = vtab + (u * D.Lb + cq0) * DVMAX;
+                    const int* shb = vsh + (u * D.Lb + cq0) * DVMAX;
+#pragma unroll
+                    for (int e = 0; e < DVMAX; ++e) {
+                        int v = -1;
+                        if (j < ncol) {
+                            const int o = tb[e];
+                            const int i = o + cuu0 + (cuu0 < shb[e] ? D.p : 0);
+                            v = o == kNoEdge ? -1 : (u + vdd[e] <= span ? i : -2 - i);
+                        }
+                        vix[j][e] = v;
+                    }
+                }
+            }
+        }
         for (int k = 1; k <= K; ++k) {
             if (rows_fixed) {
                 for (int u = ru0; u < ncu; u += rstep) check_row(u, rr0, so0);
@@ -1520,9 +1553,44 @@ __global__ void __launch_bounds__(kWinBlock) window_lds_kernel(const ConvDesc D,
                 }
             }
             __syncthreads();
-            if (cols_fixed) {
+            bool kept = false;
+            if constexpr (kKeep) {
+                if (pre) {
+                    kept = true;
+#pragma unroll
+                    for (int j = 0; j < kWinPre; ++j) {
+                        if (j >= ncol) break;
+                        const float m = mu[mix[j]];
+                        float a[DVMAX];
+#pragma unroll
+                        for (int e = 0; e < DVMAX; ++e) a[e] = vix[j][e] >= 0 ? msg[vix[j][e]] : 0.0f;
+                        float suf[DVMAX];
+                        float Ssum = 0.0f;
+#pragma unroll
+                        for (int e = DVMAX - 1; e >= 0; --e) {
+                            suf[e] = Ssum;
+                            Ssum += a[e];
+                        }
+                        float pre_sum = 0.0f;
+#pragma unroll
+                        for (int e = 0; e < DVMAX; ++e) {
+                            const float b = clip30(m + (pre_sum + suf[e]));
+                            pre_sum += a[e];
+                            const int v = vix[j][e];
+                            if (v != -1) msg[v >= 0 ? v : -2 - v] = b;
+                        }
+                        if (k == K && cu0 + j * cstep == 0) {
+                            const float L = m + pre_sum;
+                            const size_t o = frame_off + (size_t)s * D.c + crem0;
+                            post[o] = clip30(L);
+                            bits_out[o] = (uint8_t)(L < 0.0f);
+                        }
+                    }
+                }
+            }
+            if (!kept && cols_fixed) {
                 for (int u = cu0; u < nvu; u += cstep) variable_col(u, cq0, cuu0, crem0, k == K);
-            } else {
+            } else if (!kept) {
                 for (int cidx = threadIdx.x; cidx < nvu * D.c; cidx += kWinBlock) {
                     const int u = div_small(cidx, D.c, inv_c);
                     const int rem = cidx - u * D.c;
