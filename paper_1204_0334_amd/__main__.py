@@ -6,8 +6,9 @@
     python -m paper_1204_0334_amd codes
 
 Codes are the named presets (QC shift tables drawn by the seeded 4-cycle-free
-generator) or `--shifts FILE` (a JSON list of rows, -1 = zero block) with
-`--p`.  Each Eb/N0 point runs until `--min-errors` frame errors or
+generator: the benchmark workloads and the paper's Table II shapes
+table2_A..D; `--positions` unwraps a block preset into a convolutional code)
+or `--shifts FILE` (a JSON list of rows, -1 = zero block) with `--p`.  Each Eb/N0 point runs until `--min-errors` frame errors or
 `--max-frames` frames; results are appended to the JSONL log, and a rerun
 with the same log resumes unfinished points and skips finished ones.
 """
@@ -16,6 +17,18 @@ from __future__ import annotations
 import argparse
 import json
 import sys
+
+
+def _presets():
+    """Named codes: the benchmark workloads, and the 4 x 24 (rate 5/6) shapes
+    of the paper's Table II (codes A-D, p = 422, 632, 768, 1024) with the
+    seeded 4-cycle-free shifts the paper-table analogue of bench.py uses
+    (the paper does not print its shifts)."""
+    import synth
+    out = {k: dict(w) for k, w in synth.WORKLOADS.items()}
+    for name, p in (("A", 422), ("B", 632), ("C", 768), ("D", 1024)):
+        out[f"table2_{name}"] = dict(J=4, L=24, p=p, shift_seed=40 + p)
+    return out
 
 
 def _graph(args):
@@ -31,11 +44,12 @@ def _graph(args):
         if args.positions:
             return ldpc.Graph.ldpccc_from_qc(shifts, args.p, args.positions, True), key
         return ldpc.Graph.qc(shifts, args.p), key
-    if args.code not in synth.WORKLOADS:
+    presets = _presets()
+    if args.code not in presets:
         raise SystemExit(f"unknown code {args.code!r}; see `codes`")
-    w = synth.WORKLOADS[args.code]
+    w = presets[args.code]
     shifts = synth.draw_qc_shifts(w["J"], w["L"], w["p"], w["shift_seed"])
-    if "positions" in w:
+    if "positions" in w or args.positions:
         return ldpc.Graph.ldpccc_from_qc(shifts, w["p"], args.positions or w["positions"], True), args.code
     return ldpc.Graph.qc(shifts, w["p"]), args.code
 
@@ -61,8 +75,7 @@ def main(argv=None):
     sw.add_argument("--log", default="fer_sweep.jsonl")
     args = ap.parse_args(argv)
     if args.cmd == "codes":
-        import synth
-        for k, w in synth.WORKLOADS.items():
+        for k, w in _presets().items():
             print(k, json.dumps({a: b for a, b in w.items() if a != "noise_seed"}))
         return 0
     from . import fer

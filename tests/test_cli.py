@@ -8,7 +8,7 @@ def test_codes_lists_presets(capsys):
     from paper_1204_0334_amd.__main__ import main
     assert main(["codes"]) == 0
     out = capsys.readouterr().out
-    assert "qc36_p3060" in out and "cc36_p512" in out
+    assert "qc36_p3060" in out and "cc36_p512" in out and "table2_D" in out
 
 
 def test_unknown_code_and_missing_p():
