@@ -351,6 +351,13 @@ __device__ __forceinline__ void vn_column(const QCDesc& D, const BlockParams& P,
     bool lane_live = false;
 #pragma unroll
     for (int f = 0; f < FPL; ++f) lane_live = lane_live || !((frz[f] >> lane) & 1ull);
+    // the edges' packages first, outside the per-lane branch: the column is
+    // the wave's, so its edge-block table reads are uniform (scalar); inside
+    // the branch each became a vector load whose wait also drained the
+    // previous message load, one round trip per edge
+    int64_t pk[DVMAX];
+#pragma unroll
+    for (int k = 0; k < DVMAX; ++k) pk[k] = C.valid(D, k) ? C.pkg(D, k) : 0;
     float mu[FPL];
 #pragma unroll
     for (int f = 0; f < FPL; ++f) mu[f] = 0.0f;
@@ -359,7 +366,7 @@ __device__ __forceinline__ void vn_column(const QCDesc& D, const BlockParams& P,
 #pragma unroll
     for (int k = 0; k < DVMAX; ++k) {
         if (C.valid(D, k) && lane_live) {
-            load_frames<FPL>(mt + (size_t)C.pkg(D, k) * Gt, a[k]);
+            load_frames<FPL>(mt + (size_t)pk[k] * Gt, a[k]);
         } else {
 #pragma unroll
             for (int f = 0; f < FPL; ++f) a[k][f] = 0.0f;
@@ -370,7 +377,7 @@ __device__ __forceinline__ void vn_column(const QCDesc& D, const BlockParams& P,
     if (!P.last && lane_live) {
 #pragma unroll
         for (int k = 0; k < DVMAX; ++k)
-            if (C.valid(D, k)) store_frames<FPL>(mt + (size_t)C.pkg(D, k) * Gt, b[k]);
+            if (C.valid(D, k)) store_frames<FPL>(mt + (size_t)pk[k] * Gt, b[k]);
     }
     if (P.early || P.last) {
         // decisions, packed: word f, bit i <-> frame FPL*i + f
