@@ -715,13 +715,17 @@ __global__ void __launch_bounds__(kBlock) nms_train_vn_kernel(const QCDesc D, co
     const QCCol C(D, col);
     const size_t lane_off = (size_t)lane * FPL;
     const size_t base = (size_t)tile * D.E * Gt + lane_off;
+    // the edges' packages before any message load (see vn_column)
+    int64_t pk[DVMAX];
+#pragma unroll
+    for (int k = 0; k < DVMAX; ++k) pk[k] = C.valid(D, k) ? C.pkg(D, k) : 0;
     float mu[FPL];
     load_frames<FPL>(P.mu + ((size_t)tile * D.n + C.v) * Gt + lane_off, mu);
     float a[DVMAX][FPL];
 #pragma unroll
     for (int k = 0; k < DVMAX; ++k) {
         if (C.valid(D, k)) {
-            load_frames<FPL>(A + base + (size_t)C.pkg(D, k) * Gt, a[k]);
+            load_frames<FPL>(A + base + (size_t)pk[k] * Gt, a[k]);
         } else {
 #pragma unroll
             for (int f = 0; f < FPL; ++f) a[k][f] = 0.0f;
@@ -750,7 +754,7 @@ __global__ void __launch_bounds__(kBlock) nms_train_vn_kernel(const QCDesc D, co
 #pragma unroll
     for (int k = 0; k < DVMAX; ++k) {
         if (!C.valid(D, k)) continue;
-        if (dst) store_frames<FPL>(dst + base + (size_t)C.pkg(D, k) * Gt, b[k]);
+        if (dst) store_frames<FPL>(dst + base + (size_t)pk[k] * Gt, b[k]);
     }
     if (lpart) {
         lsum = wave_sum(lsum);
@@ -780,6 +784,10 @@ __global__ void __launch_bounds__(kBlock) nms_vn_backward_kernel(const QCDesc D,
     const size_t lane_off = (size_t)lane * FPL;
     const size_t base = (size_t)tile * D.E * Gt + lane_off;
     const float scale = dloss[P.iter - 1] * inv_count;
+    // the edges' packages before any message load (see vn_column)
+    int64_t pk[DVMAX];
+#pragma unroll
+    for (int k = 0; k < DVMAX; ++k) pk[k] = C.valid(D, k) ? C.pkg(D, k) : 0;
     float mu[FPL];
     load_frames<FPL>(P.mu + ((size_t)tile * D.n + C.v) * Gt + lane_off, mu);
     float a[DVMAX][FPL], gb[DVMAX][FPL];
@@ -787,13 +795,13 @@ __global__ void __launch_bounds__(kBlock) nms_vn_backward_kernel(const QCDesc D,
     for (int k = 0; k < DVMAX; ++k) {
         const bool ok = C.valid(D, k);
         if (ok) {
-            load_frames<FPL>(A + base + (size_t)C.pkg(D, k) * Gt, a[k]);
+            load_frames<FPL>(A + base + (size_t)pk[k] * Gt, a[k]);
         } else {
 #pragma unroll
             for (int f = 0; f < FPL; ++f) a[k][f] = 0.0f;
         }
         if (ok && dB) {
-            load_frames<FPL>(dB + base + (size_t)C.pkg(D, k) * Gt, gb[k]);
+            load_frames<FPL>(dB + base + (size_t)pk[k] * Gt, gb[k]);
         } else {
 #pragma unroll
             for (int f = 0; f < FPL; ++f) gb[k][f] = 0.0f;
@@ -834,7 +842,7 @@ __global__ void __launch_bounds__(kBlock) nms_vn_backward_kernel(const QCDesc D,
     }
 #pragma unroll
     for (int k = 0; k < DVMAX; ++k)
-        if (C.valid(D, k)) store_frames<FPL>(dA + base + (size_t)C.pkg(D, k) * Gt, out[k]);
+        if (C.valid(D, k)) store_frames<FPL>(dA + base + (size_t)pk[k] * Gt, out[k]);
 }
 
 __device__ __forceinline__ float abs_grad(float x) { return x > 0.0f ? 1.0f : (x < 0.0f ? -1.0f : 0.0f); }
