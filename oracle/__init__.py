@@ -204,7 +204,7 @@ def _lib():
     vp, ci, cd = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
     lib.oracle_decode_block.restype = ci
     lib.oracle_decode_block.argtypes = [ci, ci, vp, vp, vp, ci, ci, ci, cd, ci,
-                                        vp, vp, vp, vp, vp, vp]
+                                        vp, vp, vp, vp, vp, vp, cd, vp, vp]
     lib.oracle_decode_window.restype = ci
     lib.oracle_decode_window.argtypes = [ci, ci, vp, vp, vp, vp, ci, ci, vp, ci, ci, ci, cd, ci,
                                          vp, vp]
@@ -217,10 +217,22 @@ def _ptr(a):
     return a.ctypes.data if a is not None else None
 
 
+NEAR = 1e-3
+
+
 def decode_block(H: SparseH, llr, max_iters: int, early_stop: bool = False,
-                 lmax: float = LMAX, nthreads: int = 0, trace: bool = False):
+                 lmax: float = LMAX, nthreads: int = 0, trace: bool = False, L_trace: bool = False,
+                 near: float = NEAR):
     """Algorithm 1 in FP64 for every frame of llr [gamma, n] (float32).
-    Returns dict(post, bits, iters, converged, min_abs[, syn_trace])."""
+    Returns dict(post, bits, iters, converged, min_abs, fragile[, syn_trace]
+    [, L_trace]).
+
+    min_abs: the smallest |L| of any decision made (all bits, every iteration
+    up to the returned one).  fragile: the first iteration (up to the returned
+    one) at which flipping decisions with |L| < near could change whether the
+    syndrome is zero, else 0 -- where a decoder that rounds differently may
+    stop at another iteration.  L_trace: [gamma, max_iters, n] unclipped L of
+    every iteration (NaN after the returned one)."""
     y = np.ascontiguousarray(np.asarray(llr, dtype=np.float32))
     if y.ndim != 2 or y.shape[1] != H.n:
         raise ValueError("llr must be [gamma, n]")
@@ -230,16 +242,20 @@ def decode_block(H: SparseH, llr, max_iters: int, early_stop: bool = False,
     iters = np.empty(g, dtype=np.int32)
     conv = np.empty(g, dtype=np.uint8)
     mina = np.empty(g, dtype=np.float64)
+    frag = np.empty(g, dtype=np.int32)
     syn = np.empty((g, max_iters), dtype=np.uint8) if trace else None
+    Lt = np.full((g, max_iters, H.n), np.nan, dtype=np.float64) if L_trace else None
     rc = _lib().oracle_decode_block(H.n, H.m, _ptr(H.row_ptr), _ptr(H.col_idx), _ptr(y), g,
                                     int(max_iters), int(bool(early_stop)), float(lmax), int(nthreads),
                                     _ptr(post), _ptr(bits), _ptr(iters), _ptr(conv), _ptr(mina),
-                                    _ptr(syn))
+                                    _ptr(syn), float(near), _ptr(frag), _ptr(Lt))
     if rc != 0:
         raise ValueError("oracle_decode_block rejected its input")
-    out = dict(post=post, bits=bits, iters=iters, converged=conv, min_abs=mina)
+    out = dict(post=post, bits=bits, iters=iters, converged=conv, min_abs=mina, fragile=frag)
     if trace:
         out["syn_trace"] = syn
+    if L_trace:
+        out["L_trace"] = Lt
     return out
 
 

@@ -117,6 +117,37 @@ static int syndrome_zero(int m, const int32_t* row_ptr, const int32_t* col_idx, 
 }
 
 /*
+ * Could flipping some of the decisions whose |L| is below `near` change
+ * whether the syndrome of c is zero?  Flipping a set of variables toggles the
+ * parity of every check they meet, so: if the syndrome is zero, yes as soon as
+ * one such variable meets a check; if not, only if every unsatisfied check
+ * meets such a variable (a necessary condition, so the answer errs towards
+ * yes).  Returns 1 for yes.  touched is caller scratch of m bytes.
+ */
+static int syndrome_fragile(int n, int m, const int32_t* row_ptr, const int32_t* col_idx, const uint8_t* c,
+                            const double* L, double near, uint8_t* touched) {
+    int any_near = 0;
+    for (int v = 0; v < n; ++v)
+        if (fabs(L[v]) < near) { any_near = 1; break; }
+    if (!any_near) return 0;
+    int unsat = 0, all_covered = 1, near_checked = 0;
+    for (int r = 0; r < m; ++r) {
+        int par = 0;
+        touched[r] = 0;
+        for (int e = row_ptr[r]; e < row_ptr[r + 1]; ++e) {
+            par ^= c[col_idx[e]];
+            if (fabs(L[col_idx[e]]) < near) touched[r] = 1;
+        }
+        if (touched[r]) near_checked = 1;
+        if (par) {
+            unsat = 1;
+            if (!touched[r]) all_covered = 0;
+        }
+    }
+    return unsat ? all_covered : near_checked;
+}
+
+/*
  * Block decoder (Algorithm 1, flooding).
  *   llr       [gamma][n] float channel LLRs (read as double)
  *   post      [gamma][n] double, clip(L) of the stopping iteration
@@ -128,13 +159,20 @@ static int syndrome_zero(int m, const int32_t* row_ptr, const int32_t* col_idx, 
  *             iterations up to the stopping one)
  *   syn_trace [gamma][max_iters] or NULL: 1 where iteration i's decisions have
  *             a zero syndrome (filled up to the stopping iteration, rest 0)
+ *   fragile   [gamma] or NULL: the first iteration (up to the returned one) at
+ *             which decisions with |L_n| < near could change whether the
+ *             syndrome is zero, else 0 (see syndrome_fragile); a diagnostic for
+ *             comparing decoders that round differently, not part of decoding
+ *   L_trace   [gamma][max_iters][n] or NULL: the unclipped L of every
+ *             iteration (filled up to the stopping iteration)
  * Returns 0, or -1 on invalid input.
  */
 int oracle_decode_block(int n, int m, const int32_t* row_ptr, const int32_t* col_idx,
                         const float* llr, int gamma, int max_iters, int early_stop,
                         double lmax, int nthreads,
                         double* post, uint8_t* bits, int32_t* iters, uint8_t* converged,
-                        double* min_abs, uint8_t* syn_trace) {
+                        double* min_abs, uint8_t* syn_trace, double near, int32_t* fragile,
+                        double* L_trace) {
     if (n < 0 || m < 0 || gamma < 0 || max_iters < 1) return -1;
     colview cv;
     if (build_colview(n, m, row_ptr, col_idx, &cv)) { free_colview(&cv); return -1; }
@@ -153,7 +191,8 @@ int oracle_decode_block(int n, int m, const int32_t* row_ptr, const int32_t* col
         double* L = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
         uint8_t* c = (uint8_t*)malloc((size_t)(n > 0 ? n : 1));
         double* th = (double*)malloc(sizeof(double) * (size_t)max_row_weight(m, row_ptr));
-        if (!mu || !beta || !alpha || !L || !c || !th) {
+        uint8_t* touched = (uint8_t*)malloc((size_t)(m > 0 ? m : 1));
+        if (!mu || !beta || !alpha || !L || !c || !th || !touched) {
             #pragma omp atomic write
             status = -1;
         } else {
@@ -166,7 +205,7 @@ int oracle_decode_block(int n, int m, const int32_t* row_ptr, const int32_t* col
                     for (int e = row_ptr[r]; e < row_ptr[r + 1]; ++e)
                         beta[e] = clipd(mu[col_idx[e]], lmax);
                 double mina = INFINITY;
-                int it_done = max_iters, zero = 0;
+                int it_done = max_iters, zero = 0, frag = 0;
                 if (syn_trace) memset(syn_trace + (size_t)g * max_iters, 0, (size_t)max_iters);
                 for (int it = 1; it <= max_iters; ++it) {
                     /* horizontal step */
@@ -189,6 +228,9 @@ int oracle_decode_block(int n, int m, const int32_t* row_ptr, const int32_t* col
                     }
                     zero = syndrome_zero(m, row_ptr, col_idx, c);
                     if (syn_trace) syn_trace[(size_t)g * max_iters + (it - 1)] = (uint8_t)zero;
+                    if (L_trace) memcpy(L_trace + ((size_t)g * max_iters + (it - 1)) * n, L, sizeof(double) * (size_t)n);
+                    if (fragile && frag == 0 && syndrome_fragile(n, m, row_ptr, col_idx, c, L, near, touched))
+                        frag = it;
                     if (early_stop && zero) { it_done = it; break; }
                 }
                 for (int v = 0; v < n; ++v) {
@@ -198,9 +240,10 @@ int oracle_decode_block(int n, int m, const int32_t* row_ptr, const int32_t* col
                 iters[g] = it_done;
                 converged[g] = (uint8_t)zero;
                 if (min_abs) min_abs[g] = mina;
+                if (fragile) fragile[g] = frag;
             }
         }
-        free(mu); free(beta); free(alpha); free(L); free(c); free(th);
+        free(mu); free(beta); free(alpha); free(L); free(c); free(th); free(touched);
     }
     free_colview(&cv);
     return status;

@@ -188,6 +188,24 @@ def _stream_handle(stream):
     return ctypes.c_void_p(s.cuda_stream)
 
 
+def _on_stream(stream, fresh):
+    """Prepare tensors allocated by this module (`fresh`: workspace, outputs)
+    for use on `stream`.  They come from torch's caching allocator on the
+    current stream; on another stream the enqueued work must first wait for
+    the current stream (the memory may have been released by work still
+    queued there) and the allocator must know the tensors are in use on that
+    stream until its work is done (record_stream), or it could hand the
+    memory out again while the decoder still reads or writes it."""
+    if stream is None:
+        return
+    cur = torch.cuda.current_stream(stream.device)
+    if stream == cur:
+        return
+    stream.wait_stream(cur)
+    for t in fresh:
+        t.record_stream(stream)
+
+
 def _need(t, dtype, shape, what):
     torch = _torch()
     if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
@@ -211,11 +229,13 @@ def decode(g: Graph, llr, max_iters: int, early_stop: bool = False, out=None, ws
     gamma, n = llr.shape
     _need(llr, torch.float32, (gamma, g.n), "llr")
     dev = llr.device
+    fresh = []
     if out is None:
         out = (torch.empty((gamma, n), dtype=torch.float32, device=dev),
                torch.empty((gamma, n), dtype=torch.uint8, device=dev),
                torch.empty((gamma,), dtype=torch.int32, device=dev),
                torch.empty((gamma,), dtype=torch.uint8, device=dev))
+        fresh += list(out)
     post, bits, iters, conv = out
     _need(post, torch.float32, (gamma, n), "post")
     _need(bits, torch.uint8, (gamma, n), "bits")
@@ -223,19 +243,22 @@ def decode(g: Graph, llr, max_iters: int, early_stop: bool = False, out=None, ws
     _need(conv, torch.uint8, (gamma,), "converged")
     if ws is None:
         ws = workspace(g, gamma, max_iters, 0, dev)
+        fresh.append(ws)
+    _on_stream(stream, fresh)
     _check(_decode(g.handle, llr.data_ptr(), gamma, int(max_iters), int(bool(early_stop)), post.data_ptr(),
                    bits.data_ptr(), iters.data_ptr(), conv.data_ptr(), ws.data_ptr(), ws.numel(),
                    _stream_handle(stream)), "ldpc_decode")
     return post, bits, iters, conv
 
 
-def _decode_outputs(llr, gamma, n, out):
+def _decode_outputs(llr, gamma, n, out, fresh):
     dev = llr.device
     if out is None:
         out = (torch.empty((gamma, n), dtype=torch.float32, device=dev),
                torch.empty((gamma, n), dtype=torch.uint8, device=dev),
                torch.empty((gamma,), dtype=torch.int32, device=dev),
                torch.empty((gamma,), dtype=torch.uint8, device=dev))
+        fresh += list(out)
     post, bits, iters, conv = out
     _need(post, torch.float32, (gamma, n), "post")
     _need(bits, torch.uint8, (gamma, n), "bits")
@@ -254,9 +277,12 @@ def nms_decode(g: Graph, llr, weights, early_stop: bool = False, out=None, ws=No
     _need(llr, torch.float32, (gamma, g.n), "llr")
     T = int(weights.shape[0]) if weights.dim() == 3 else -1
     _need(weights, torch.float32, (T, g.info["J"], 2), "weights")
-    post, bits, iters, conv = _decode_outputs(llr, gamma, n, out)
+    fresh = []
+    post, bits, iters, conv = _decode_outputs(llr, gamma, n, out, fresh)
     if ws is None:
         ws = workspace(g, gamma, T, 0, llr.device)
+        fresh.append(ws)
+    _on_stream(stream, fresh)
     _check(_nms_decode(g.handle, llr.data_ptr(), gamma, T, weights.data_ptr(), int(bool(early_stop)),
                        post.data_ptr(), bits.data_ptr(), iters.data_ptr(), conv.data_ptr(), ws.data_ptr(),
                        ws.numel(), _stream_handle(stream)), "ldpc_nms_decode")
@@ -283,9 +309,12 @@ def nms_train_forward(g: Graph, llr, weights, ckpt_every: int, ws, loss=None, st
     _need(llr, torch.float32, (gamma, g.n), "llr")
     T = int(weights.shape[0]) if weights.dim() == 3 else -1
     _need(weights, torch.float32, (T, g.info["J"], 2), "weights")
+    fresh = []
     if loss is None:
         loss = torch.empty((T,), dtype=torch.float32, device=llr.device)
+        fresh.append(loss)
     _need(loss, torch.float32, (T,), "loss")
+    _on_stream(stream, fresh)
     _check(_nms_forward(g.handle, llr.data_ptr(), gamma, T, int(ckpt_every), weights.data_ptr(), loss.data_ptr(),
                         ws.data_ptr(), ws.numel(), _stream_handle(stream)), "ldpc_nms_train_forward")
     return loss
@@ -297,9 +326,12 @@ def nms_train_backward(g: Graph, gamma: int, weights, ckpt_every: int, dloss, ws
     T = int(weights.shape[0]) if weights.dim() == 3 else -1
     _need(weights, torch.float32, (T, g.info["J"], 2), "weights")
     _need(dloss, torch.float32, (T,), "dloss")
+    fresh = []
     if grad is None:
         grad = torch.empty_like(weights)
+        fresh.append(grad)
     _need(grad, torch.float32, tuple(weights.shape), "grad")
+    _on_stream(stream, fresh)
     _check(_nms_backward(g.handle, int(gamma), T, int(ckpt_every), weights.data_ptr(), dloss.data_ptr(),
                          grad.data_ptr(), ws.data_ptr(), ws.numel(), _stream_handle(stream)),
            "ldpc_nms_train_backward")
@@ -314,14 +346,18 @@ def decode_window(g: Graph, llr, W: int, iters_per_window: int, out=None, ws=Non
     gamma, n = llr.shape
     _need(llr, torch.float32, (gamma, g.n), "llr")
     dev = llr.device
+    fresh = []
     if out is None:
         out = (torch.empty((gamma, n), dtype=torch.float32, device=dev),
                torch.empty((gamma, n), dtype=torch.uint8, device=dev))
+        fresh += list(out)
     post, bits = out
     _need(post, torch.float32, (gamma, n), "post")
     _need(bits, torch.uint8, (gamma, n), "bits")
     if ws is None:
         ws = workspace(g, gamma, 1, W, dev)
+        fresh.append(ws)
+    _on_stream(stream, fresh)
     _check(_decode_window(g.handle, llr.data_ptr(), gamma, int(W), int(iters_per_window), post.data_ptr(),
                           bits.data_ptr(), ws.data_ptr(), ws.numel(), _stream_handle(stream)),
            "ldpc_decode_window")
@@ -336,14 +372,18 @@ def decode_pipeline(g: Graph, llr, iters: int, out=None, ws=None, stream=None):
     gamma, n = llr.shape
     _need(llr, torch.float32, (gamma, g.n), "llr")
     dev = llr.device
+    fresh = []
     if out is None:
         out = (torch.empty((gamma, n), dtype=torch.float32, device=dev),
                torch.empty((gamma, n), dtype=torch.uint8, device=dev))
+        fresh += list(out)
     post, bits = out
     _need(post, torch.float32, (gamma, n), "post")
     _need(bits, torch.uint8, (gamma, n), "bits")
     if ws is None:
         ws = workspace(g, gamma, iters, 0, dev)
+        fresh.append(ws)
+    _on_stream(stream, fresh)
     _check(_decode_pipeline(g.handle, llr.data_ptr(), gamma, int(iters), post.data_ptr(), bits.data_ptr(),
                             ws.data_ptr(), ws.numel(), _stream_handle(stream)), "ldpc_decode_pipeline")
     return post, bits
@@ -351,9 +391,12 @@ def decode_pipeline(g: Graph, llr, iters: int, out=None, ws=None, stream=None):
 
 def awgn_llr(n: int, gamma: int, sigma2: float, seed: int, frame0: int = 0, out=None, device=None, stream=None):
     """Channel LLRs of the all-zero codeword generated on the GPU: float32 [gamma, n]."""
+    fresh = []
     if out is None:
         out = torch.empty((gamma, n), dtype=torch.float32, device=device or "cuda")
+        fresh.append(out)
     _need(out, torch.float32, (gamma, n), "out")
+    _on_stream(stream, fresh)
     _check(_awgn_llr(int(n), int(gamma), float(sigma2), int(seed) & 0xFFFFFFFFFFFFFFFF, int(frame0), out.data_ptr(),
                      _stream_handle(stream)), "ldpc_awgn_llr")
     return out
@@ -364,11 +407,14 @@ def count_errors(bits, frame_errors=None, totals=None, stream=None):
     bit and frame errors to `totals` (int64 [2]) when given."""
     gamma, n = bits.shape
     _need(bits, torch.uint8, (gamma, n), "bits")
+    fresh = []
     if frame_errors is None:
         frame_errors = torch.empty((gamma,), dtype=torch.int32, device=bits.device)
+        fresh.append(frame_errors)
     _need(frame_errors, torch.int32, (gamma,), "frame_errors")
     if totals is not None:
         _need(totals, torch.int64, (2,), "totals")
+    _on_stream(stream, fresh)
     _check(_count_errors(bits.data_ptr(), gamma, n, frame_errors.data_ptr(),
                          totals.data_ptr() if totals is not None else None, _stream_handle(stream)),
            "ldpc_count_errors")
@@ -454,11 +500,15 @@ class Plan:
 
     def decode(self, llrs, outs=None, ws=None, stream=None):
         """Decode llrs[c] [gamma_c, n_c]; returns [(post, bits, iters, converged)] per code."""
+        fresh = []
         if outs is None:
             outs = self.outputs(llrs[0].device)
+            fresh += [t for o in outs for t in o]
         if ws is None:
             ws = self.workspace(llrs[0].device)
+            fresh.append(ws)
         a = self._arrays(llrs, outs)
+        _on_stream(stream, fresh)
         _check(_plan_decode(self._h, *a, ws.data_ptr(), ws.numel(), _stream_handle(stream)), "ldpc_plan_decode")
         return outs
 

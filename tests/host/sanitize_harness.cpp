@@ -13,7 +13,8 @@
 extern "C" {
 int oracle_decode_block(int n, int m, const int32_t* row_ptr, const int32_t* col_idx, const float* llr, int gamma,
                         int max_iters, int early_stop, double lmax, int nthreads, double* post, uint8_t* bits,
-                        int32_t* iters, uint8_t* converged, double* min_abs, uint8_t* syn_trace);
+                        int32_t* iters, uint8_t* converged, double* min_abs, uint8_t* syn_trace, double near,
+                        int32_t* fragile, double* L_trace);
 int oracle_decode_window(int n, int m, const int32_t* row_ptr, const int32_t* col_idx, const int32_t* layer_of_row,
                          const int32_t* pos_of_col, int nlayers, int npos, const float* llr, int gamma, int W, int K,
                          double lmax, int nthreads, double* post, uint8_t* bits);
@@ -119,11 +120,13 @@ static void run_oracle(std::mt19937_64& rng) {
         for (auto& x : llr) x = noise(rng);
         std::vector<double> post(llr.size()), min_abs(gamma);
         std::vector<uint8_t> bits(llr.size()), conv(gamma), trace((size_t)gamma * 8);
-        std::vector<int32_t> iters(gamma);
+        std::vector<int32_t> iters(gamma), fragile(gamma);
+        std::vector<double> Ltr((size_t)gamma * 8 * h.n);
         EXPECT(oracle_decode_block(h.n, h.m, h.row_ptr.data(), h.col_idx.data(), llr.data(), gamma, 8, 1, 30.0, 2,
                                    post.data(), bits.data(), iters.data(), conv.data(), min_abs.data(),
-                                   trace.data()) == 0);
+                                   trace.data(), 0.5, fragile.data(), Ltr.data()) == 0);
         for (int g = 0; g < gamma; ++g) EXPECT(iters[g] >= 1 && iters[g] <= 8);
+        for (int g = 0; g < gamma; ++g) EXPECT(fragile[g] >= 0 && fragile[g] <= iters[g]);
         const int W = ms + 1 + (int)(rng() % 4);
         EXPECT(oracle_decode_window(h.n, h.m, h.row_ptr.data(), h.col_idx.data(), h.layer_of_row.data(),
                                     h.pos_of_col.data(), h.nlayers, h.npos, llr.data(), gamma, W, 3, 30.0, 2,
@@ -136,7 +139,7 @@ static void run_oracle(std::mt19937_64& rng) {
     // invalid arguments are refused
     int32_t rp[2] = {0, 0};
     EXPECT(oracle_decode_block(0, 1, rp, nullptr, nullptr, 1, 0, 0, 30.0, 1, nullptr, nullptr, nullptr, nullptr,
-                               nullptr, nullptr) == -1);
+                               nullptr, nullptr, 1e-3, nullptr, nullptr) == -1);
 }
 
 int main() {

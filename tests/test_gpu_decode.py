@@ -2,9 +2,18 @@
 on the same seeded inputs.
 
 Tolerance (FP32 GPU vs FP64 reference, LLRs clipped at 30):
-|clip(gpu) - clip(ref)| <= 1e-4 * max(|clip(ref)|, 1).  Hard decisions and
-iteration counts are compared exactly except on frames where the reference
-met some |L| < 1e-3 at a decision (there the sign is decided by rounding).
+|clip(gpu) - clip(ref)| <= 1e-4 * max(|clip(ref)|, 1) -- relative, with a
+floor of 1 so that it is 1e-4 absolute for |L| < 1.  Decisions take part in
+the result only through the syndrome test (which iteration is returned) and
+the returned bits, so:
+  * iteration counts and convergence flags are exact on every frame where no
+    decision with |L| < 1e-3 could have changed whether the syndrome is zero
+    (the reference's `fragile` diagnostic is 0);
+  * decisions are exact on frames that converged on both sides and on frames
+    whose every decision had |L| >= 1e-3;
+  * posteriors are gated on every frame after 1-3 iterations and on frames
+    that converged on both sides; on frames that never converge, BP amplifies
+    the rounding difference between FP32 and FP64, so they are not gated.
 """
 import os
 
@@ -51,19 +60,18 @@ def qc_case(J, L, p, seed, gamma, ebn0, noise_seed, codeword="zero"):
 
 
 def check_parity(gpu, ref, gate_all_posteriors, what):
-    exempt = ref["min_abs"] < 1e-3
-    ok = ~exempt
-    assert np.array_equal(gpu["bits"][ok], ref["bits"][ok]), f"{what}: hard decisions differ"
-    assert np.array_equal(gpu["iters"][ok], ref["iters"][ok]), f"{what}: iteration counts differ"
-    assert np.array_equal(gpu["converged"][ok], ref["converged"][ok]), f"{what}: convergence flags differ"
+    """Returns the number of frames whose posteriors were gated."""
+    robust = ref["fragile"] == 0
+    assert np.array_equal(gpu["iters"][robust], ref["iters"][robust]), f"{what}: iteration counts differ"
+    assert np.array_equal(gpu["converged"][robust], ref["converged"][robust]), f"{what}: convergence flags differ"
+    both = robust & (gpu["converged"] == 1) & (ref["converged"] == 1)
+    bitgate = both | (ref["min_abs"] >= 1e-3)
+    assert np.array_equal(gpu["bits"][bitgate], ref["bits"][bitgate]), f"{what}: hard decisions differ"
     err = rel_err(gpu["post"], ref["post"])
-    if gate_all_posteriors:
-        gate = np.ones(len(err), dtype=bool)
-    else:
-        gate = ok & (gpu["converged"] == 1) & (ref["converged"] == 1)
+    gate = np.ones(len(err), dtype=bool) if gate_all_posteriors else both
     worst = err[gate].max() if gate.any() else 0.0
     assert worst <= TOL, f"{what}: posterior error {worst:.3e} > {TOL}"
-    return worst
+    return int(gate.sum())
 
 
 # ----------------------------------------------------------------------------
@@ -151,6 +159,41 @@ def test_wide_rows_use_narrow_tiles():
         check_parity(gpu_decode(ldpc.Graph.qc(a, p), llr, 3, False), ref, True, f"{J}x{L}")
 
 
+@pytest.fixture
+def two_frames_per_lane(monkeypatch):
+    # LDPC_FRAMES_PER_LANE is read at every call; 2 is the most the tiling
+    # allows for rows of weight 9..16
+    monkeypatch.setenv("LDPC_FRAMES_PER_LANE", "2")
+
+
+@pytest.mark.parametrize("iters", [1, 2, 3])
+def test_rate_two_thirds_fixed_iterations_all_frames(iters, two_frames_per_lane):
+    # 3 x 9 base: rows of weight 9 (the 12-slot row class, 2 frames per
+    # lane, tiles of 128 frames); 370 frames = 3 tiles, the last one ragged
+    a, llr, _ = qc_case(3, 9, 72, 53, 370, 3.0, 401)
+    g = ldpc.Graph.qc(a, 72)
+    ref = oracle.decode_block(oracle.qc_parity_check(a, 72), llr, iters)
+    check_parity(gpu_decode(g, llr, iters, False), ref, True, f"3x9 I={iters}")
+
+
+def test_rate_two_thirds_twenty_iterations_early_stop(two_frames_per_lane):
+    a, llr, _ = qc_case(3, 9, 72, 53, 370, 2.5, 402)
+    g = ldpc.Graph.qc(a, 72)
+    H = oracle.qc_parity_check(a, 72)
+    ref = oracle.decode_block(H, llr, 20, early_stop=True)
+    gpu = gpu_decode(g, llr, 20, True)
+    check_parity(gpu, ref, False, "3x9 I=20 early stop")
+    assert np.array_equal(gpu["converged"].astype(bool), ~H.syndrome(gpu["bits"]).any(1))
+    assert gpu["converged"].sum() >= 300 and len(set(gpu["iters"].tolist())) >= 3
+
+
+def test_rate_two_thirds_one_frame_per_lane():
+    # the same rows with one frame per lane (the default tiling for 300 frames)
+    a, llr, _ = qc_case(3, 9, 40, 54, 300, 3.0, 403)
+    ref = oracle.decode_block(oracle.qc_parity_check(a, 40), llr, 3)
+    check_parity(gpu_decode(ldpc.Graph.qc(a, 40), llr, 3, False), ref, True, "3x9 one frame per lane")
+
+
 def test_degenerate_codes_and_inputs():
     # a variable in no check, weight-1 checks (alpha = +inf), all-zero and saturated LLRs
     a = np.array([[0, -1], [3, -1]])
@@ -213,6 +256,29 @@ def test_batch_and_permutation_invariance_and_determinism():
         assert np.array_equal(shuf[k], full[k][perm]), k
 
 
+def test_decode_on_another_stream_with_buffers_allocated_by_the_binding():
+    # workspace and outputs allocated by the binding on the current stream,
+    # the decode enqueued on a second stream (default priority): the same
+    # results as on the current stream, also while other work churns the
+    # allocator in between
+    a, llr, _ = qc_case(3, 6, 64, 1, 300, 1.75, 61)
+    g = ldpc.Graph.qc(a, 64)
+    x = torch.from_numpy(llr).to(DEV)
+    ref = [t.clone() for t in ldpc.decode(g, x, 15, early_stop=True)]
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream(device=DEV)
+    outs = []
+    for rep in range(3):
+        outs.append(ldpc.decode(g, x, 15, early_stop=True, stream=side))
+        junk = torch.empty(1 << 22, device=DEV).fill_(float(rep))   # reuses freed allocator blocks
+        del junk
+    side.synchronize()
+    torch.cuda.synchronize()
+    for o in outs:
+        for a_, b_ in zip(o, ref):
+            assert torch.equal(a_, b_)
+
+
 def test_codeword_symmetry():
     a, llr, cw = qc_case(3, 6, 64, 1, 128, 2.0, 21, codeword="random")
     g = ldpc.Graph.qc(a, 64)
@@ -242,7 +308,7 @@ def test_n18360_full_batch_sampled_frames():
     pick = np.array([0, 1, 255, 256, 511, 700, 1022, 1023])
     ref = oracle.decode_block(H, llr[pick], 20)
     sub = {k: v[pick] for k, v in gpu.items()}
-    check_parity(sub, ref, False, "n=18360 sampled")
+    assert check_parity(sub, ref, False, "n=18360 sampled") >= 4
     # the codewords were random: converged frames reproduce them, except for
     # rare undetected errors -- other codewords (QC codes with weight-1
     # circulants and three block rows have minimum distance at most 24)
@@ -257,9 +323,9 @@ def test_n18360_early_stop_sampled_frames():
     w = synth.workload_inputs("qc36_p3060", gamma=256, ebn0_db=1.25)
     a, llr = w["shifts"], w["llr"]
     gpu = gpu_decode(ldpc.Graph.qc(a, 3060), llr, 30, True)
-    pick = np.array([0, 3, 100, 200, 255])
+    pick = np.array([0, 3, 40, 77, 100, 130, 160, 200, 230, 255])
     ref = oracle.decode_block(oracle.qc_parity_check(a, 3060), llr[pick], 30, early_stop=True)
-    check_parity({k: v[pick] for k, v in gpu.items()}, ref, False, "n=18360 early stop")
+    assert check_parity({k: v[pick] for k, v in gpu.items()}, ref, False, "n=18360 early stop") >= 4
 
 
 # ----------------------------------------------------------------------------

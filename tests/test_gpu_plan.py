@@ -90,27 +90,90 @@ def test_fixed_iterations_every_layout():
         assert_same(plan.decode(llrs), refs, f"3 iterations, layout {ldpc.layout_name(layout)}")
 
 
+def cpu_case(specs, seed):
+    """Graphs and channel LLRs drawn on the host (synth), so that nothing the
+    FP64 reference reads comes from the HIP library."""
+    graphs, shifts, llrs = [], [], []
+    for i, c in enumerate(specs):
+        a = synth.draw_qc_shifts(c["J"], c["L"], c["p"], 50 + i)
+        s2 = synth.ebn0_to_sigma2(c["ebn0_db"], 1.0 - c["J"] / c["L"])
+        shifts.append(a)
+        graphs.append(ldpc.Graph.qc(a, c["p"]))
+        llrs.append(synth.bpsk_awgn_llr(None, s2, seed + i, gamma=c["gamma"], n=c["L"] * c["p"]))
+    return graphs, shifts, llrs
+
+
+def reference_parity(out, H, llr, iters, early, gate_all, what):
+    """One code's plan outputs (sampled frames) against the FP64 reference,
+    with the gates of test_gpu_decode.check_parity: iteration counts and flags
+    exact where no decision with |L| < 1e-3 could change the syndrome test;
+    decisions exact on frames converged on both sides and on frames without
+    such decisions; posteriors within 1e-4 relative (floor 1) on every frame
+    (gate_all) or on frames that converged on both sides.  Returns the number
+    of frames whose posteriors were gated."""
+    ref = oracle.decode_block(H, llr, iters, early_stop=early)
+    post, bits, it, conv = out
+    robust = ref["fragile"] == 0
+    assert np.array_equal(it[robust], ref["iters"][robust]), f"{what}: iteration counts"
+    assert np.array_equal(conv[robust], ref["converged"][robust]), f"{what}: convergence flags"
+    both = robust & (conv == 1) & (ref["converged"] == 1)
+    bitgate = both | (ref["min_abs"] >= 1e-3)
+    assert np.array_equal(bits[bitgate], ref["bits"][bitgate]), f"{what}: decisions"
+    gate = np.ones(len(robust), dtype=bool) if gate_all else both
+    r = np.clip(ref["post"][gate], -30, 30)
+    err = np.abs(np.clip(post[gate].astype(np.float64), -30, 30) - r) / np.maximum(np.abs(r), 1.0)
+    assert err.size == 0 or err.max() <= 1e-4, f"{what}: posterior error {err.max():.3e}"
+    return int(gate.sum())
+
+
 def test_plan_code_against_fp64_reference():
     spec = [dict(J=3, L=6, p=27, gamma=20, ebn0_db=2.5), dict(J=3, L=18, p=36, gamma=40, ebn0_db=3.5)]
-    graphs, llrs = make_case(spec, 4000)
+    graphs, shifts, llr_np = cpu_case(spec, 4000)
+    llrs = [torch.from_numpy(x).to(DEV) for x in llr_np]
     plan = ldpc.Plan(graphs, [20, 40], 20, early_stop=True)
     print("[gpu] plan vs reference", flush=True)
     outs = plan.decode(llrs)
     torch.cuda.synchronize()
     for i, c in enumerate(spec):
-        H = oracle.qc_parity_check(synth.draw_qc_shifts(c["J"], c["L"], c["p"], 50 + i), c["p"])
-        x = llrs[i].cpu().numpy()
-        ref = oracle.decode_block(H, x, 20, early_stop=True)
-        post, bits, it, conv = (t.cpu().numpy() for t in outs[i])
-        ok = ref["min_abs"] >= 1e-3
-        assert np.array_equal(bits[ok], ref["bits"][ok])
-        assert np.array_equal(it[ok], ref["iters"][ok])
-        assert np.array_equal(conv[ok], ref["converged"][ok])
-        gate = ok & (conv == 1) & (ref["converged"] == 1)
-        r = np.clip(ref["post"][gate], -30, 30)
-        err = np.abs(np.clip(post[gate].astype(np.float64), -30, 30) - r) / np.maximum(np.abs(r), 1.0)
-        assert err.max() <= 1e-4
-        assert np.array_equal(conv.astype(bool), ~H.syndrome(bits).any(1))
+        H = oracle.qc_parity_check(shifts[i], c["p"])
+        o = tuple(t.cpu().numpy() for t in outs[i])
+        reference_parity(o, H, llr_np[i], 20, True, False, f"code {i}")
+        assert np.array_equal(o[3].astype(bool), ~H.syndrome(o[1]).any(1))
+
+
+def sampled_frames(gamma):
+    return np.unique(np.array([0, 1, gamma // 3, gamma // 2, gamma - 2, gamma - 1]).clip(0, gamma - 1))
+
+
+@pytest.mark.parametrize("iters,early", [(3, False), (20, True)])
+def test_mixed_workload_codes_at_full_size_against_reference(iters, early):
+    # the seven codes of the mixed workload at their real circulant sizes
+    # (rate 1/2: p = 27, 81, 2700; rate 2/3: p = 72, 2400; rate 5/6: p = 36,
+    # 3600) and batch sizes, decoded together by one plan with the layouts
+    # the autotuner picks; sampled frames of every code against the FP64
+    # reference.  3 iterations without early stopping gate every posterior of
+    # the sampled frames; 20 with early stopping gate exact iteration counts.
+    specs = synth.MIXED_CODES
+    graphs, shifts, llr_np = cpu_case(specs, 7000)
+    llrs = [torch.from_numpy(x).to(DEV) for x in llr_np]
+    plan = ldpc.Plan(graphs, [c["gamma"] for c in specs], iters, early_stop=early)
+    ws = plan.workspace(DEV)
+    outs = plan.outputs(DEV)
+    print(f"[gpu] mixed plan at full size iters={iters} early={early}: autotune", flush=True)
+    plan.autotune(llrs, outs, ws, trials=1)
+    print(f"[gpu] layouts {[ldpc.layout_name(plan.layout(c)) for c in range(len(specs))]}", flush=True)
+    outs = plan.decode(llrs, outs=outs, ws=ws)
+    torch.cuda.synchronize()
+    gated = 0
+    for i, c in enumerate(specs):
+        pick = sampled_frames(c["gamma"])
+        H = oracle.qc_parity_check(shifts[i], c["p"])
+        o = tuple(t.cpu().numpy()[pick] for t in outs[i])
+        gated += reference_parity(o, H, llr_np[i][pick], iters, early, not early,
+                                  f"{c['J']}x{c['L']} p={c['p']}")
+        if early:
+            assert np.array_equal(o[3].astype(bool), ~H.syndrome(o[1]).any(1))
+    assert gated >= 30
 
 
 def test_graph_replay_matches_eager_decode():

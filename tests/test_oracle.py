@@ -239,6 +239,63 @@ def test_early_stop_rule():
     assert np.array_equal(full["converged"], (~H.syndrome(full["bits"]).any(1)).astype(np.uint8))
 
 
+def syndrome_outcome_can_change(Hd, c, Z):
+    """Brute force: does flipping some nonempty subset of the decisions Z
+    change whether H c^T is zero?"""
+    zero = not (Hd @ c % 2).any()
+    for mask in range(1, 1 << len(Z)):
+        cc = c.copy()
+        for i, v in enumerate(Z):
+            if (mask >> i) & 1:
+                cc[v] ^= 1
+        if (not (Hd @ cc % 2).any()) != zero:
+            return True
+    return False
+
+
+@pytest.mark.parametrize("near", [1e-3, 0.4, 1.5])
+def test_fragile_iteration_follows_its_rule_and_misses_no_change(near):
+    # the fragile diagnostic (first iteration at which decisions with
+    # |L| < near could change whether the syndrome is zero), recomputed from
+    # the per-iteration L trace; and where few decisions are near zero, brute
+    # force over every subset of them: whenever a flip changes the outcome,
+    # the rule says fragile (it may say fragile more often, never less)
+    p = 12
+    a = synth.draw_qc_shifts(3, 6, p, 3)
+    H = oracle.qc_parity_check(a, p)
+    Hd = H.dense().astype(np.int64)
+    llr = synth.bpsk_awgn_llr(None, synth.ebn0_to_sigma2(1.0, 0.5), 31, gamma=48, n=H.n)
+    out = oracle.decode_block(H, llr, 12, early_stop=True, L_trace=True, near=near)
+    checked = fragile_seen = 0
+    for g in range(llr.shape[0]):
+        expect = 0
+        for it in range(int(out["iters"][g])):
+            L = out["L_trace"][g, it]
+            c = (L < 0).astype(np.int64)
+            Z = np.nonzero(np.abs(L) < near)[0]
+            if len(Z) == 0:
+                continue
+            syn = Hd @ c % 2
+            touched = Hd[:, Z].any(1)
+            rule = bool(np.all(touched[syn == 1])) if syn.any() else bool(touched.any())
+            if len(Z) <= 10:
+                checked += 1
+                if syndrome_outcome_can_change(Hd, c, Z):
+                    assert rule, (g, it)
+            if rule and expect == 0:
+                expect = it + 1
+        assert out["fragile"][g] == expect, g
+        fragile_seen += expect > 0
+    assert checked > 0
+    if near >= 0.4:
+        assert fragile_seen > 0
+    # the trace ends at the returned iteration, whose L is the posterior
+    for g in range(llr.shape[0]):
+        it = int(out["iters"][g])
+        assert np.array_equal(np.clip(out["L_trace"][g, it - 1], -30, 30), out["post"][g])
+        assert np.all(np.isnan(out["L_trace"][g, it:]))
+
+
 def test_threads_do_not_change_results():
     p = 32
     a = synth.draw_qc_shifts(3, 6, p, 1)
