@@ -340,18 +340,37 @@ def gpu_window(g, llr, W, K):
     return dict(post=post.cpu().numpy(), bits=bits.cpu().numpy())
 
 
-def window_parity(gpu, ref, what):
-    # decisions exact away from |L| < 1e-3; posteriors gated on frames that
-    # decoded the all-zero codeword on both sides, reported elsewhere
-    close = np.abs(ref["post"]) < 1e-3
-    exempt = close.any(1)
-    ok = ~exempt
-    assert np.array_equal(gpu["bits"][ok], ref["bits"][ok]), f"{what}: decisions differ"
-    good = ok & (gpu["bits"].sum(1) == 0) & (ref["bits"].sum(1) == 0)
-    err = rel_err(gpu["post"], ref["post"])
-    worst = err[good].max() if good.any() else 0.0
+def window_parity(gpu, ref, what, c, back=8, ahead=5):
+    """Per code frame (chain position of c bits), as the paper's frames:
+    decisions exact at every position whose neighbourhood (`back` positions
+    before it, `ahead` after: the positions that share its windows or feed
+    them frozen messages) holds no reference posterior with |L| < 1e-3;
+    posteriors gated at every position whose neighbourhood decoded the
+    all-zero codeword on both sides (inside error bursts BP amplifies the
+    FP32/FP64 rounding difference).  Returns the fraction of positions whose
+    posteriors were gated."""
+    s = gpu["post"].shape[0]
+    P = gpu["post"].shape[1] // c
+    post_r = ref["post"].reshape(s, P, c)
+    close = (np.abs(post_r) < 1e-3).any(2)
+    wrong = gpu["bits"].reshape(s, P, c).any(2) | ref["bits"].reshape(s, P, c).any(2)
+
+    def spread(m):
+        out = np.zeros_like(m)
+        for d in range(-back, ahead + 1):
+            lo, hi = max(0, -d), min(P, P - d)
+            out[:, lo:hi] |= m[:, lo + d:hi + d]
+        return out
+
+    bitgate = np.repeat(~spread(close), c, axis=1)
+    assert np.array_equal(gpu["bits"][bitgate], ref["bits"][bitgate]), f"{what}: decisions differ"
+    gate = ~spread(close | wrong)
+    err = rel_err(gpu["post"], ref["post"]).reshape(s, P, c).max(2)
+    worst = err[gate].max() if gate.any() else 0.0
     assert worst <= TOL, f"{what}: posterior error {worst:.3e}"
-    return good.mean()
+    print(f"{what}: posteriors gated at {gate.sum()} of {gate.size} positions, decisions at "
+          f"{bitgate.sum() // c} of {gate.size}", flush=True)
+    return gate.mean()
 
 
 @pytest.mark.parametrize("p,positions,W,K,gamma,terminate", [(32, 16, 6, 10, 64, True), (17, 12, 3, 4, 100, True),
@@ -363,7 +382,7 @@ def test_window_decoder_small(p, positions, W, K, gamma, terminate):
     llr = synth.bpsk_awgn_llr(None, synth.ebn0_to_sigma2(1.5, 0.5), 103, gamma=gamma, n=Hc.n)
     ref = oracle.decode_window(Hc, llr, W, K)
     gpu = gpu_window(ldpc.Graph.ldpccc_from_qc(a, p, positions, terminate), llr, W, K)
-    window_parity(gpu, ref, f"window p={p}")
+    window_parity(gpu, ref, f"window p={p}", 2 * p)
 
 
 def test_window_decoder_single_position_window_tight():
@@ -385,7 +404,8 @@ def test_window_decoder_paper_scale_sampled_streams():
     Hc, _ = oracle.unwrap_qc(a, spec["p"], spec["positions"])
     pick = np.array([0, 257, 511])
     ref = oracle.decode_window(Hc, llr[pick], spec["window"], spec["iters_per_window"])
-    window_parity({k: v[pick] for k, v in gpu.items()}, ref, "cc p=512 sampled")
+    gated = window_parity({k: v[pick] for k, v in gpu.items()}, ref, "cc p=512 sampled", 2 * spec["p"])
+    assert gated >= 0.15
     # a 6-position window leaves residual errors at 1.5 dB (the full chain
     # decodes under flooding BP); the bit error rate stays low
     assert gpu["bits"].mean() < 1e-2
@@ -444,7 +464,7 @@ def test_window_ring_too_big_for_lds_takes_the_launch_path():
     ldpc.timing_enable(False)
     t = ldpc.timing_read()
     assert t["window_lds"][0] == 0 and t["window_check_node"][0] > 0, t
-    window_parity(gpu, oracle.decode_window(Hc, llr, W, K), "window p=1024")
+    window_parity(gpu, oracle.decode_window(Hc, llr, W, K), "window p=1024", 2 * p)
 
 
 # ----------------------------------------------------------------------------
@@ -470,7 +490,7 @@ def test_pipeline_decoder_small(p, positions, I, gamma, terminate):
     gpu = gpu_pipeline(ldpc.Graph.ldpccc_from_qc(a, p, positions, terminate), llr, I)
     if I <= 3:
         assert rel_err(gpu["post"], ref["post"]).max() <= TOL
-    window_parity(gpu, ref, f"pipeline p={p} I={I}")
+    window_parity(gpu, ref, f"pipeline p={p} I={I}", 2 * p)
 
 
 def test_pipeline_matches_flooding_reference_on_the_chain():
@@ -480,7 +500,7 @@ def test_pipeline_matches_flooding_reference_on_the_chain():
     llr = synth.bpsk_awgn_llr(None, synth.ebn0_to_sigma2(2.0, 0.5), 9, gamma=64, n=Hc.n)
     ref = oracle.decode_block(Hc, llr, 6)
     gpu = gpu_pipeline(ldpc.Graph.ldpccc_from_qc(a, 20, 10), llr, 6)
-    window_parity(gpu, ref, "pipeline vs flooding")
+    window_parity(gpu, ref, "pipeline vs flooding", 40)
 
 
 def test_pipeline_paper_scale_sampled_streams():
@@ -493,7 +513,8 @@ def test_pipeline_paper_scale_sampled_streams():
     Hc, info = oracle.unwrap_qc(a, spec["p"], spec["positions"])
     pick = np.array([0, 300, 511])
     ref = oracle.decode_pipeline(Hc, llr[pick], I, info["ms"])
-    window_parity({k: v[pick] for k, v in gpu.items()}, ref, "pipeline p=512 sampled")
+    gated = window_parity({k: v[pick] for k, v in gpu.items()}, ref, "pipeline p=512 sampled", 2 * spec["p"])
+    assert gated >= 0.5
     assert gpu["bits"].mean() < 1e-3
 
 
