@@ -168,6 +168,31 @@ ldpc_status ldpc_decode(const ldpc_graph* g, const float* llr, int32_t gamma, in
                         uint8_t* converged, void* workspace, size_t workspace_bytes, void* stream);
 
 /*
+ * ldpc_decode for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation.  It
+ * takes no workspace argument.  Its workspace is a static device array of
+ * LDPC_NOALLOC_SCRATCH_BYTES that the library holds once on every device it
+ * runs on, until the process ends; the first call on a device looks up that
+ * device's copy (hipGetSymbolAddress), later calls reuse the address.  The
+ * call itself allocates nothing (no hipMalloc, no hipFree, no events: kernel
+ * timing is not recorded for it).  The caller still passes the inputs and
+ * outputs, with the arguments, results and kernels of ldpc_decode; the
+ * stream must belong to the current device.
+ * Every call on a device shares that device's array, which keeps the last
+ * call's contents (the decode clears what must start at zero with a kernel,
+ * so no memset node is recorded under capture): calls that overlap on one
+ * device (on different streams, or from different threads) race and return
+ * garbage.  Serialise them.
+ * Errors: those of ldpc_decode; EWORKSPACE when the decode needs more than
+ * LDPC_NOALLOC_SCRATCH_BYTES (ldpc_workspace_size(g, gamma, max_iters, 0)
+ * tells); EUNSUPPORTED for a device ordinal >= 64.
+ */
+#define LDPC_NOALLOC_SCRATCH_BYTES (64u * 1024u * 1024u)
+ldpc_status ldpc_decode_noalloc(const ldpc_graph* g, const float* llr, int32_t gamma, int32_t max_iters,
+                                int32_t early_stop, float* post, uint8_t* bits, int32_t* iters,
+                                uint8_t* converged, void* stream);
+
+/*
  * Learned min-sum decoding (an addition to the paper: the neural normalized
  * / offset min-sum of Nachmani et al. 2016/2018 and Lugosch & Gross 2017 on
  * the flooding schedule of Algorithm 1).  The horizontal step (Eq. 3) is

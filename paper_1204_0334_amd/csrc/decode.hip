@@ -1703,6 +1703,7 @@ std::mutex mtx;
 bool enabled = false;
 std::vector<Rec> recs;
 std::vector<hipEvent_t> pool;
+thread_local bool suppressed = false;   // set while an entry point that must not create events runs
 int64_t launches[LDPC_TIMING_CLASSES];
 double total_ms[LDPC_TIMING_CLASSES];
 
@@ -1718,6 +1719,7 @@ hipEvent_t get_event() {
 }
 
 Scope::Scope(int cls, hipStream_t s) : st(s) {
+    if (suppressed) return;
     std::lock_guard<std::mutex> g(mtx);
     if (!enabled) return;
     Rec r{cls, get_event(), get_event()};
@@ -2389,6 +2391,70 @@ ldpc_status ldpc_decode(const ldpc_graph* g, const float* llr, int32_t gamma, in
                         size_t workspace_bytes, void* stream) {
     return decode_block(g, llr, gamma, max_iters, early_stop, post, bits, iters, converged, workspace, workspace_bytes,
                         stream, nullptr);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Decoding without allocation.  The workspace of ldpc_decode_noalloc is this
+// static device array: every device the library runs on holds one copy of
+// it, at its own address, until the process ends.  Host code never passes
+// the array's name to a kernel (on the host it is only a stand-in for the
+// symbol); it looks up each device's address once with hipGetSymbolAddress
+// and uses that.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[LDPC_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kScratchDevices = 64;
+std::mutex scratch_mtx;
+void* scratch_addr[kScratchDevices];
+
+// address of the current device's copy (looked up at the first call on it)
+ldpc_status scratch_for_current_device(void** out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return LDPC_EHIP;
+    }
+    if (dev < 0 || dev >= kScratchDevices) return LDPC_EUNSUPPORTED;
+    std::lock_guard<std::mutex> lock(scratch_mtx);
+    if (!scratch_addr[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return LDPC_EHIP;
+        }
+        scratch_addr[dev] = p;
+    }
+    *out = scratch_addr[dev];
+    return LDPC_OK;
+}
+
+struct NoTimingEvents {
+    bool was = timing::suppressed;
+    NoTimingEvents() { timing::suppressed = true; }
+    ~NoTimingEvents() { timing::suppressed = was; }
+};
+}  // namespace
+
+extern "C" {
+
+ldpc_status ldpc_decode_noalloc(const ldpc_graph* g, const float* llr, int32_t gamma, int32_t max_iters,
+                                int32_t early_stop, float* post, uint8_t* bits, int32_t* iters, uint8_t* converged,
+                                void* stream) {
+    if (!g || !llr || !post || !bits) return LDPC_EINVAL;
+    if (g->kind != LDPC_GRAPH_QC) return LDPC_EINVAL;
+    if (gamma < 1 || max_iters < 1 || max_iters > LDPC_MAX_ITERS) return LDPC_EINVAL;
+    if ((int64_t)gamma * g->n > ((int64_t)1 << 40)) return LDPC_EUNSUPPORTED;
+    const size_t need = block_layout(g, choose_tiling(gamma, g), max_iters).total;
+    if (need > (size_t)LDPC_NOALLOC_SCRATCH_BYTES) return LDPC_EWORKSPACE;
+    void* ws = nullptr;
+    const ldpc_status got = scratch_for_current_device(&ws);
+    if (got != LDPC_OK) return got;
+    NoTimingEvents quiet;
+    return decode_block(g, llr, gamma, max_iters, early_stop, post, bits, iters, converged, ws,
+                        (size_t)LDPC_NOALLOC_SCRATCH_BYTES, stream, nullptr);
 }
 
 ldpc_status ldpc_nms_decode(const ldpc_graph* g, const float* llr, int32_t gamma, int32_t iters, const float* weights,

@@ -40,6 +40,7 @@ def layout_name(layout: int) -> str:
 PLAN_MAX_CODES = 16
 TIMING_CLASSES = 22
 MAX_ITERS = 100000
+NOALLOC_SCRATCH_BYTES = 64 * 1024 * 1024
 
 
 class GraphInfo(ctypes.Structure):
@@ -64,6 +65,7 @@ _get_info = _sig("ldpc_graph_get_info", _i32, [_vp, ctypes.POINTER(GraphInfo)])
 _destroy = _sig("ldpc_graph_destroy", None, [_vp])
 _ws_size = _sig("ldpc_workspace_size", _i32, [_vp, _i32, _i32, _i32, ctypes.POINTER(_sz)])
 _decode = _sig("ldpc_decode", _i32, [_vp, _vp, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _sz, _vp])
+_decode_noalloc = _sig("ldpc_decode_noalloc", _i32, [_vp, _vp, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp])
 _nms_decode = _sig("ldpc_nms_decode", _i32, [_vp, _vp, _i32, _i32, _vp, _i32, _vp, _vp, _vp, _vp, _vp, _sz, _vp])
 _nms_ws_size = _sig("ldpc_nms_train_workspace_size", _i32, [_vp, _i32, _i32, _i32, ctypes.POINTER(_sz)])
 _nms_forward = _sig("ldpc_nms_train_forward", _i32, [_vp, _vp, _i32, _i32, _i32, _vp, _vp, _vp, _sz, _vp])
@@ -88,7 +90,7 @@ _timing_read = _sig("ldpc_timing_read", _i32, [ctypes.POINTER(_i64), ctypes.POIN
 _class_name = _sig("ldpc_kernel_class_name", ctypes.c_char_p, [_i32])
 
 EXPORTED = ["ldpc_graph_create_qc", "ldpc_graph_create_ldpccc_from_qc", "ldpc_graph_create_ldpccc_sf",
-            "ldpc_graph_get_info", "ldpc_graph_destroy", "ldpc_workspace_size", "ldpc_decode",
+            "ldpc_graph_get_info", "ldpc_graph_destroy", "ldpc_workspace_size", "ldpc_decode", "ldpc_decode_noalloc",
             "ldpc_nms_decode", "ldpc_nms_train_workspace_size", "ldpc_nms_train_forward",
             "ldpc_nms_train_backward", "ldpc_plan_create", "ldpc_plan_destroy", "ldpc_plan_workspace_size",
             "ldpc_plan_set_layout", "ldpc_plan_get_layout", "ldpc_plan_decode", "ldpc_plan_capture",
@@ -248,6 +250,24 @@ def decode(g: Graph, llr, max_iters: int, early_stop: bool = False, out=None, ws
     _check(_decode(g.handle, llr.data_ptr(), gamma, int(max_iters), int(bool(early_stop)), post.data_ptr(),
                    bits.data_ptr(), iters.data_ptr(), conv.data_ptr(), ws.data_ptr(), ws.numel(),
                    _stream_handle(stream)), "ldpc_decode")
+    return post, bits, iters, conv
+
+
+def decode_noalloc(g: Graph, llr, max_iters: int, early_stop: bool = False, out=None, stream=None):
+    """ldpc_decode_noalloc: decode without a workspace; the library's static
+    per-device array of NOALLOC_SCRATCH_BYTES serves as one (calls on one
+    device must not overlap).  Outputs as for decode; pass `out` to keep this
+    binding from allocating them."""
+    if llr.dim() != 2:
+        raise ValueError("llr must be [gamma, n]")
+    gamma, n = llr.shape
+    _need(llr, torch.float32, (gamma, g.n), "llr")
+    fresh = []
+    post, bits, iters, conv = _decode_outputs(llr, gamma, n, out, fresh)
+    _on_stream(stream, fresh)
+    _check(_decode_noalloc(g.handle, llr.data_ptr(), gamma, int(max_iters), int(bool(early_stop)), post.data_ptr(),
+                           bits.data_ptr(), iters.data_ptr(), conv.data_ptr(), _stream_handle(stream)),
+           "ldpc_decode_noalloc")
     return post, bits, iters, conv
 
 

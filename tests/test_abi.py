@@ -152,6 +152,26 @@ def test_decode_validates_before_launching():
     assert d(qc.handle, FAKE, 1024, 20, 1, FAKE, FAKE, FAKE, FAKE, FAKE, ws, None) == ldpc.EWORKSPACE
 
 
+def test_decode_noalloc_validates_before_launching():
+    qc = ldpc.Graph.qc(synth.draw_qc_shifts(3, 6, 64, 1), 64)
+    cc = ldpc.Graph.ldpccc_from_qc(synth.draw_qc_shifts(3, 6, 32, 2), 32, 16)
+    d = ldpc._decode_noalloc
+    assert d(qc.handle, None, 64, 20, 1, FAKE, FAKE, FAKE, FAKE, None) == ldpc.EINVAL
+    assert d(qc.handle, FAKE, 64, 20, 1, None, FAKE, FAKE, FAKE, None) == ldpc.EINVAL
+    assert d(qc.handle, FAKE, 64, 20, 1, FAKE, None, FAKE, FAKE, None) == ldpc.EINVAL
+    assert d(None, FAKE, 64, 20, 1, FAKE, FAKE, FAKE, FAKE, None) == ldpc.EINVAL
+    assert d(cc.handle, FAKE, 64, 20, 1, FAKE, FAKE, FAKE, FAKE, None) == ldpc.EINVAL
+    assert d(qc.handle, FAKE, 0, 20, 1, FAKE, FAKE, FAKE, FAKE, None) == ldpc.EINVAL
+    assert d(qc.handle, FAKE, 64, 0, 1, FAKE, FAKE, FAKE, FAKE, None) == ldpc.EINVAL
+    assert d(qc.handle, FAKE, 64, ldpc.MAX_ITERS + 1, 1, FAKE, FAKE, FAKE, FAKE, None) == ldpc.EINVAL
+    # the static workspace bounds the batch: 1024 frames of n = 18360 need
+    # about 300 MB, more than it holds
+    big = ldpc.Graph.qc(synth.draw_qc_shifts(3, 6, 3060, 2), 3060)
+    assert big.workspace_size(1024, 20) > ldpc.NOALLOC_SCRATCH_BYTES
+    assert d(big.handle, FAKE, 1024, 20, 1, FAKE, FAKE, FAKE, FAKE, None) == ldpc.EWORKSPACE
+    assert ldpc.status_str(ldpc.EWORKSPACE)
+
+
 def test_decode_window_validates_before_launching():
     qc = ldpc.Graph.qc(synth.draw_qc_shifts(3, 6, 64, 1), 64)
     cc = ldpc.Graph.ldpccc_from_qc(synth.draw_qc_shifts(3, 6, 32, 2), 32, 16)
