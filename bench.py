@@ -29,6 +29,7 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 METRIC = "coded Mbit/s at 20 BP iters (n=18360, Γ=1024) + %HBM peak; FER learned vs plain"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_qc36_p3060.json")
+TRAFFIC_FILE_4096 = os.path.join(ROOT, "profiles", "traffic_qc36_p3060_g4096.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1204_0334_amd", "csrc", f)
                   for f in ("decode.hip", "device.h", "internal.h")]
 
@@ -720,7 +721,8 @@ def early_stop_sweep(g, gamma, iters, points, steps=5):
 
 def gamma_control(g, llr_dev, iters, gamma, steps=5):
     """The benchmark decode at a larger batch whose working set exceeds the
-    256 MB Infinity Cache (frames repeated from the benchmark batch)."""
+    256 MB Infinity Cache (frames repeated from the benchmark batch), with the
+    roofline of its variable-node pass: the HBM-resident figure."""
     import torch
 
     from paper_1204_0334_amd import ldpc
@@ -737,8 +739,24 @@ def gamma_control(g, llr_dev, iters, gamma, steps=5):
     b.record()
     torch.cuda.synchronize()
     ms = a.elapsed_time(b) / steps
+    ldpc.timing_read()
+    ldpc.timing_enable(True)
+    for _ in range(steps):
+        ldpc.decode(g, x, iters, False, out=out, ws=ws)
+    torch.cuda.synchronize()
+    ldpc.timing_enable(False)
+    per_kernel = ldpc.timing_read()
     del out, ws, x
-    return {"gamma": gamma, "ms_per_step": round(ms, 4), "coded_mbps": round(gamma * g.n / (ms * 1e-3) / 1e6, 1)}
+    algo = algorithmic_bytes(g.n, g.info["E"], gamma)["variable_node"]
+    launches, kms = per_kernel["variable_node"]
+    avg_s = kms / launches * 1e-3
+    achieved = algo / avg_s / 1e9
+    roof = {"kernel": "variable_node", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "avg_launch_us": round(avg_s * 1e6, 2),
+            "algorithmic_bytes_per_launch": algo,
+            "traffic": measured_traffic("variable_node", TRAFFIC_FILE_4096)}
+    return {"gamma": gamma, "ms_per_step": round(ms, 4), "coded_mbps": round(gamma * g.n / (ms * 1e-3) / 1e6, 1),
+            "roofline": roof}
 
 
 def main():
@@ -774,16 +792,26 @@ def main():
     ap.add_argument("--fer-frames", type=int, default=1 << 17,
                     help="benchmark line: frames per Eb/N0 point of its learned-vs-plain FER check (0: skip)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
-                    help="only run 5 device-to-device copies of BYTES (counter calibration) and exit")
+                    help="only run 6 device-to-device copies of BYTES (counter calibration and the copy "
+                         "bandwidth ceiling; the last 5 are timed) and exit")
     args = ap.parse_args()
     if args.calibrate_copy:
         import torch
         src = torch.ones(args.calibrate_copy // 4, dtype=torch.float32, device="cuda:0")
         dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
         for _ in range(5):
             dst.copy_(src)
+        b.record()
         torch.cuda.synchronize()
-        print(json.dumps({"copy_bytes": src.numel() * 4, "copies": 5}), flush=True)
+        ms = a.elapsed_time(b) / 5
+        nbytes = src.numel() * 4
+        # a copy reads and writes every byte once
+        print(json.dumps({"copy_bytes": nbytes, "copies": 6, "ms_per_copy": round(ms, 4),
+                          "read_plus_write_gbs": round(2 * nbytes / (ms * 1e-3) / 1e9, 1)}), flush=True)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this decoder runs on a single MI355X; a batch of frames "
@@ -880,6 +908,8 @@ def main():
                                "avg_iters_sp30": r["sp30"]["avg_iters"]} for r in learned["points"]]}
     sweep = early_stop_sweep(g, gamma, iters, [1.0, 1.25, 1.5, 1.75, 2.0, 2.25, 2.5]) if args.extras else None
     control = gamma_control(g, llr, iters, 4096) if args.extras else None
+    if control is not None:
+        roofline["gamma_4096"] = control["roofline"]
     cpu = None if args.no_cpu else cpu_baseline(shifts, p, llr_h, iters, min(args.cpu_sample, gamma))
     line = {
         "metric": METRIC, "value": round(value, 2), "unit": "coded Mbit/s", "n_gpus": 1, "steps": args.steps,

@@ -359,7 +359,8 @@ def window_parity(gpu, ref, what, c, back=8, ahead=5):
         out = np.zeros_like(m)
         for d in range(-back, ahead + 1):
             lo, hi = max(0, -d), min(P, P - d)
-            out[:, lo:hi] |= m[:, lo + d:hi + d]
+            if lo < hi:
+                out[:, lo:hi] |= m[:, lo + d:hi + d]
         return out
 
     bitgate = np.repeat(~spread(close), c, axis=1)
