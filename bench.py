@@ -369,12 +369,12 @@ def bench_train(args):
     from paper_1204_0334_amd import fer, ldpc, nnms
     spec = synth.WORKLOADS["qc36_p3060"]
     g = ldpc.Graph.qc(synth.draw_qc_shifts(3, 6, spec["p"], spec["shift_seed"]), spec["p"])
-    n, E, J = g.info["n"], g.info["E"], g.info["J"]
+    n, E, nb = g.info["n"], g.info["E"], g.info["blocks"]
     gamma, T, k = args.gamma, 12, 4
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     llr = ldpc.awgn_llr(n, gamma, fer.ebn0_to_sigma2(1.75, 0.5), 11, 0, device=dev)
-    W = nnms.initial_weights(T, J, 0.8, 0.0, device=dev).requires_grad_(True)
+    W = nnms.initial_weights(T, nb, 0.8, 0.0, device=dev).requires_grad_(True)
     opt = torch.optim.Adam([W], lr=0.01)
     ws = ldpc.nms_train_workspace(g, gamma, T, k, dev)
 
@@ -507,6 +507,25 @@ def bench_plan(args):
     plan.capture(llrs, outs, ws)
     ms = timed(plan.replay, args.steps, args.warmup)
     conv = sum(int(o[3].sum()) for o in outs) / sum(gammas)
+    # the same decode as one persistent launch: with the layouts tuned for the
+    # phase launches, then with layouts tuned for itself (graph replay both)
+    per = ldpc.Plan(graphs, gammas, iters, early_stop=True)
+    per.set_persistent(True)
+    for c in range(len(graphs)):
+        per.set_layout(c, plan.layout(c))
+    pws = per.workspace(dev)
+    pouts = per.outputs(dev)
+    per.decode(llrs, outs=pouts, ws=pws)
+    per.check(pws)
+    per.capture(llrs, pouts, pws)
+    per_same_ms = timed(per.replay, args.steps, args.warmup)
+    per_tuned_ms = per.autotune(llrs, pouts, pws, trials=3)
+    per_layouts = [ldpc.layout_name(per.layout(c)) for c in range(len(graphs))]
+    per.capture(llrs, pouts, pws)
+    per_ms = timed(per.replay, args.steps, args.warmup)
+    per.check(pws)
+    same = all(torch.equal(a, b) for o, q in zip(outs, pouts) for a, b in zip(o, q))
+    del pws, pouts
     # the same frames code by code
     wss = [ldpc.workspace(g, x, iters, 0, dev) for g, x in zip(graphs, gammas)]
     souts = [ldpc.decode(g, x, iters, True, ws=w) for g, x, w in zip(graphs, llrs, wss)]
@@ -561,6 +580,12 @@ def bench_plan(args):
             "; 20 flooding sum-product iterations with early stop; HIP graph replay",
                    "coded_bits_per_step": bits, "layouts": layouts, "autotuned_ms": round(tuned_ms, 4),
                    "frames_converged": round(conv, 4)},
+        "persistent": {"ms_per_step": round(per_ms, 4), "value": round(bits / (per_ms * 1e-3) / 1e6, 2),
+                       "vs_phase_launches": round(ms / per_ms, 3), "layouts": per_layouts,
+                       "autotuned_ms": round(per_tuned_ms, 4),
+                       "ms_with_phase_launch_layouts": round(per_same_ms, 4),
+                       "outputs_equal_phase_launches": bool(same),
+                       "how": "one persistent launch per decode (ldpc_plan_set_persistent), HIP graph replay"},
         "sequential": {"ms_per_step": round(seq_ms, 4), "value": round(bits / (seq_ms * 1e-3) / 1e6, 2),
                        "speedup_of_plan": round(seq_ms / ms, 3),
                        "how": "the same frames decoded code by code with ldpc_decode (early stop)"},
@@ -593,7 +618,7 @@ def learned_vs_plain(g, points, *, train_frames: int, eval_frames: int, T: int =
     if ckpt_every is None:
         ckpt_every = nnms.choose_ckpt_every(g, 1024, T, dev)
     W, hist = nnms.train(g, T=T, ckpt_every=ckpt_every, frames=train_frames, batch=1024, lr=0.01, seed=7,
-                         init=nnms.initial_weights(T, g.info["J"], 0.8, 0.0, device=dev), log_every=128)
+                         init=nnms.initial_weights(T, g.info["blocks"], 0.8, 0.0, device=dev), log_every=128)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
     rows = []
@@ -609,7 +634,7 @@ def learned_vs_plain(g, points, *, train_frames: int, eval_frames: int, T: int =
         row = {"ebn0_db": e, "learned_nms": run("nms", weights=W), "sp30": run("block", iters=30)}
         if extra:
             row["sp_T"] = run("block", iters=T)
-            row["nms_untrained"] = run("nms", weights=nnms.initial_weights(T, g.info["J"], 0.8, 0.0, device=dev))
+            row["nms_untrained"] = run("nms", weights=nnms.initial_weights(T, g.info["blocks"], 0.8, 0.0, device=dev))
         rows.append(row)
         if log:
             log(row)

@@ -69,6 +69,8 @@ typedef struct {
     int32_t c, c_minus_b;    /* convolutional: bits per code position, checks per layer */
     int32_t positions;       /* convolutional: code positions kept (terminated chain) */
     int32_t layers;          /* convolutional: check layers kept */
+    int32_t blocks;          /* nonzero circulants of the QC base (numbered row by row, left to
+                                right) or of the syndrome-former table */
     double design_rate;      /* 1 - J/L (QC), b/c (convolutional) */
 } ldpc_graph_info;
 
@@ -196,13 +198,16 @@ ldpc_status ldpc_decode_noalloc(const ldpc_graph* g, const float* llr, int32_t g
  * Learned min-sum decoding (an addition to the paper: the neural normalized
  * / offset min-sum of Nachmani et al. 2016/2018 and Lugosch & Gross 2017 on
  * the flooding schedule of Algorithm 1).  The horizontal step (Eq. 3) is
- * replaced, at iteration t for a check row of base row j, by
- *   alpha_k = w[t][j] * s_k * max(m_k - b[t][j], 0),
+ * replaced, at iteration t on edge k of a check row, by
+ *   alpha_k = w[t][e] * s_k * max(m_k - b[t][e], 0),
+ * e = the edge's class: its circulant block (0 .. blocks-1, the base's
+ * nonzero blocks numbered row by row, left to right; ldpc_graph_info.blocks),
  * m_k = min(|beta_k'|) over the row's other edges (|beta| clipped at 30),
  * s_k = product of their signs (negative iff beta < 0).  The vertical step
  * (Eq. 4), the posterior (Eq. 5), the decision (Eq. 6), the clip of beta at
  * +-30 and early stopping are those of ldpc_decode.
- *   weights  device, float [iters][J][2]: (w, b) per iteration and base row
+ *   weights  device, float [iters][blocks][2]: (w, b) per iteration and edge
+ *            class
  *   iters    iterations, 1..LDPC_MAX_ITERS (the weight rows used)
  * Other arguments as for ldpc_decode (workspace from
  * ldpc_workspace_size(g, gamma, iters, 0)).  Errors: those of ldpc_decode,
@@ -226,7 +231,7 @@ ldpc_status ldpc_nms_decode(const ldpc_graph* g, const float* llr, int32_t gamma
  *
  * ldpc_nms_train_backward, called after ldpc_nms_train_forward on the same
  * workspace with the same graph, gamma, iters, ckpt_every and weights,
- * writes grad (device float [iters][J][2]) = d(sum_t dloss[t] loss[t]) /
+ * writes grad (device float [iters][blocks][2]) = d(sum_t dloss[t] loss[t]) /
  * d weights, for dloss device float [iters] (the upstream gradient).  It
  * recomputes each segment of ckpt_every iterations from its checkpoint
  * and runs the hand-written backward of the vertical and horizontal steps
@@ -331,6 +336,37 @@ ldpc_status ldpc_plan_autotune(ldpc_plan* plan, const float* const* llr, float* 
                                size_t workspace_bytes, int32_t trials, void* stream, double* best_ms);
 
 /*
+ * Persistent launch of a plan (the paper's flexibility claim of its
+ * Conclusion, with Algorithm 1 run for several codes at once): with `on` = 1,
+ * ldpc_plan_decode, ldpc_plan_capture and ldpc_plan_autotune enqueue the
+ * whole decode as ONE kernel instead of 2 * max_iters + 4 phase launches.
+ * Inside it, workgroups take numbered tickets of work (a few wavefronts of
+ * one step of one code); steps of one code run in order (ingest, then per
+ * iteration the check-node pass, the flag reduction, the variable-node pass,
+ * then the final syndrome, frame status and output), while different codes
+ * advance independently.  A ticket waits only for tickets of lower numbers,
+ * so the launch needs no co-residency of its workgroups.  Results equal the
+ * phase launches' bit for bit (same device functions, same order within
+ * each step).  Each wait is bounded by wait_limit_us (0: 2 s); if a wait
+ * expires the kernel stops early and still exits normally, leaving the
+ * outputs undefined, and the next ldpc_plan_check reports it.  Switching
+ * the mode invalidates a captured graph.
+ *   on             0 (the phase launches, the default) or 1
+ *   wait_limit_us  >= 0
+ * Errors: EINVAL (NULL plan, on not 0/1, negative limit), EHIP (device
+ * queries).  ldpc_plan_decode / _capture return EUNSUPPORTED in persistent
+ * mode when a decode would need 2^31 tickets or more, or a code's share of
+ * the workspace is 2 GiB or more.
+ *
+ * ldpc_plan_check: synchronises `stream`, then returns EHIP if a persistent
+ * decode on this workspace had a wait expire since the last check (and
+ * clears that record), LDPC_OK otherwise.  workspace: the plan's workspace
+ * (device), after at least one decode with the current buffers.
+ */
+ldpc_status ldpc_plan_set_persistent(ldpc_plan* plan, int32_t on, int64_t wait_limit_us);
+ldpc_status ldpc_plan_check(ldpc_plan* plan, void* workspace, void* stream);
+
+/*
  * Sliding-window decoding of `gamma` independent streams of a terminated
  * convolutional graph (Sec. II-E: checks span at most ms+1 positions).  For
  * target position s = 0..positions-1: the window holds check layers
@@ -422,10 +458,11 @@ const char* ldpc_status_str(ldpc_status s);
  *   check-node backward, 16 training loss and gradient reductions,
  *   17 plan ingest, 18 plan check-node, 19 plan variable-node, 20 plan
  *   final syndrome, frame status and output, 21 window decoding with the
- *   ring in LDS (one launch per call).
+ *   ring in LDS (one launch per call), 22 plan decode in one persistent
+ *   launch.
  * ldpc_kernel_class_name returns a static name for a class index.
  */
-#define LDPC_TIMING_CLASSES 22
+#define LDPC_TIMING_CLASSES 23
 ldpc_status ldpc_timing_enable(int32_t enable);
 ldpc_status ldpc_timing_read(int64_t* launches, double* total_ms, int32_t capacity);
 const char* ldpc_kernel_class_name(int32_t cls);

@@ -5,13 +5,16 @@ never by the product).
 
 The decoder keeps the flooding schedule of Algorithm 1 and replaces the
 check-node rule (Eq. 3) by a scaled and offset minimum, with one scale w and
-one offset b per iteration t and per base row (check-node class) j -- the
-neural normalized / offset min-sum of Nachmani et al. (2016, 2018) and
-Lugosch & Gross (2017):
+one offset b per iteration t and per edge class e -- the neural normalized /
+offset min-sum of Nachmani et al. (2016, 2018) and Lugosch & Gross (2017),
+with weights shared by the edges of a class:
 
-    alpha_mn = w[t, j] * prod_{n' != n} sgn(beta_mn') * max(min_{n' != n} |beta_mn'| - b[t, j], 0)
+    alpha_mn = w[t, e] * prod_{n' != n} sgn(beta_mn') * max(min_{n' != n} |beta_mn'| - b[t, e], 0)
 
-with sgn(x) = -1 for x < 0 and +1 otherwise.  The variable-node step (Eq. 4,
+where e is the class of edge (m, n) and sgn(x) = -1 for x < 0 and +1
+otherwise.  For a QC code (Eq. 2) the class of an edge is its circulant
+block: the nonzero blocks of the base matrix numbered row by row, left to
+right (18 classes for a full 3 x 6 base).  The variable-node step (Eq. 4,
 a direct sum over the other edges), the posterior (Eq. 5), the hard decision
 (Eq. 6) and the clip of beta at +-30 are those of the sum-product decoder.
 Training loss: binary cross-entropy of every iteration's posterior against the
@@ -32,10 +35,10 @@ LMAX = 30.0
 
 class EdgeGraph:
     """Edges of an explicit parity-check matrix (row-major) with tables of the
-    edges of every row and of every column, and each row's class (its base
-    row for a QC code)."""
+    edges of every row and of every column, and each edge's class (edge ids
+    in row-major order; default: one class)."""
 
-    def __init__(self, H, row_class=None):
+    def __init__(self, H, edge_class=None):
         rp = np.asarray(H.row_ptr, dtype=np.int64)
         ci = np.asarray(H.col_idx, dtype=np.int64)
         self.n, self.m = H.n, H.m
@@ -57,16 +60,32 @@ class EdgeGraph:
         ct = -np.ones((H.n, dv), dtype=np.int64)
         ct[ci[order], cpos] = order
         self.coltab = torch.from_numpy(ct)
-        rc = np.zeros(H.m, dtype=np.int64) if row_class is None else np.asarray(row_class, dtype=np.int64)
-        self.row_class = torch.from_numpy(rc)
+        ec = np.zeros(self.E, dtype=np.int64) if edge_class is None else np.asarray(edge_class, dtype=np.int64)
+        if ec.shape != (self.E,):
+            raise ValueError("one class per edge")
+        self.edge_class = torch.from_numpy(ec)
 
 
-def qc_row_class(J: int, p: int) -> np.ndarray:
-    return np.repeat(np.arange(J), p)
+def qc_edge_class(shifts, p: int) -> np.ndarray:
+    """Class of every edge of the QC code of `shifts` (row-major edge order,
+    as qc_parity_check lays it out): the index of its circulant block among
+    the base's nonzero blocks, numbered row by row, left to right.  Row
+    (j, s) meets its blocks in increasing base column, which is also the
+    order of its columns."""
+    a = np.asarray(shifts)
+    J, L = a.shape
+    block = -np.ones((J, L), dtype=np.int64)
+    nz = a >= 0
+    block[nz] = np.arange(int(nz.sum()))
+    out = []
+    for j in range(J):
+        row = block[j][block[j] >= 0]
+        out.append(np.tile(row, p))
+    return np.concatenate(out) if out else np.zeros(0, dtype=np.int64)
 
 
 def check_step(G: EdgeGraph, beta: torch.Tensor, w: torch.Tensor, b: torch.Tensor) -> torch.Tensor:
-    """alpha [F, E] from beta [F, E]; w, b [classes]."""
+    """alpha [F, E] from beta [F, E]; w, b [edge classes]."""
     F = beta.shape[0]
     pad = G.rowtab < 0
     mag = beta.abs()[:, G.rowtab.clamp(min=0)]                   # [F, m, dc]
@@ -78,8 +97,9 @@ def check_step(G: EdgeGraph, beta: torch.Tensor, w: torch.Tensor, b: torch.Tenso
     excl_min = torch.where(other, mag.unsqueeze(-2), torch.full_like(mag.unsqueeze(-2), float("inf"))).amin(-1)
     excl_neg = (neg.unsqueeze(-2) & other).sum(-1) % 2
     sgn = 1.0 - 2.0 * excl_neg.to(beta.dtype)
-    wr = w[G.row_class].view(1, -1, 1)
-    br = b[G.row_class].view(1, -1, 1)
+    cls = G.edge_class[G.rowtab.clamp(min=0)]                    # [m, dc]
+    wr = w[cls].unsqueeze(0)
+    br = b[cls].unsqueeze(0)
     a_rows = wr * sgn * torch.clamp(excl_min - br, min=0.0)     # [F, m, dc]
     alpha = torch.zeros((F, G.E), dtype=beta.dtype)
     alpha = alpha.index_put((torch.arange(F).view(-1, 1), G.rowtab[~pad].view(1, -1)), a_rows[:, ~pad])
@@ -103,7 +123,8 @@ def variable_step(G: EdgeGraph, mu: torch.Tensor, alpha: torch.Tensor, lmax: flo
 
 
 def run(G: EdgeGraph, llr, w, b, T: int, lmax: float = LMAX):
-    """T iterations of the learned min-sum decoder.  llr [F, n]; w, b [T, J].
+    """T iterations of the learned min-sum decoder.  llr [F, n]; w, b [T,
+    edge classes].
     Returns the posteriors L^(1..T), each [F, n]."""
     mu = torch.as_tensor(np.asarray(llr), dtype=torch.float64)
     beta = torch.clamp(mu[:, G.col], -lmax, lmax)

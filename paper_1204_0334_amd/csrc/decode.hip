@@ -267,8 +267,14 @@ __device__ __forceinline__ void cn_row(const QCDesc& D, const BlockParams& P, co
     if constexpr (RULE == 0) {
         sp_check<DCMAX, FPL>(in, R.d, outv);
     } else {
-        const float* wp = P.nms_w + ((size_t)(P.iter - 1) * D.J + R.j) * 2;
-        const float w = wp[0], b = wp[1];
+        // (scale, offset) of each edge's class: its circulant block b0 + k
+        const float* wp = P.nms_w + ((size_t)(P.iter - 1) * D.nb + R.b0) * 2;
+        float w[DCMAX], b[DCMAX];
+#pragma unroll
+        for (int k = 0; k < DCMAX; ++k) {
+            w[k] = R.valid(D, k) ? wp[2 * k] : 0.0f;
+            b[k] = R.valid(D, k) ? wp[2 * k + 1] : 0.0f;
+        }
 #pragma unroll
         for (int f = 0; f < FPL; ++f) {
             float mag[DCMAX];
@@ -283,7 +289,7 @@ __device__ __forceinline__ void cn_row(const QCDesc& D, const BlockParams& P, co
 #pragma unroll
             for (int k = 0; k < DCMAX; ++k) {
                 const float m = (k == mi.idx1) ? mi.min2 : mi.min1;
-                const float a = w * fmaxf(m - b, 0.0f);
+                const float a = w[k] * fmaxf(m - b[k], 0.0f);
                 outv[k][f] = (mi.parity ^ neg[k]) ? -a : a;
             }
         }
@@ -854,8 +860,9 @@ __device__ __forceinline__ float abs_grad(float x) { return x > 0.0f ? 1.0f : (x
 //   dw += dA_k s_k max(a_k, 0),  db -= dA_k w s_k [a_k > 0],
 //   the gradient w s_k [a_k > 0] dA_k reaches |beta| of the edge holding m_k
 // (the row minimum for k != argmin, the second minimum for k = argmin).
-// Writes dB (gradient with respect to the betas read; NULL at iteration 1) and
-// the wave's (dw, db) partial sums.
+// Weights per edge class (the edge's circulant block).  Writes dB (gradient
+// with respect to the betas read; NULL at iteration 1) and the wave's (dw, db)
+// partial sums, one pair per edge slot of the row.
 template <int DCMAX, int FPL>
 __global__ void __launch_bounds__(kBlock) nms_cn_backward_kernel(const QCDesc D, const BlockParams P,
                                                                  const float* src, const float* dA, float* dB,
@@ -884,9 +891,15 @@ __global__ void __launch_bounds__(kBlock) nms_cn_backward_kernel(const QCDesc D,
             }
         }
     }
-    const float* wp = P.nms_w + ((size_t)(P.iter - 1) * D.J + R.j) * 2;
-    const float w = wp[0], b = wp[1];
-    float dw = 0.0f, db = 0.0f;
+    const float* wp = P.nms_w + ((size_t)(P.iter - 1) * D.nb + R.b0) * 2;
+    float w[DCMAX], b[DCMAX], dw[DCMAX], db[DCMAX];
+#pragma unroll
+    for (int k = 0; k < DCMAX; ++k) {
+        w[k] = R.valid(D, k) ? wp[2 * k] : 0.0f;
+        b[k] = R.valid(D, k) ? wp[2 * k + 1] : 0.0f;
+        dw[k] = 0.0f;
+        db[k] = 0.0f;
+    }
     float out[DCMAX][FPL];
 #pragma unroll
     for (int f = 0; f < FPL; ++f) {
@@ -905,11 +918,11 @@ __global__ void __launch_bounds__(kBlock) nms_cn_backward_kernel(const QCDesc D,
             if (!R.valid(D, k)) continue;
             const float m = (k == mi.idx1) ? mi.min2 : mi.min1;
             const float sg = (mi.parity ^ neg[k]) ? -1.0f : 1.0f;
-            const float a = m - b;
+            const float a = m - b[k];
             const float act = a >= 0.0f ? 1.0f : 0.0f;
-            dw += da[k][f] * sg * fmaxf(a, 0.0f);
-            db -= da[k][f] * w * sg * act;
-            const float gk = da[k][f] * w * sg * act;
+            dw[k] += da[k][f] * sg * fmaxf(a, 0.0f);
+            db[k] -= da[k][f] * w[k] * sg * act;
+            const float gk = da[k][f] * w[k] * sg * act;
             if (k == mi.idx1) G2 = gk;
             else G1 += gk;
         }
@@ -926,23 +939,31 @@ __global__ void __launch_bounds__(kBlock) nms_cn_backward_kernel(const QCDesc D,
         for (int k = 0; k < DCMAX; ++k)
             if (R.valid(D, k)) store_frames<FPL>(dB + base + (size_t)R.pkg(D, k) * Gt, out[k]);
     }
-    dw = wave_sum(dw);
-    db = wave_sum(db);
-    if (lane == 0) partial[wave] = make_float2(dw, db);
+    // one (dw, db) pair per edge slot of the row: slot k feeds block b0 + k
+#pragma unroll
+    for (int k = 0; k < DCMAX; ++k) {
+        if (!R.valid(D, k)) continue;
+        const float sw = wave_sum(dw[k]);
+        const float sb = wave_sum(db[k]);
+        if (lane == 0) partial[(size_t)wave * D.dc_max + k] = make_float2(sw, sb);
+    }
 }
 
-// grad[t][j] = sum of the check-node backward partials of iteration t + 1
-// over the rows of base row j, in a fixed order; grid (J, T), partial
-// [T][tiles * m].
+// grad[t][b] = sum of the check-node backward partials of iteration t + 1
+// over the rows of block b's base row j, slot b - rstart[j], in a fixed
+// order; grid (nb, T), partial [T][tiles * m][dc_max].
 __global__ void __launch_bounds__(256) nms_grad_reduce_kernel(const QCDesc D, const float2* partial, int tiles,
                                                               float* grad) {
     __shared__ float sw[256], sb[256];
-    const int j = blockIdx.x, t = blockIdx.y;
-    const float2* pt = partial + (size_t)t * tiles * D.m;
+    const int blk = blockIdx.x, t = blockIdx.y;
+    int j = 0;
+    while (j + 1 < D.J && D.rstart[j + 1] <= blk) ++j;
+    const int k = blk - D.rstart[j];
+    const float2* pt = partial + (size_t)t * tiles * D.m * D.dc_max;
     float aw = 0.0f, ab = 0.0f;
     for (int i = threadIdx.x; i < tiles * D.p; i += 256) {
         const int tile = i / D.p, s = i - tile * D.p;
-        const float2 v = pt[(size_t)tile * D.m + (size_t)j * D.p + s];
+        const float2 v = pt[((size_t)tile * D.m + (size_t)j * D.p + s) * D.dc_max + k];
         aw += v.x;
         ab += v.y;
     }
@@ -957,8 +978,8 @@ __global__ void __launch_bounds__(256) nms_grad_reduce_kernel(const QCDesc D, co
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        grad[((size_t)t * D.J + j) * 2 + 0] = sw[0];
-        grad[((size_t)t * D.J + j) * 2 + 1] = sb[0];
+        grad[((size_t)t * D.nb + blk) * 2 + 0] = sw[0];
+        grad[((size_t)t * D.nb + blk) * 2 + 1] = sb[0];
     }
 }
 
@@ -1965,7 +1986,7 @@ static void run_block(const ldpc_graph* g, const float* llr, int gamma, int max_
 // backward pass starts without recomputing), buffers for recomputing one
 // other segment (k alphas, k - 1 betas), the gradient buffers, and the
 // per-wave partial sums of the loss ([T][tiles n]) and of the gradient
-// ([T][tiles m] pairs).
+// ([T][tiles m][dc_max] pairs: one per edge slot of a row).
 struct TrainLayout {
     int k, nseg, nck, last;
     size_t arr, mu, ckpt, A, B, Al, Bl, dA, dB, lpart, gpart, total;
@@ -1989,7 +2010,7 @@ static TrainLayout train_layout(const ldpc_graph* g, const Tiling& t, int T, int
     L.dA = take(L.arr);
     L.dB = take(L.arr);
     L.lpart = take((size_t)T * t.tiles * g->n * sizeof(float));
-    L.gpart = take((size_t)T * t.tiles * g->m * sizeof(float2));
+    L.gpart = take((size_t)T * t.tiles * g->m * g->dc_max * sizeof(float2));
     L.total = off;
     return L;
 }
@@ -2117,7 +2138,7 @@ static void train_backward(TrainRun& r, const float* dloss, float* grad) {
                 timing::Scope ts(15, r.st);
                 const float* bsrc = t == c + 1 ? r.ckpt(c) : r.arr(Bbuf, t - c - 2);
                 float* dBout = t == 1 ? nullptr : dB;
-                float2* part = gpart + (size_t)(t - 1) * r.tl.tiles * D.m;
+                float2* part = gpart + (size_t)(t - 1) * r.tl.tiles * D.m * D.dc_max;
                 LDPC_DC_SWITCH(dcc, if constexpr (DC <= MaxDC<FPL>::value) {
                     nms_cn_backward_kernel<DC, FPL><<<cn_grid, kBlock, 0, r.st>>>(D, r.P, bsrc, dA, dBout, part);
                 });
@@ -2125,7 +2146,7 @@ static void train_backward(TrainRun& r, const float* dloss, float* grad) {
         }
     }
     timing::Scope ts(16, r.st);
-    nms_grad_reduce_kernel<<<dim3(D.J, r.T), 256, 0, r.st>>>(D, gpart, r.tl.tiles, grad);
+    nms_grad_reduce_kernel<<<dim3(D.nb, r.T), 256, 0, r.st>>>(D, gpart, r.tl.tiles, grad);
 }
 
 // host-side helpers for the convolutional schedules
@@ -2633,7 +2654,7 @@ const char* ldpc_kernel_class_name(int32_t cls) {
         "window_variable_node", "pipeline_ingest", "pipeline_check_node", "pipeline_variable_node",
         "train_check_node", "train_variable_node", "train_variable_node_backward", "train_check_node_backward",
         "train_reduce", "plan_ingest", "plan_check_node", "plan_variable_node", "plan_finish",
-        "window_lds"};
+        "window_lds", "plan_persistent"};
     if (cls < 0 || cls >= LDPC_TIMING_CLASSES) return "unknown";
     return names[cls];
 }

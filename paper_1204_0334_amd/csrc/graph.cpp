@@ -211,6 +211,11 @@ ldpc_status ldpc_graph_get_info(const ldpc_graph* g, ldpc_graph_info* info) {
         r.c = g->Lb * g->p; r.c_minus_b = g->Jb * g->p;
         r.positions = g->positions; r.layers = g->layers;
     }
+    if (g->kind == LDPC_GRAPH_QC) {
+        r.blocks = g->qc.nb;
+    } else {
+        for (int32_t v : g->sf) r.blocks += v >= 0 ? 1 : 0;
+    }
     r.design_rate = g->rate;
     *info = r;
     return LDPC_OK;

@@ -28,6 +28,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstddef>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -74,6 +76,79 @@ struct PlanCode {
     uint64_t* badw;       // early stopping: [tiles * cn_wpt][FPL] frames violating each check wave's rows
     int64_t red0;         // first block in the flag-reduction launch (red_chunks blocks per tile)
     int red_chunks;       // blocks per tile in the flag-reduction launch
+    char* region;         // start of the code's workspace region (mu .. badw lie inside it)
+};
+
+// Memory access policies of the plan bodies.  PlainMem: ordinary loads and
+// stores (the phase launches; a kernel boundary separates producer and
+// consumer).  CoherentMem: device-coherent buffer accesses (cache policy
+// sc1: stores write through the L2 of their XCD, loads do not hit stale
+// lines), addressed relative to the code's region, for the persistent launch
+// where one ticket's stores are read by tickets on other XCDs within the same
+// launch; the region of a code stays below 2^31 bytes there.
+struct PlainMem {
+    template <int FPL>
+    static __device__ __forceinline__ void ld(const PlanCode&, const float* p, float (&v)[FPL]) {
+        load_frames<FPL>(p, v);
+    }
+    template <int FPL>
+    static __device__ __forceinline__ void st(const PlanCode&, float* p, const float (&v)[FPL]) {
+        store_frames<FPL>(p, v);
+    }
+    static __device__ __forceinline__ uint64_t ld64(const PlanCode&, const uint64_t* p) { return *p; }
+    static __device__ __forceinline__ void st64(const PlanCode&, uint64_t* p, uint64_t v) { *p = v; }
+    static __device__ __forceinline__ float ldf(const PlanCode&, const float* p) { return *p; }
+    static __device__ __forceinline__ void stf(const PlanCode&, float* p, float v) { *p = v; }
+};
+
+struct CoherentMem {
+    static constexpr int kSc1 = 16;   // cache-policy operand: sc1
+    static __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const PlanCode& C) {
+        return __builtin_amdgcn_make_buffer_rsrc(C.region, 0, 0x7fffffff, 0x00020000);
+    }
+    static __device__ __forceinline__ int off(const PlanCode& C, const void* p) {
+        return (int)(reinterpret_cast<const char*>(p) - C.region);
+    }
+    template <int FPL>
+    static __device__ __forceinline__ void ld(const PlanCode& C, const float* p, float (&v)[FPL]) {
+        if constexpr (FPL == 4) {
+            const auto x = __builtin_amdgcn_raw_buffer_load_b128(rsrc(C), off(C, p), 0, kSc1);
+            v[0] = __uint_as_float(x[0]); v[1] = __uint_as_float(x[1]);
+            v[2] = __uint_as_float(x[2]); v[3] = __uint_as_float(x[3]);
+        } else if constexpr (FPL == 2) {
+            const auto x = __builtin_amdgcn_raw_buffer_load_b64(rsrc(C), off(C, p), 0, kSc1);
+            v[0] = __uint_as_float(x[0]); v[1] = __uint_as_float(x[1]);
+        } else {
+            v[0] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rsrc(C), off(C, p), 0, kSc1));
+        }
+    }
+    template <int FPL>
+    static __device__ __forceinline__ void st(const PlanCode& C, float* p, const float (&v)[FPL]) {
+        if constexpr (FPL == 4) {
+            __attribute__((ext_vector_type(4))) unsigned x = {__float_as_uint(v[0]), __float_as_uint(v[1]),
+                                                              __float_as_uint(v[2]), __float_as_uint(v[3])};
+            __builtin_amdgcn_raw_buffer_store_b128(x, rsrc(C), off(C, p), 0, kSc1);
+        } else if constexpr (FPL == 2) {
+            __attribute__((ext_vector_type(2))) unsigned x = {__float_as_uint(v[0]), __float_as_uint(v[1])};
+            __builtin_amdgcn_raw_buffer_store_b64(x, rsrc(C), off(C, p), 0, kSc1);
+        } else {
+            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v[0]), rsrc(C), off(C, p), 0, kSc1);
+        }
+    }
+    static __device__ __forceinline__ uint64_t ld64(const PlanCode& C, const uint64_t* p) {
+        const auto x = __builtin_amdgcn_raw_buffer_load_b64(rsrc(C), off(C, p), 0, kSc1);
+        return (uint64_t)x[0] | ((uint64_t)x[1] << 32);
+    }
+    static __device__ __forceinline__ void st64(const PlanCode& C, uint64_t* p, uint64_t v) {
+        __attribute__((ext_vector_type(2))) unsigned x = {(unsigned)v, (unsigned)(v >> 32)};
+        __builtin_amdgcn_raw_buffer_store_b64(x, rsrc(C), off(C, p), 0, kSc1);
+    }
+    static __device__ __forceinline__ float ldf(const PlanCode& C, const float* p) {
+        return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rsrc(C), off(C, p), 0, kSc1));
+    }
+    static __device__ __forceinline__ void stf(const PlanCode& C, float* p, float v) {
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), rsrc(C), off(C, p), 0, kSc1);
+    }
 };
 
 struct PlanStep {
@@ -169,7 +244,7 @@ __device__ __forceinline__ uint64_t plan_pick(const uint64_t (&a)[FPL], int i) {
 // skips tiles frozen by iteration iter-2 and ORs the syndrome of iteration
 // iter-1's decisions into unsat[iter-1]; the decision words are loaded right
 // after the messages and the flag update comes after the stores.
-template <int DCMAX, int G, int FPL, int V>
+template <int DCMAX, int G, int FPL, int V, class M>
 __device__ __forceinline__ void plan_cn_body(const PlanCode& C, const PlanStep& S, int64_t lw, int lane) {
     constexpr int R = 64 / G;
     constexpr int Gt = G * FPL;
@@ -182,7 +257,7 @@ __device__ __forceinline__ void plan_cn_body(const PlanCode& C, const PlanStep& 
         const uint64_t* fz = C.frozen + ((size_t)(S.iter - 2) * C.tiles + tile) * FPL;
         bool all = true;
 #pragma unroll
-        for (int i = 0; i < FPL; ++i) all = all && (fz[i] == ~0ull);
+        for (int i = 0; i < FPL; ++i) all = all && (M::ld64(C, fz + i) == ~0ull);
         if (all) return;
     }
     const size_t lane_off = (G == 64) ? (size_t)lane * FPL : (size_t)f;
@@ -203,7 +278,7 @@ __device__ __forceinline__ void plan_cn_body(const PlanCode& C, const PlanStep& 
         for (int k = 0; k < DCMAX; ++k) {
             if (k < d[v]) {
                 const float* s = S.iter == 1 ? ut + (size_t)Rw.var(D, k) * Gt : mt + (size_t)Rw.pkg(D, k) * Gt;
-                load_frames<FPL>(s, in[v][k]);
+                M::template ld<FPL>(C, s, in[v][k]);
             } else {
 #pragma unroll
                 for (int i = 0; i < FPL; ++i) in[v][k][i] = 0.0f;
@@ -221,7 +296,7 @@ __device__ __forceinline__ void plan_cn_body(const PlanCode& C, const PlanStep& 
             // lane k*FPL + f: word f of variable k; lane f ends with parity word f
             const int kk = lane / FPL, ff = lane - kk * FPL;
             const PlanRow Rw(D, j, d[0] ? srow[0] : 0, d[0] > 0);
-            if (kk < d[0]) par = bt[(size_t)Rw.var(D, kk) * FPL + ff];
+            if (kk < d[0]) par = M::ld64(C, bt + (size_t)Rw.var(D, kk) * FPL + ff);
 #pragma unroll
             for (int off = 32; off >= FPL; off >>= 1) par ^= __shfl_xor(par, off);
         } else {
@@ -234,7 +309,7 @@ __device__ __forceinline__ void plan_cn_body(const PlanCode& C, const PlanStep& 
 #pragma unroll
                 for (int q = 0; q < (DCMAX + G - 1) / G; ++q) {
                     const int k = q * G + f;
-                    if (k < d[v]) x ^= bt[Rw.var(D, k)];
+                    if (k < d[v]) x ^= M::ld64(C, bt + Rw.var(D, k));
                 }
 #pragma unroll
                 for (int off = G / 2; off >= 1; off >>= 1) x ^= __shfl_xor(x, off);
@@ -251,11 +326,11 @@ __device__ __forceinline__ void plan_cn_body(const PlanCode& C, const PlanStep& 
         sp_check<DCMAX, FPL>(in[v], d[v], out);
 #pragma unroll
         for (int k = 0; k < DCMAX; ++k)
-            if (k < d[v]) store_frames<FPL>(mt + (size_t)Rw.pkg(D, k) * Gt, out[k]);
+            if (k < d[v]) M::template st<FPL>(C, mt + (size_t)Rw.pkg(D, k) * Gt, out[k]);
     }
     // the wave's violated frames go to its own words (plain stores; the flag
     // word of the tile is formed by plan_unsat_kernel)
-    if (syn && lane < FPL) C.badw[lw * FPL + lane] = par & valid_word<FPL>(nvalid, lane);
+    if (syn && lane < FPL) M::st64(C, C.badw + lw * FPL + lane, par & valid_word<FPL>(nvalid, lane));
 }
 
 // Variable-node pass of iteration S.iter for wave lw of code C: betas (not
@@ -263,7 +338,7 @@ __device__ __forceinline__ void plan_cn_body(const PlanCode& C, const PlanStep& 
 // iteration the packed decisions and the posterior of the frames still
 // running (frozen frames keep theirs).  A wave handles V groups of R
 // variables; all their loads are issued before the first result is stored.
-template <int DVMAX, int G, int FPL, int V>
+template <int DVMAX, int G, int FPL, int V, class M>
 __device__ __forceinline__ void plan_vn_body(const PlanCode& C, const PlanStep& S, int64_t lw, int lane) {
     constexpr int R = 64 / G;
     constexpr int Gt = G * FPL;
@@ -279,15 +354,15 @@ __device__ __forceinline__ void plan_vn_body(const PlanCode& C, const PlanStep& 
     for (int i = 0; i < FPL; ++i) {
         uint64_t z = ~valid_word<FPL>(nvalid, i);
         if (S.early && S.iter >= 2) {
-            z |= C.frozen[((size_t)(S.iter - 2) * C.tiles + tile) * FPL + i] |
-                 ~C.unsat[((size_t)(S.iter - 1) * C.tiles + tile) * FPL + i];
+            z |= M::ld64(C, C.frozen + ((size_t)(S.iter - 2) * C.tiles + tile) * FPL + i) |
+                 ~M::ld64(C, C.unsat + ((size_t)(S.iter - 1) * C.tiles + tile) * FPL + i);
         }
         frz[i] = z;
         any = any || (z & valid_word<FPL>(nvalid, i)) != 0;
         all = all && (z == ~0ull);
     }
     if (S.early && rw == 0 && lane < FPL)
-        C.frozen[((size_t)(S.iter - 1) * C.tiles + tile) * FPL + lane] = plan_pick<FPL>(frz, lane);
+        M::st64(C, C.frozen + ((size_t)(S.iter - 1) * C.tiles + tile) * FPL + lane, plan_pick<FPL>(frz, lane));
     if (S.early && all) return;
     const size_t lane_off = (G == 64) ? (size_t)lane * FPL : (size_t)f;
     float* mt = C.msg + (size_t)tile * D.E * Gt + lane_off;
@@ -305,7 +380,7 @@ __device__ __forceinline__ void plan_vn_body(const PlanCode& C, const PlanStep& 
         const PlanCol Cc(D, l, active[v] ? tcol[v] : 0, active[v]);
         dv[v] = Cc.d;
         if (active[v]) {
-            load_frames<FPL>(C.mu + ((size_t)tile * D.n + var[v]) * Gt + lane_off, mu[v]);
+            M::template ld<FPL>(C, C.mu + ((size_t)tile * D.n + var[v]) * Gt + lane_off, mu[v]);
         } else {
 #pragma unroll
             for (int i = 0; i < FPL; ++i) mu[v][i] = 0.0f;
@@ -313,7 +388,7 @@ __device__ __forceinline__ void plan_vn_body(const PlanCode& C, const PlanStep& 
 #pragma unroll
         for (int k = 0; k < DVMAX; ++k) {
             if (k < dv[v]) {
-                load_frames<FPL>(mt + (size_t)Cc.pkg(D, k) * Gt, a[v][k]);
+                M::template ld<FPL>(C, mt + (size_t)Cc.pkg(D, k) * Gt, a[v][k]);
             } else {
 #pragma unroll
                 for (int i = 0; i < FPL; ++i) a[v][k][i] = 0.0f;
@@ -328,7 +403,7 @@ __device__ __forceinline__ void plan_vn_body(const PlanCode& C, const PlanStep& 
         if (!S.last) {
 #pragma unroll
             for (int k = 0; k < DVMAX; ++k)
-                if (k < dv[v]) store_frames<FPL>(mt + (size_t)Cc.pkg(D, k) * Gt, b[k]);
+                if (k < dv[v]) M::template st<FPL>(C, mt + (size_t)Cc.pkg(D, k) * Gt, b[k]);
         }
         if (S.early || S.last) {
             uint64_t* bw = C.bits + ((size_t)tile * D.n + (active[v] ? var[v] : 0)) * FPL;
@@ -338,17 +413,17 @@ __device__ __forceinline__ void plan_vn_body(const PlanCode& C, const PlanStep& 
 #pragma unroll
                 for (int i = 0; i < FPL; ++i) {
                     uint64_t w = __ballot(L[i] < 0.0f);
-                    if (any) w = (w & ~frz[i]) | (bw[i] & frz[i]);
+                    if (any) w = (w & ~frz[i]) | (M::ld64(C, bw + i) & frz[i]);
                     if (lane == i) mine = w;
                 }
-                if (active[v] && lane < FPL) bw[lane] = mine;
+                if (active[v] && lane < FPL) M::st64(C, bw + lane, mine);
             } else {
                 // bits r*G .. r*G+G-1 of the ballot are the G frames of variable r
                 const uint64_t gmask = (1ull << G) - 1ull;
                 uint64_t w = (__ballot(active[v] && L[0] < 0.0f) >> (r * G)) & gmask;
                 if (active[v] && f == 0) {
-                    if (any) w = (w & ~frz[0]) | (bw[0] & frz[0]);
-                    bw[0] = w;
+                    if (any) w = (w & ~frz[0]) | (M::ld64(C, bw) & frz[0]);
+                    M::st64(C, bw, w);
                 }
             }
             if (active[v]) {
@@ -356,10 +431,46 @@ __device__ __forceinline__ void plan_vn_body(const PlanCode& C, const PlanStep& 
 #pragma unroll
                 for (int i = 0; i < FPL; ++i) {
                     const int bit = (G == 64) ? lane : f;   // frame lane_off + i: word i, bit `bit`
-                    if (!((frz[i] >> bit) & 1ull)) pw[i] = clip30(L[i]);
+                    if (!((frz[i] >> bit) & 1ull)) M::stf(C, pw + i, clip30(L[i]));
                 }
             }
         }
+    }
+}
+
+// One wave of the check-node pass (every layout and row-weight class).
+template <class M>
+__device__ __forceinline__ void plan_cn_wave(const PlanCode& C, const PlanStep& S, int64_t lw, int lane) {
+    if (C.cpw == 1) {
+        PLAN_LAYOUT_SWITCH(C.layout, PLAN_DC_SWITCH(C.dcc, if constexpr (FPL == 1 || DC <= (FPL == 4 ? 6 : 12)) {
+            plan_cn_body<DC, G, FPL, 1, M>(C, S, lw, lane);
+        }));
+    } else if (C.cpw == 2) {
+        PLAN_LAYOUT_SWITCH(C.layout, PLAN_DC_SWITCH(C.dcc, if constexpr (FPL == 1 && DC <= 8) {
+            plan_cn_body<DC, G, FPL, 2, M>(C, S, lw, lane);
+        }));
+    } else {
+        PLAN_LAYOUT_SWITCH(C.layout, PLAN_DC_SWITCH(C.dcc, if constexpr (FPL == 1 && DC <= 6) {
+            plan_cn_body<DC, G, FPL, 4, M>(C, S, lw, lane);
+        }));
+    }
+}
+
+// One wave of the variable-node pass.
+template <class M>
+__device__ __forceinline__ void plan_vn_wave(const PlanCode& C, const PlanStep& S, int64_t lw, int lane) {
+    if (C.vpw == 1) {
+        PLAN_LAYOUT_SWITCH(C.layout, PLAN_DV_SWITCH(C.dvc, if constexpr (FPL == 1 || DV <= 8) {
+            plan_vn_body<DV, G, FPL, 1, M>(C, S, lw, lane);
+        }));
+    } else if (C.vpw == 2) {
+        PLAN_LAYOUT_SWITCH(C.layout, PLAN_DV_SWITCH(C.dvc, if constexpr (FPL == 1 && DV <= 8) {
+            plan_vn_body<DV, G, FPL, 2, M>(C, S, lw, lane);
+        }));
+    } else {
+        PLAN_LAYOUT_SWITCH(C.layout, PLAN_DV_SWITCH(C.dvc, if constexpr (FPL == 1 && DV <= 8) {
+            plan_vn_body<DV, G, FPL, 4, M>(C, S, lw, lane);
+        }));
     }
 }
 
@@ -370,19 +481,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))
     const PlanCode& C = codes[plan_find(codes, ncodes, wave, &PlanCode::cn0)];
     const int64_t lw = wave - C.cn0;
     if (lw >= (int64_t)C.tiles * C.cn_wpt) return;
-    if (C.cpw == 1) {
-        PLAN_LAYOUT_SWITCH(C.layout, PLAN_DC_SWITCH(C.dcc, if constexpr (FPL == 1 || DC <= (FPL == 4 ? 6 : 12)) {
-            plan_cn_body<DC, G, FPL, 1>(C, S, lw, lane);
-        }));
-    } else if (C.cpw == 2) {
-        PLAN_LAYOUT_SWITCH(C.layout, PLAN_DC_SWITCH(C.dcc, if constexpr (FPL == 1 && DC <= 8) {
-            plan_cn_body<DC, G, FPL, 2>(C, S, lw, lane);
-        }));
-    } else {
-        PLAN_LAYOUT_SWITCH(C.layout, PLAN_DC_SWITCH(C.dcc, if constexpr (FPL == 1 && DC <= 6) {
-            plan_cn_body<DC, G, FPL, 4>(C, S, lw, lane);
-        }));
-    }
+    plan_cn_wave<PlainMem>(C, S, lw, lane);
 }
 
 // 8 waves per SIMD (64 VGPRs; a few values the wave keeps for its whole life
@@ -395,19 +494,7 @@ plan_vn_kernel(const PlanCode* __restrict__ codes, int ncodes, PlanStep S) {
     const PlanCode& C = codes[plan_find(codes, ncodes, wave, &PlanCode::vn0)];
     const int64_t lw = wave - C.vn0;
     if (lw >= (int64_t)C.tiles * C.vn_wpt) return;
-    if (C.vpw == 1) {
-        PLAN_LAYOUT_SWITCH(C.layout, PLAN_DV_SWITCH(C.dvc, if constexpr (FPL == 1 || DV <= 8) {
-            plan_vn_body<DV, G, FPL, 1>(C, S, lw, lane);
-        }));
-    } else if (C.vpw == 2) {
-        PLAN_LAYOUT_SWITCH(C.layout, PLAN_DV_SWITCH(C.dvc, if constexpr (FPL == 1 && DV <= 8) {
-            plan_vn_body<DV, G, FPL, 2>(C, S, lw, lane);
-        }));
-    } else {
-        PLAN_LAYOUT_SWITCH(C.layout, PLAN_DV_SWITCH(C.dvc, if constexpr (FPL == 1 && DV <= 8) {
-            plan_vn_body<DV, G, FPL, 4>(C, S, lw, lane);
-        }));
-    }
+    plan_vn_wave<PlainMem>(C, S, lw, lane);
 }
 
 // unsat[iter-1][tile] |= OR of the tile's check-wave words.  Block (code,
@@ -420,11 +507,11 @@ plan_vn_kernel(const PlanCode* __restrict__ codes, int ncodes, PlanStep S) {
 constexpr int kPlanRedPerThread = 8;
 constexpr int kPlanRedWords = 256 * kPlanRedPerThread;
 
-__global__ void __launch_bounds__(256) plan_unsat_kernel(const PlanCode* __restrict__ codes, int ncodes,
-                                                         PlanStep S) {
-    __shared__ uint64_t part[4][4];
-    const PlanCode& C = codes[plan_find(codes, ncodes, blockIdx.x, &PlanCode::red0)];
-    const int64_t b = blockIdx.x - C.red0;
+// Block b of code C's flag reduction (256 threads; every early return is
+// uniform over the block).
+template <class M>
+__device__ __forceinline__ void plan_unsat_block(const PlanCode& C, const PlanStep& S, int64_t b,
+                                                 uint64_t (&part)[4][4]) {
     const int tile = (int)(b / C.red_chunks);
     const int chunk = (int)(b - (int64_t)tile * C.red_chunks);
     if (tile >= C.tiles) return;
@@ -432,7 +519,7 @@ __global__ void __launch_bounds__(256) plan_unsat_kernel(const PlanCode* __restr
     if (S.iter >= 3) {
         const uint64_t* fz = C.frozen + ((size_t)(S.iter - 2) * C.tiles + tile) * fpl;
         bool all = true;
-        for (int i = 0; i < fpl; ++i) all = all && (fz[i] == ~0ull);
+        for (int i = 0; i < fpl; ++i) all = all && (M::ld64(C, fz + i) == ~0ull);
         if (all) return;
     }
     const int64_t nw = (int64_t)C.cn_wpt * fpl;
@@ -442,7 +529,7 @@ __global__ void __launch_bounds__(256) plan_unsat_kernel(const PlanCode* __restr
 #pragma unroll
     for (int k = 0; k < kPlanRedPerThread; ++k) {
         const int64_t w = w0 + (int64_t)k * 256;
-        if (w < nw) acc |= bw[w];
+        if (w < nw) acc |= M::ld64(C, bw + w);
     }
     for (int off = 32; off >= fpl; off >>= 1) acc |= __shfl_xor(acc, off);
     const int lane = threadIdx.x & 63;
@@ -456,10 +543,17 @@ __global__ void __launch_bounds__(256) plan_unsat_kernel(const PlanCode* __restr
     }
 }
 
+__global__ void __launch_bounds__(256) plan_unsat_kernel(const PlanCode* __restrict__ codes, int ncodes,
+                                                         PlanStep S) {
+    __shared__ uint64_t part[4][4];
+    const PlanCode& C = codes[plan_find(codes, ncodes, blockIdx.x, &PlanCode::red0)];
+    plan_unsat_block<PlainMem>(C, S, blockIdx.x - C.red0, part);
+}
+
 // Syndrome of the final decisions into unsat[max_iters]: one thread per
 // (code, tile, row); each code's threads start at a multiple of 64, so a
 // wave belongs to one code; its rows may straddle two tiles.
-template <int FPL>
+template <int FPL, class M>
 __device__ __forceinline__ void plan_syndrome_body(const PlanCode& C, const PlanStep& S, int64_t t, int lane) {
     const QCDesc& D = C.D;
     const int Gt = C.Gt;
@@ -475,7 +569,7 @@ __device__ __forceinline__ void plan_syndrome_body(const PlanCode& C, const Plan
         for (int k = 0; k < Rw.d; ++k) {
             const uint64_t* w = bt + (size_t)Rw.var(D, k) * FPL;
 #pragma unroll
-            for (int i = 0; i < FPL; ++i) par[i] ^= w[i];
+            for (int i = 0; i < FPL; ++i) par[i] ^= M::ld64(C, w + i);
         }
         const int nvalid = min(C.gamma - tile * Gt, Gt);
 #pragma unroll
@@ -499,56 +593,63 @@ __device__ __forceinline__ void plan_syndrome_body(const PlanCode& C, const Plan
     }
 }
 
+template <class M>
+__device__ __forceinline__ void plan_syndrome_thread(const PlanCode& C, const PlanStep& S, int64_t t, int lane) {
+    if (C.fpl == 4) {
+        plan_syndrome_body<4, M>(C, S, t, lane);
+    } else if (C.fpl == 2) {
+        plan_syndrome_body<2, M>(C, S, t, lane);
+    } else {
+        plan_syndrome_body<1, M>(C, S, t, lane);
+    }
+}
+
 __global__ void __launch_bounds__(kBlock) plan_syndrome_kernel(const PlanCode* __restrict__ codes, int ncodes,
                                                                PlanStep S) {
     const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const int64_t wave0 = (int64_t)blockIdx.x * kBlock + wave_in_block() * 64;
     const PlanCode& C = codes[plan_find(codes, ncodes, wave0, &PlanCode::syn0)];
-    const int64_t t = gid - C.syn0;
-    if (C.fpl == 4) {
-        plan_syndrome_body<4>(C, S, t, threadIdx.x & 63);
-    } else if (C.fpl == 2) {
-        plan_syndrome_body<2>(C, S, t, threadIdx.x & 63);
-    } else {
-        plan_syndrome_body<1>(C, S, t, threadIdx.x & 63);
-    }
+    plan_syndrome_thread<PlainMem>(C, S, gid - C.syn0, threadIdx.x & 63);
 }
 
-// Per-frame iteration count and convergence flag from the flag words.
-__global__ void __launch_bounds__(kBlock) plan_status_kernel(const PlanCode* __restrict__ codes, int ncodes,
-                                                             PlanStep S) {
-    const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const int64_t wave0 = (int64_t)blockIdx.x * kBlock + wave_in_block() * 64;
-    const PlanCode& C = codes[plan_find(codes, ncodes, wave0, &PlanCode::st0)];
-    const int64_t g = gid - C.st0;
+// Per-frame iteration count and convergence flag from the flag words (frame g
+// of code C).
+template <class M>
+__device__ __forceinline__ void plan_status_thread(const PlanCode& C, const PlanStep& S, int64_t g) {
     if (g >= C.gamma || (!C.iters && !C.converged)) return;
     const int tile = (int)(g / C.Gt), fl = (int)(g - (int64_t)tile * C.Gt);
     const int w = fl % C.fpl, bit = fl / C.fpl;
     int it = S.max_iters, ok = 0;
     if (S.early) {
         for (int i = 1; i <= S.max_iters; ++i) {
-            if (!((C.unsat[((size_t)i * C.tiles + tile) * C.fpl + w] >> bit) & 1ull)) {
+            if (!((M::ld64(C, C.unsat + ((size_t)i * C.tiles + tile) * C.fpl + w) >> bit) & 1ull)) {
                 it = i;
                 ok = 1;
                 break;
             }
         }
     } else {
-        ok = !((C.unsat[((size_t)S.max_iters * C.tiles + tile) * C.fpl + w] >> bit) & 1ull);
+        ok = !((M::ld64(C, C.unsat + ((size_t)S.max_iters * C.tiles + tile) * C.fpl + w) >> bit) & 1ull);
     }
     if (C.iters) C.iters[g] = it;
     if (C.converged) C.converged[g] = (uint8_t)ok;
 }
 
+__global__ void __launch_bounds__(kBlock) plan_status_kernel(const PlanCode* __restrict__ codes, int ncodes,
+                                                             PlanStep S) {
+    const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t wave0 = (int64_t)blockIdx.x * kBlock + wave_in_block() * 64;
+    const PlanCode& C = codes[plan_find(codes, ncodes, wave0, &PlanCode::st0)];
+    plan_status_thread<PlainMem>(C, S, gid - C.st0);
+}
+
 // Ingest: llr [gamma][n] -> mu [tile][n][Gt] (padding frames 0), through LDS,
 // 64 variables x 64 frames per block; block 0 of a code clears its flags.
-__global__ void __launch_bounds__(256) plan_ingest_kernel(const PlanCode* __restrict__ codes, int ncodes) {
-    __shared__ float tileS[64][65];
-    const PlanCode& C = codes[plan_find(codes, ncodes, blockIdx.x, &PlanCode::io0)];
-    const int64_t b = blockIdx.x - C.io0;
+template <class M>
+__device__ __forceinline__ void plan_ingest_block(const PlanCode& C, int64_t b, float (&tileS)[64][65]) {
     if (b >= (int64_t)C.io_vchunks * C.io_fchunks) return;
     if (b == 0)
-        for (int64_t i = threadIdx.x; i < 2 * C.flag_words; i += 256) C.unsat[i] = 0ull;
+        for (int64_t i = threadIdx.x; i < 2 * C.flag_words; i += 256) M::st64(C, C.unsat + i, 0ull);
     const int n = C.D.n, Gt = C.Gt, gpad = C.tiles * C.Gt;
     const int c0 = (int)(b % C.io_vchunks) * 64, f0 = (int)(b / C.io_vchunks) * 64;
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
@@ -563,18 +664,22 @@ __global__ void __launch_bounds__(256) plan_ingest_kernel(const PlanCode* __rest
         const int c = c0 + r, g = f0 + tx;
         if (c < n && g < gpad) {
             const int tile = g / Gt, fl = g - tile * Gt;
-            C.mu[((size_t)tile * n + c) * Gt + fl] = tileS[tx][r];
+            M::stf(C, C.mu + ((size_t)tile * n + c) * Gt + fl, tileS[tx][r]);
         }
     }
 }
 
+__global__ void __launch_bounds__(256) plan_ingest_kernel(const PlanCode* __restrict__ codes, int ncodes) {
+    __shared__ float tileS[64][65];
+    const PlanCode& C = codes[plan_find(codes, ncodes, blockIdx.x, &PlanCode::io0)];
+    plan_ingest_block<PlainMem>(C, blockIdx.x - C.io0, tileS);
+}
+
 // Output: posterior and decisions of every frame from the package layout to
 // the caller's [gamma][n] buffers, through LDS.
-__global__ void __launch_bounds__(256) plan_output_kernel(const PlanCode* __restrict__ codes, int ncodes) {
-    __shared__ float Ps[64][65];
-    __shared__ uint8_t Bs[64][65];
-    const PlanCode& C = codes[plan_find(codes, ncodes, blockIdx.x, &PlanCode::io0)];
-    const int64_t b = blockIdx.x - C.io0;
+template <class M>
+__device__ __forceinline__ void plan_output_block(const PlanCode& C, int64_t b, float (&Ps)[64][65],
+                                                  uint8_t (&Bs)[64][65]) {
     if (b >= (int64_t)C.io_vchunks * C.io_fchunks) return;
     const int n = C.D.n, Gt = C.Gt, fpl = C.fpl;
     const int c0 = (int)(b % C.io_vchunks) * 64, f0 = (int)(b / C.io_vchunks) * 64;
@@ -583,8 +688,8 @@ __global__ void __launch_bounds__(256) plan_output_kernel(const PlanCode* __rest
         const int c = c0 + r, g = f0 + tx;
         if (c < n && g < C.gamma) {
             const int tile = g / Gt, fl = g - tile * Gt;
-            Ps[r][tx] = C.postw[((size_t)tile * n + c) * Gt + fl];
-            const uint64_t w = C.bits[((size_t)tile * n + c) * fpl + fl % fpl];
+            Ps[r][tx] = M::ldf(C, C.postw + ((size_t)tile * n + c) * Gt + fl);
+            const uint64_t w = M::ld64(C, C.bits + ((size_t)tile * n + c) * fpl + fl % fpl);
             Bs[r][tx] = (uint8_t)((w >> (fl / fpl)) & 1ull);
         }
     }
@@ -595,6 +700,227 @@ __global__ void __launch_bounds__(256) plan_output_kernel(const PlanCode* __rest
             const size_t o = (size_t)g * n + c;
             C.post[o] = Ps[tx][r];
             C.bits_out[o] = Bs[tx][r];
+        }
+    }
+}
+
+__global__ void __launch_bounds__(256) plan_output_kernel(const PlanCode* __restrict__ codes, int ncodes) {
+    __shared__ float Ps[64][65];
+    __shared__ uint8_t Bs[64][65];
+    const PlanCode& C = codes[plan_find(codes, ncodes, blockIdx.x, &PlanCode::io0)];
+    plan_output_block<PlainMem>(C, blockIdx.x - C.io0, Ps, Bs);
+}
+
+// ---------------------------------------------------------------------------
+// Persistent decode: one launch runs a whole decode of the plan.
+//
+// The work is cut into tickets.  A ticket is a run of up to
+// items_per_ticket consecutive items of one step of one code; an item is 4
+// waves of a check- or variable-node pass, or one 256-thread block of the
+// other steps.  Tickets are numbered step-major: the ingest of every code,
+// then per iteration the check passes of every code, their flag reductions
+// (early stopping), their variable passes, and last the final syndrome, the
+// frame status and the output.  A workgroup takes the next number from a
+// counter.  Before working on a ticket it waits until its code's completion
+// counter has counted every ticket of that code's earlier steps, so codes
+// advance independently of each other.  A ticket only waits for tickets with
+// smaller numbers, and those have all been taken by workgroups already
+// running: the launch needs no co-residency and cannot deadlock.
+//
+// Ordering: everything one ticket hands to another goes through
+// device-coherent accesses (CoherentMem: stores write through the L2 of
+// their XCD, loads never hit a stale line), so no cache is written back or
+// invalidated.  Each wave waits until its stores have completed, then the
+// workgroup barrier, then one thread counts the ticket done (an atomic).  The
+// waiting thread polls the counter before the barrier that releases its
+// workgroup's waves.  (Agent-scope fences instead write back the whole L2 of
+// the XCD at every ticket: measured 7-15x slower.)
+//
+// Each wait is bounded in time.  On expiry the workgroup sets the error word
+// and stops; the others stop at their next wait or ticket.  The last
+// workgroup to leave resets the counters for the next launch and folds the
+// error into the word the host reads (ldpc_plan_check).
+// ---------------------------------------------------------------------------
+enum PersistKind { kKindIngest = 0, kKindCN, kKindUnsat, kKindVN, kKindSyn, kKindStatus, kKindOut, kKinds };
+
+// Each counter has a 128-byte line of its own: every workgroup takes tickets
+// from `next`, and the workgroups waiting on one code poll its `done` line.
+struct alignas(128) PersistCounter {
+    uint32_t v;
+    uint32_t pad[31];
+};
+struct PersistState {
+    PersistCounter next;                          // next ticket number
+    PersistCounter exited;                        // workgroups that have left
+    PersistCounter err;                           // a wait expired during this launch
+    PersistCounter err_sticky;                    // OR of err over launches; read and cleared by the host
+    PersistCounter done[LDPC_PLAN_MAX_CODES];     // completed tickets per code (cumulative over the launch)
+};
+
+struct PersistArgs {
+    int ncodes, max_iters, early, items_per_ticket;
+    uint32_t total;                       // tickets of one decode
+    uint32_t T0, Titer;                   // tickets of the ingest block, of one iteration block
+    uint64_t wait_ticks;                  // bound of one wait, wall-clock ticks
+    int32_t tk[kKinds][LDPC_PLAN_MAX_CODES];      // tickets per step kind and code
+    int32_t items[kKinds][LDPC_PLAN_MAX_CODES];   // items per step kind and code
+};
+
+// kind, code, iteration and ticket index within the (kind, code) step of
+// ticket t (t < A.total; wave-uniform)
+__device__ __forceinline__ void persist_decode(const PersistArgs& A, uint32_t t, int& kind, int& code, int& iter,
+                                               uint32_t& idx) {
+    iter = 0;
+    if (t < A.T0) {
+        kind = kKindIngest;
+    } else {
+        t -= A.T0;
+        const uint32_t body = (uint32_t)A.max_iters * A.Titer;
+        if (t < body) {
+            iter = (int)(t / A.Titer) + 1;
+            t -= (uint32_t)(iter - 1) * A.Titer;
+            kind = kKindCN;
+        } else {
+            t -= body;
+            iter = A.max_iters;
+            kind = kKindSyn;
+        }
+    }
+    const int last_kind = kind == kKindIngest ? kKindIngest : kind == kKindCN ? kKindVN : kKindOut;
+    for (;; ++kind) {
+        for (int c = 0; c < A.ncodes; ++c) {
+            const uint32_t k = (uint32_t)A.tk[kind][c];
+            if (t < k) {
+                code = c;
+                idx = t;
+                return;
+            }
+            t -= k;
+        }
+        if (kind == last_kind) break;
+    }
+    code = 0;   // not reached for t < A.total
+    idx = 0;
+}
+
+// tickets of code c in the steps before (kind, iter)
+__device__ __forceinline__ uint32_t persist_before(const PersistArgs& A, int kind, int c, int iter) {
+    const uint32_t per_it = (uint32_t)(A.tk[kKindCN][c] + A.tk[kKindUnsat][c] + A.tk[kKindVN][c]);
+    const uint32_t ing = (uint32_t)A.tk[kKindIngest][c];
+    switch (kind) {
+        case kKindIngest: return 0;
+        case kKindCN: return ing + (uint32_t)(iter - 1) * per_it;
+        case kKindUnsat: return ing + (uint32_t)(iter - 1) * per_it + A.tk[kKindCN][c];
+        case kKindVN: return ing + (uint32_t)(iter - 1) * per_it + A.tk[kKindCN][c] + A.tk[kKindUnsat][c];
+        case kKindSyn: return ing + (uint32_t)A.max_iters * per_it;
+        case kKindStatus: return ing + (uint32_t)A.max_iters * per_it + A.tk[kKindSyn][c];
+        default: return ing + (uint32_t)A.max_iters * per_it + A.tk[kKindSyn][c] + A.tk[kKindStatus][c];
+    }
+}
+
+// one thread waits until code c has completed `need` tickets; 0 if the wait
+// expired or another workgroup reported an expired wait
+__device__ __forceinline__ int persist_wait(PersistState* st, int c, uint32_t need, uint64_t limit) {
+    if (__hip_atomic_load(&st->done[c].v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+        const uint64_t t0 = wall_clock64();
+        int nap = 1;   // polls back off exponentially (s_sleep units of 64 clocks)
+        for (;;) {
+            for (int i = 0; i < nap; ++i) __builtin_amdgcn_s_sleep(1);
+            if (nap < 64) nap *= 2;
+            if (__hip_atomic_load(&st->done[c].v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= need) break;
+            if (__hip_atomic_load(&st->err.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return 0;
+            if (wall_clock64() - t0 > limit) {
+                __hip_atomic_fetch_or(&st->err.v, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                return 0;
+            }
+        }
+    }
+    return 1;
+}
+
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4)))
+plan_persistent_kernel(const PlanCode* __restrict__ codes, PersistState* st, PersistArgs A) {
+    __shared__ float lf[64][65];
+    __shared__ uint8_t lb[64][65];
+    __shared__ uint64_t part[4][4];
+    __shared__ uint32_t sh_next;
+    __shared__ int sh_go;
+    const int lane = threadIdx.x & 63;
+    const int wv = wave_in_block();
+    if (threadIdx.x == 0) sh_next = __hip_atomic_fetch_add(&st->next.v, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    uint32_t t = sh_next;
+    __syncthreads();
+    while (t < A.total) {
+        int kind, c, iter;
+        uint32_t idx;
+        persist_decode(A, t, kind, c, iter, idx);
+        if (threadIdx.x == 0) {
+            // take the following ticket now (it is processed after this one)
+            sh_next = __hip_atomic_fetch_add(&st->next.v, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const uint32_t need = persist_before(A, kind, c, iter);
+            sh_go = need ? persist_wait(st, c, need, A.wait_ticks) : 1;
+        }
+        __syncthreads();
+        const uint32_t t_next = sh_next;
+        if (!sh_go) break;
+        const PlanCode& C = codes[c];
+        PlanStep S{iter, iter == A.max_iters, A.early, A.max_iters};
+        const int64_t i0 = (int64_t)idx * A.items_per_ticket;
+        const int64_t i1 = min(i0 + A.items_per_ticket, (int64_t)A.items[kind][c]);
+        for (int64_t it = i0; it < i1; ++it) {
+            switch (kind) {
+                case kKindIngest:
+                    plan_ingest_block<CoherentMem>(C, it, lf);
+                    __syncthreads();
+                    break;
+                case kKindCN: {
+                    const int64_t lw = it * kWavesPerBlock + wv;
+                    if (lw < (int64_t)C.tiles * C.cn_wpt) plan_cn_wave<CoherentMem>(C, S, lw, lane);
+                    break;
+                }
+                case kKindUnsat:
+                    if (A.early && iter >= 2) {
+                        plan_unsat_block<CoherentMem>(C, S, it, part);
+                        __syncthreads();
+                    }
+                    break;
+                case kKindVN: {
+                    const int64_t lw = it * kWavesPerBlock + wv;
+                    if (lw < (int64_t)C.tiles * C.vn_wpt) plan_vn_wave<CoherentMem>(C, S, lw, lane);
+                    break;
+                }
+                case kKindSyn:
+                    plan_syndrome_thread<CoherentMem>(C, S, it * kBlock + threadIdx.x, lane);
+                    break;
+                case kKindStatus:
+                    plan_status_thread<CoherentMem>(C, S, it * kBlock + threadIdx.x);
+                    break;
+                default:
+                    plan_output_block<CoherentMem>(C, it, lf, lb);
+                    __syncthreads();
+                    break;
+            }
+        }
+        // this wave's stores (write-through) have completed: wait for its
+        // vector memory counter (it counts stores on this architecture)
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __syncthreads();
+        if (threadIdx.x == 0) __hip_atomic_fetch_add(&st->done[c].v, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        t = t_next;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t left = __hip_atomic_fetch_add(&st->exited.v, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (left == gridDim.x - 1) {
+            // every other workgroup has left: reset the counters for the next launch
+            const uint32_t e = __hip_atomic_load(&st->err.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (e) __hip_atomic_fetch_or(&st->err_sticky.v, e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&st->err.v, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&st->next.v, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            for (int i = 0; i < LDPC_PLAN_MAX_CODES; ++i)
+                __hip_atomic_store(&st->done[i].v, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&st->exited.v, 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
 }
@@ -693,6 +1019,13 @@ struct ldpc_plan {
     bool table_valid = false;
     const void* table_ws = nullptr;
     uint64_t generation = 1;              // bumped whenever layouts or bound buffers change
+    // persistent launch (ldpc_plan_set_persistent)
+    int persistent = 0;
+    int64_t wait_us = 2000000;
+    uint64_t wait_ticks = 0;              // wait_us in device wall-clock ticks
+    int persist_grid = 0;                 // workgroups: what fits the device at once
+    size_t state_off = 0;                 // PersistState in the workspace
+    PersistArgs pa{};
     // graph
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
@@ -722,6 +1055,14 @@ ldpc_status check_buffers(const ldpc_plan* P, const PlanBuffers& B, const void* 
     return LDPC_OK;
 }
 
+// items per ticket of the persistent launch; LDPC_PLAN_TICKET_ITEMS (1..64)
+// overrides the default
+int persist_items_per_ticket() {
+    const char* env = std::getenv("LDPC_PLAN_TICKET_ITEMS");
+    const int v = env ? std::atoi(env) : 0;
+    return v >= 1 && v <= 64 ? v : 2;
+}
+
 // fill the host table for the current layouts and buffers
 void build_table(ldpc_plan* P, const PlanBuffers& B, char* ws) {
     P->table.assign(P->ncodes, PlanCode{});
@@ -740,6 +1081,7 @@ void build_table(ldpc_plan* P, const PlanBuffers& B, char* ws) {
         T.unsat = reinterpret_cast<uint64_t*>(base + R.flags);
         T.badw = reinterpret_cast<uint64_t*>(base + R.badw);
         T.frozen = T.unsat + R.flag_words;
+        T.region = base;
         T.llr = B.llr[c];
         T.post = B.post[c];
         T.bits_out = B.bits[c];
@@ -775,6 +1117,40 @@ void build_table(ldpc_plan* P, const PlanBuffers& B, char* ws) {
         io += (int64_t)T.io_vchunks * T.io_fchunks;
         red += (int64_t)T.tiles * T.red_chunks;
     }
+    // persistent launch: items and tickets per step kind and code
+    PersistArgs& A = P->pa;
+    A = PersistArgs{};
+    A.ncodes = P->ncodes;
+    A.max_iters = P->max_iters;
+    A.early = P->early;
+    A.items_per_ticket = persist_items_per_ticket();
+    uint64_t T0 = 0, Titer = 0, Ttail = 0;
+    for (int c = 0; c < P->ncodes; ++c) {
+        const PlanCode& T = P->table[c];
+        const ldpc_graph* g = P->graphs[c];
+        const int64_t io = (int64_t)T.io_vchunks * T.io_fchunks;
+        const int64_t items[kKinds] = {io,
+                                       ((int64_t)T.tiles * T.cn_wpt + kWavesPerBlock - 1) / kWavesPerBlock,
+                                       P->early ? (int64_t)T.tiles * T.red_chunks : 0,
+                                       ((int64_t)T.tiles * T.vn_wpt + kWavesPerBlock - 1) / kWavesPerBlock,
+                                       ((int64_t)T.tiles * g->m + kBlock - 1) / kBlock,
+                                       ((int64_t)T.gamma + kBlock - 1) / kBlock,
+                                       io};
+        for (int k = 0; k < kKinds; ++k) {
+            A.items[k][c] = (int32_t)items[k];
+            A.tk[k][c] = (int32_t)((items[k] + A.items_per_ticket - 1) / A.items_per_ticket);
+        }
+        T0 += A.tk[kKindIngest][c];
+        Titer += A.tk[kKindCN][c] + A.tk[kKindUnsat][c] + A.tk[kKindVN][c];
+        Ttail += A.tk[kKindSyn][c] + A.tk[kKindStatus][c] + A.tk[kKindOut][c];
+    }
+    uint64_t total = T0 + (uint64_t)P->max_iters * Titer + Ttail;
+    for (int c = 0; c < P->ncodes; ++c)   // coherent accesses use 31-bit offsets within a code's region
+        if (code_region(P->graphs[c], P->gammas[c], P->layouts[c], P->max_iters).total >= ((size_t)1 << 31))
+            total = 0;
+    A.T0 = (uint32_t)T0;
+    A.Titer = (uint32_t)Titer;
+    A.total = total < ((uint64_t)1 << 31) ? (uint32_t)total : 0u;   // 0: the launch cannot take this plan
     P->red_blocks = red;
     P->cn_waves = cn;
     P->vn_waves = vn;
@@ -798,8 +1174,10 @@ bool same_buffers(const ldpc_plan* P, const PlanBuffers& B, const void* ws) {
 ldpc_status upload_table(ldpc_plan* P, const PlanBuffers& B, char* ws, hipStream_t st) {
     if (same_buffers(P, B, ws)) return LDPC_OK;
     build_table(P, B, ws);
-    if (hipMemcpyAsync(ws, P->table.data(), P->table.size() * sizeof(PlanCode), hipMemcpyHostToDevice, st) !=
-            hipSuccess ||
+    // the table, then the persistent launch's counters (zero)
+    std::vector<char> host(P->state_off + sizeof(PersistState), 0);
+    std::memcpy(host.data(), P->table.data(), P->table.size() * sizeof(PlanCode));
+    if (hipMemcpyAsync(ws, host.data(), host.size(), hipMemcpyHostToDevice, st) != hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess)
         return LDPC_EHIP;
     P->table_valid = true;
@@ -814,6 +1192,14 @@ unsigned blocks_for(int64_t units, int per_block) { return (unsigned)((units + p
 void enqueue(ldpc_plan* P, char* ws, hipStream_t st) {
     const PlanCode* T = reinterpret_cast<const PlanCode*>(ws);
     const int nc = P->ncodes;
+    if (P->persistent) {
+        PersistArgs A = P->pa;
+        A.wait_ticks = P->wait_ticks;
+        timing::Scope ts(22, st);
+        plan_persistent_kernel<<<(unsigned)std::min<int64_t>(P->persist_grid, A.total), kBlock, 0, st>>>(
+            T, reinterpret_cast<PersistState*>(ws + P->state_off), A);
+        return;
+    }
     PlanStep S{0, 0, P->early, P->max_iters};
     {
         timing::Scope ts(17, st);
@@ -880,7 +1266,8 @@ ldpc_status ldpc_plan_create(const ldpc_graph* const* graphs, const int32_t* gam
     P->graphs.assign(graphs, graphs + ncodes);
     P->gammas.assign(gammas, gammas + ncodes);
     P->layouts.resize(ncodes);
-    P->table_bytes = align256((size_t)ncodes * sizeof(PlanCode));
+    P->state_off = align256((size_t)ncodes * sizeof(PlanCode));
+    P->table_bytes = align256(P->state_off + sizeof(PersistState));
     size_t off = P->table_bytes;
     for (int c = 0; c < ncodes; ++c) {
         P->layouts[c] = default_layout(graphs[c], gammas[c]);
@@ -937,6 +1324,7 @@ ldpc_status ldpc_plan_decode(ldpc_plan* P, const float* const* llr, float* const
     (void)hipGetLastError();
     ldpc_status up = upload_table(P, B, ws, st);
     if (up != LDPC_OK) return up;
+    if (P->persistent && P->pa.total == 0) return LDPC_EUNSUPPORTED;
     enqueue(P, ws, st);
     return hipGetLastError() == hipSuccess ? LDPC_OK : LDPC_EHIP;
 }
@@ -953,6 +1341,7 @@ ldpc_status ldpc_plan_capture(ldpc_plan* P, const float* const* llr, float* cons
     (void)hipGetLastError();
     ldpc_status up = upload_table(P, B, ws, st);
     if (up != LDPC_OK) return up;
+    if (P->persistent && P->pa.total == 0) return LDPC_EUNSUPPORTED;
     if (!P->cap_stream && hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking) != hipSuccess) {
         P->cap_stream = nullptr;
         return LDPC_EHIP;
@@ -1003,6 +1392,7 @@ ldpc_status ldpc_plan_autotune(ldpc_plan* P, const float* const* llr, float* con
         (void)hipGetLastError();
         ldpc_status up = upload_table(P, B, ws, st);
         if (up != LDPC_OK) return up;
+        if (P->persistent && P->pa.total == 0) return LDPC_EUNSUPPORTED;
         enqueue(P, ws, st);
         float ms = 0.0f;
         if (hipEventRecord(e0, st) != hipSuccess) return LDPC_EHIP;
@@ -1040,6 +1430,50 @@ ldpc_status ldpc_plan_autotune(ldpc_plan* P, const float* const* llr, float* con
     (void)hipEventDestroy(e1);
     if (status == LDPC_OK && best_ms) *best_ms = best;
     return status;
+}
+
+ldpc_status ldpc_plan_set_persistent(ldpc_plan* P, int32_t on, int64_t wait_limit_us) {
+    if (!P || (on != 0 && on != 1) || wait_limit_us < 0) return LDPC_EINVAL;
+    const int64_t us = wait_limit_us ? wait_limit_us : 2000000;
+    if (on) {
+        int dev = 0, cus = 0, per_cu = 0, rate_khz = 0;
+        (void)hipGetLastError();
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, plan_persistent_kernel, kBlock, 0) != hipSuccess ||
+            cus < 1 || per_cu < 1 || rate_khz < 1) {
+            (void)hipGetLastError();
+            return LDPC_EHIP;
+        }
+        P->persist_grid = cus * per_cu;
+        P->wait_ticks = (uint64_t)us * (uint64_t)rate_khz / 1000u;
+        if (P->wait_ticks == 0) P->wait_ticks = 1;
+    }
+    P->wait_us = us;
+    if (P->persistent != on) {
+        P->persistent = on;
+        P->generation += 1;   // a captured graph holds the other form
+    }
+    return LDPC_OK;
+}
+
+ldpc_status ldpc_plan_check(ldpc_plan* P, void* workspace, void* stream) {
+    if (!P || !workspace) return LDPC_EINVAL;
+    if (!P->table_valid || P->table_ws != workspace) return LDPC_EINVAL;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    char* w = reinterpret_cast<char*>(workspace) + P->state_off + offsetof(PersistState, err_sticky.v);
+    uint32_t err = 0;
+    (void)hipGetLastError();
+    if (hipMemcpyAsync(&err, w, sizeof(err), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return LDPC_EHIP;
+    if (!err) return LDPC_OK;
+    const uint32_t zero = 0;
+    if (hipMemcpyAsync(w, &zero, sizeof(zero), hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return LDPC_EHIP;
+    return LDPC_EHIP;
 }
 
 }  // extern "C"

@@ -32,7 +32,7 @@ def simulate(g: ldpc.Graph, ebn0_db: float, *, decoder: str = "block", gamma: in
     """Simulate until `min_frame_errors` frame errors or `max_frames` frames.
 
     decoder: "block" (QC graph, `iters` flooding iterations), "nms" (QC
-    graph, learned min-sum with `weights` [T, J, 2], T iterations), "pipeline"
+    graph, learned min-sum with `weights` [T, blocks, 2], T iterations), "pipeline"
     (convolutional graph, `iters` processors) or "window" (convolutional
     graph, window `window`, `iters` iterations per window).  A frame is one
     codeword of the block code, or one stream of the convolutional chain.

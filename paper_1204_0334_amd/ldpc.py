@@ -38,7 +38,7 @@ def layout_name(layout: int) -> str:
     v, c = (layout >> 4) & 3, (layout >> 6) & 3
     return LAYOUT_NAMES[layout & 15] + ("" if v == 0 else f"/VN{1 << v}") + ("" if c == 0 else f"/CN{1 << c}")
 PLAN_MAX_CODES = 16
-TIMING_CLASSES = 22
+TIMING_CLASSES = 23
 MAX_ITERS = 100000
 NOALLOC_SCRATCH_BYTES = 64 * 1024 * 1024
 
@@ -46,7 +46,7 @@ NOALLOC_SCRATCH_BYTES = 64 * 1024 * 1024
 class GraphInfo(ctypes.Structure):
     _fields_ = [("kind", _i32), ("n", _i32), ("m", _i32), ("E", _i32), ("dv_max", _i32), ("dc_max", _i32),
                 ("J", _i32), ("L", _i32), ("p", _i32), ("ms", _i32), ("T", _i32), ("Jb", _i32), ("Lb", _i32),
-                ("c", _i32), ("c_minus_b", _i32), ("positions", _i32), ("layers", _i32),
+                ("c", _i32), ("c_minus_b", _i32), ("positions", _i32), ("layers", _i32), ("blocks", _i32),
                 ("design_rate", ctypes.c_double)]
 
 
@@ -80,6 +80,8 @@ _plan_capture = _sig("ldpc_plan_capture", _i32, [_vp, _vp, _vp, _vp, _vp, _vp, _
 _plan_replay = _sig("ldpc_plan_replay", _i32, [_vp, _vp])
 _plan_autotune = _sig("ldpc_plan_autotune", _i32,
                       [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _i32, _vp, ctypes.POINTER(ctypes.c_double)])
+_plan_set_persistent = _sig("ldpc_plan_set_persistent", _i32, [_vp, _i32, _i64])
+_plan_check = _sig("ldpc_plan_check", _i32, [_vp, _vp, _vp])
 _decode_window = _sig("ldpc_decode_window", _i32, [_vp, _vp, _i32, _i32, _i32, _vp, _vp, _vp, _sz, _vp])
 _decode_pipeline = _sig("ldpc_decode_pipeline", _i32, [_vp, _vp, _i32, _i32, _vp, _vp, _vp, _sz, _vp])
 _awgn_llr = _sig("ldpc_awgn_llr", _i32, [_i64, _i32, ctypes.c_double, ctypes.c_uint64, _i64, _vp, _vp])
@@ -94,7 +96,7 @@ EXPORTED = ["ldpc_graph_create_qc", "ldpc_graph_create_ldpccc_from_qc", "ldpc_gr
             "ldpc_nms_decode", "ldpc_nms_train_workspace_size", "ldpc_nms_train_forward",
             "ldpc_nms_train_backward", "ldpc_plan_create", "ldpc_plan_destroy", "ldpc_plan_workspace_size",
             "ldpc_plan_set_layout", "ldpc_plan_get_layout", "ldpc_plan_decode", "ldpc_plan_capture",
-            "ldpc_plan_replay", "ldpc_plan_autotune", "ldpc_decode_window", "ldpc_decode_pipeline", "ldpc_awgn_llr",
+            "ldpc_plan_replay", "ldpc_plan_autotune", "ldpc_plan_set_persistent", "ldpc_plan_check", "ldpc_decode_window", "ldpc_decode_pipeline", "ldpc_awgn_llr",
             "ldpc_count_errors", "ldpc_status_str", "ldpc_timing_enable", "ldpc_timing_read",
             "ldpc_kernel_class_name"]
 
@@ -289,14 +291,15 @@ def _decode_outputs(llr, gamma, n, out, fresh):
 
 def nms_decode(g: Graph, llr, weights, early_stop: bool = False, out=None, ws=None, stream=None):
     """Learned min-sum decoding of llr [gamma, n] with weights float32
-    [iters, J, 2] (scale, offset) on the device; iters = weights.shape[0].
+    [iters, blocks, 2] (scale, offset per edge class: the graph's circulant
+    blocks) on the device; iters = weights.shape[0].
     Returns (post, bits, iters, converged)."""
     if llr.dim() != 2:
         raise ValueError("llr must be [gamma, n]")
     gamma, n = llr.shape
     _need(llr, torch.float32, (gamma, g.n), "llr")
     T = int(weights.shape[0]) if weights.dim() == 3 else -1
-    _need(weights, torch.float32, (T, g.info["J"], 2), "weights")
+    _need(weights, torch.float32, (T, g.info["blocks"], 2), "weights")
     fresh = []
     post, bits, iters, conv = _decode_outputs(llr, gamma, n, out, fresh)
     if ws is None:
@@ -328,7 +331,7 @@ def nms_train_forward(g: Graph, llr, weights, ckpt_every: int, ws, loss=None, st
     gamma, n = llr.shape
     _need(llr, torch.float32, (gamma, g.n), "llr")
     T = int(weights.shape[0]) if weights.dim() == 3 else -1
-    _need(weights, torch.float32, (T, g.info["J"], 2), "weights")
+    _need(weights, torch.float32, (T, g.info["blocks"], 2), "weights")
     fresh = []
     if loss is None:
         loss = torch.empty((T,), dtype=torch.float32, device=llr.device)
@@ -341,10 +344,10 @@ def nms_train_forward(g: Graph, llr, weights, ckpt_every: int, ws, loss=None, st
 
 
 def nms_train_backward(g: Graph, gamma: int, weights, ckpt_every: int, dloss, ws, grad=None, stream=None):
-    """Gradient float32 [iters, J, 2] of sum_t dloss[t] loss[t] with respect to
+    """Gradient float32 [iters, blocks, 2] of sum_t dloss[t] loss[t] with respect to
     the weights, after nms_train_forward on the same workspace."""
     T = int(weights.shape[0]) if weights.dim() == 3 else -1
-    _need(weights, torch.float32, (T, g.info["J"], 2), "weights")
+    _need(weights, torch.float32, (T, g.info["blocks"], 2), "weights")
     _need(dloss, torch.float32, (T,), "dloss")
     fresh = []
     if grad is None:
@@ -548,6 +551,16 @@ class Plan:
         _check(_plan_autotune(self._h, *a, ws.data_ptr(), ws.numel(), int(trials), _stream_handle(stream),
                               ctypes.byref(best)), "ldpc_plan_autotune")
         return float(best.value)
+
+    def set_persistent(self, on: bool = True, wait_limit_us: int = 0):
+        """Decode (and capture, autotune) as one persistent launch instead of
+        the phase launches; wait_limit_us bounds each of its waits (0: 2 s)."""
+        _check(_plan_set_persistent(self._h, int(bool(on)), int(wait_limit_us)), "ldpc_plan_set_persistent")
+
+    def check(self, ws, stream=None):
+        """Raise LdpcError(EHIP) if a persistent decode on `ws` had a wait
+        expire since the last check (synchronises the stream)."""
+        _check(_plan_check(self._h, ws.data_ptr(), _stream_handle(stream)), "ldpc_plan_check")
 
     def close(self):
         h = getattr(self, "_h", None)

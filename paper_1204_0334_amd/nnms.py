@@ -3,9 +3,9 @@ wrapper of the library's training entry points, Adam training on frames that
 the GPU generates, and the FER comparison with plain sum-product.
 
 The decoder keeps the flooding schedule of Algorithm 1 and replaces the
-horizontal step (Eq. 3) by alpha = w[t, j] * sign * max(min|beta| - b[t, j], 0)
-with one (w, b) pair per iteration t and base row j (Nachmani et al. 2016,
-2018; Lugosch & Gross 2017).  Forward, backward and decoding run in the HIP
+horizontal step (Eq. 3) by alpha = w[t, e] * sign * max(min|beta| - b[t, e], 0)
+with one (w, b) pair per iteration t and edge class e, the edge's circulant
+block (Nachmani et al. 2016, 2018; Lugosch & Gross 2017).  Forward, backward and decoding run in the HIP
 library (`ldpc_nms_train_forward`, `ldpc_nms_train_backward`,
 `ldpc_nms_decode`); this module holds the optimiser loop.
 """
@@ -21,7 +21,7 @@ from . import fer, ldpc
 
 
 class IterationLosses(torch.autograd.Function):
-    """weights [T, J, 2] -> per-iteration BCE losses [T] of the learned
+    """weights [T, blocks, 2] -> per-iteration BCE losses [T] of the learned
     min-sum decoder on llr [gamma, n] (all-zero codeword).  The backward pass
     is the library's hand-written one, recomputing every `ckpt_every`
     iterations from the checkpoints the forward pass left in `ws`."""
@@ -45,8 +45,9 @@ def iteration_losses(weights, g, llr, ckpt_every: int, ws):
     return IterationLosses.apply(weights, g, llr, ckpt_every, ws)
 
 
-def initial_weights(T: int, J: int, scale: float = 0.8, offset: float = 0.0, device=None):
-    w = torch.empty((T, J, 2), dtype=torch.float32, device=device or "cuda")
+def initial_weights(T: int, classes: int, scale: float = 0.8, offset: float = 0.0, device=None):
+    """[T, classes, 2]: every class starts at (scale, offset)."""
+    w = torch.empty((T, classes, 2), dtype=torch.float32, device=device or "cuda")
     w[..., 0] = scale
     w[..., 1] = offset
     return w
@@ -68,7 +69,7 @@ def train(g: ldpc.Graph, T: int = 12, ckpt_every: int | None = None, frames: int
     """Adam on sum_t loss_weights[t] * (BCE of iteration t) (default: the
     mean over iterations), batches of `batch` fresh frames, each run of
     `chunk` frames at an Eb/N0 drawn uniformly from `ebn0_range`.  Scales and
-    offsets are kept >= 0 after every step.  Returns (weights [T, J, 2],
+    offsets are kept >= 0 after every step.  Returns (weights [T, blocks, 2],
     history of (frames, loss)).  `ckpt_every` None: choose_ckpt_every.
 
     With `checkpoint_path`, the weights, the Adam state, the step count, the
@@ -78,10 +79,10 @@ def train(g: ldpc.Graph, T: int = 12, ckpt_every: int | None = None, frames: int
     frames as an uninterrupted one)."""
     dev = torch.device(device or "cuda:0")
     info = g.info
-    n, J, rate = info["n"], info["J"], info["design_rate"]
+    n, classes, rate = info["n"], info["blocks"], info["design_rate"]
     if batch % chunk:
         raise ValueError("batch must be a multiple of chunk")
-    W = (init.clone() if init is not None else initial_weights(T, J, device=dev)).requires_grad_(True)
+    W = (init.clone() if init is not None else initial_weights(T, classes, device=dev)).requires_grad_(True)
     opt = torch.optim.Adam([W], lr=lr)
     if ckpt_every is None:
         ckpt_every = choose_ckpt_every(g, batch, T, dev)

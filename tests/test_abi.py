@@ -344,3 +344,16 @@ def test_mixed_workload_codes_fit_a_plan():
     plan = ldpc.Plan(graphs, [c["gamma"] for c in synth.MIXED_CODES], 20, early_stop=True)
     assert plan.workspace_size() > 0
     assert [g.info["dc_max"] for g in graphs] == [6, 6, 6, 9, 9, 18, 18]
+
+
+def test_plan_persistent_mode_validates_before_touching_the_gpu():
+    g36 = ldpc.Graph.qc(synth.draw_qc_shifts(3, 6, 27, 1), 27)
+    plan = ldpc.Plan([g36], [8], 20, early_stop=True)
+    sp, chk = ldpc._plan_set_persistent, ldpc._plan_check
+    assert sp(None, 1, 0) == ldpc.EINVAL
+    assert sp(plan.handle, 2, 0) == ldpc.EINVAL
+    assert sp(plan.handle, 1, -1) == ldpc.EINVAL
+    assert sp(plan.handle, 0, 0) == ldpc.OK            # the phase launches need no device query
+    assert chk(None, FAKE, None) == ldpc.EINVAL
+    assert chk(plan.handle, None, None) == ldpc.EINVAL
+    assert chk(plan.handle, FAKE, None) == ldpc.EINVAL  # no decode has bound this workspace

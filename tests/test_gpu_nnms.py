@@ -33,15 +33,18 @@ def case(J, L, p, seed, gamma, ebn0, noise_seed):
     return a, llr
 
 
-def rand_weights(T, J, seed):
+def rand_weights(T, classes, seed):
+    """[T, classes, 2]: (scale, offset) per iteration and edge class."""
     rng = np.random.default_rng(seed)
-    w = np.stack([rng.uniform(0.55, 1.0, size=(T, J)), rng.uniform(0.0, 0.6, size=(T, J))], axis=-1)
+    w = np.stack([rng.uniform(0.55, 1.0, size=(T, classes)), rng.uniform(0.0, 0.6, size=(T, classes))], axis=-1)
     return w.astype(np.float32)
 
 
 def ref_graph(a, p):
-    J = a.shape[0]
-    return ref_nnms.EdgeGraph(oracle.qc_parity_check(a, p), ref_nnms.qc_row_class(J, p))
+    return ref_nnms.EdgeGraph(oracle.qc_parity_check(a, p), ref_nnms.qc_edge_class(a, p))
+
+
+NB36, NB318 = 18, 54   # edge classes (circulant blocks) of the 3 x 6 and 3 x 18 bases
 
 
 def gpu_nms(g, llr, w, early=False):
@@ -67,7 +70,7 @@ def check_decode(gpu, ref, what):
 @pytest.mark.parametrize("T,gamma", [(1, 64), (3, 64), (12, 64), (12, 200), (4, 1), (5, 65)])
 def test_nms_decode_matches_reference(T, gamma):
     a, llr = case(3, 6, 64, 1, gamma, 2.0, 101)
-    w = rand_weights(T, 3, T)
+    w = rand_weights(T, NB36, T)
     ref = ref_nnms.decode(ref_graph(a, 64), llr.astype(np.float64), w[..., 0], w[..., 1], T)
     gpu = gpu_nms(ldpc.Graph.qc(a, 64), llr, w)
     check_decode(gpu, ref, f"T={T} gamma={gamma}")
@@ -77,7 +80,7 @@ def test_nms_decode_matches_reference(T, gamma):
 def test_nms_decode_wide_rows():
     # 3 x 18 base (row weight 18): one frame per lane, row-weight class 24
     a, llr = case(3, 18, 36, 3, 96, 3.5, 55)
-    w = rand_weights(8, 3, 5)
+    w = rand_weights(8, NB318, 5)
     ref = ref_nnms.decode(ref_graph(a, 36), llr.astype(np.float64), w[..., 0], w[..., 1], 8)
     check_decode(gpu_nms(ldpc.Graph.qc(a, 36), llr, w), ref, "3x18")
 
@@ -87,7 +90,7 @@ def test_nms_early_stop_returns_the_stopping_iteration():
     g = ldpc.Graph.qc(a, 64)
     H = oracle.qc_parity_check(a, 64)
     T = 12
-    w = rand_weights(T, 3, 9)
+    w = rand_weights(T, NB36, 9)
     gpu = gpu_nms(g, llr, w, early=True)
     syn = H.syndrome(gpu["bits"])
     assert np.array_equal(gpu["converged"].astype(bool), ~syn.any(1))
@@ -127,7 +130,7 @@ def check_grad(gg, gw, gb, what):
 @pytest.mark.parametrize("gamma,T,ckpt", [(64, 6, 2), (200, 5, 2), (256, 12, 4)])
 def test_gradient_matches_fp64_autograd(gamma, T, ckpt):
     a, llr = case(3, 6, 64, 1, gamma, 1.5, 303)
-    w = rand_weights(T, 3, 11)
+    w = rand_weights(T, NB36, 11)
     g = ldpc.Graph.qc(a, 64)
     loss, gg = gpu_grad(g, llr, w, ckpt)
     G = ref_graph(a, 64)
@@ -143,7 +146,7 @@ def test_gradient_matches_fp64_autograd(gamma, T, ckpt):
 def test_gradient_with_per_iteration_upstream():
     a, llr = case(3, 6, 64, 1, 128, 1.5, 304)
     T = 4
-    w = rand_weights(T, 3, 12)
+    w = rand_weights(T, NB36, 12)
     coef = np.array([0.0, 2.0, -0.5, 1.0])
     g = ldpc.Graph.qc(a, 64)
     _, gg = gpu_grad(g, llr, w, 2, dloss=coef)
@@ -156,7 +159,7 @@ def test_gradient_with_per_iteration_upstream():
 def test_gradient_independent_of_checkpoint_interval():
     a, llr = case(3, 6, 64, 1, 256, 1.5, 305)
     T = 6
-    w = rand_weights(T, 3, 13)
+    w = rand_weights(T, NB36, 13)
     g = ldpc.Graph.qc(a, 64)
     grads = [gpu_grad(g, llr, w, k)[1] for k in (1, 2, 4, 6)]
     for k, gk in zip((2, 4, 6), grads[1:]):
@@ -167,12 +170,32 @@ def test_gradient_independent_of_checkpoint_interval():
 def test_gradient_wide_rows():
     a, llr = case(3, 18, 36, 3, 64, 3.5, 56)
     T = 4
-    w = rand_weights(T, 3, 14)
+    w = rand_weights(T, NB318, 14)
     _, gg = gpu_grad(ldpc.Graph.qc(a, 36), llr, w, 2)
     x = np.ones_like(llr, dtype=np.float64)
     _, gw, gb = ref_nnms.grad(ref_graph(a, 36), llr.astype(np.float64), x, w[..., 0].astype(np.float64),
                               w[..., 1].astype(np.float64), T)
     check_grad(gg, gw, gb, "3x18")
+
+
+def test_irregular_base_decode_and_gradient():
+    # zero blocks: base rows with 4 and 5 blocks, columns with 1 to 3, so an
+    # edge slot of a row is not its block's base column
+    a = np.array([[0, 5, -1, 7, 2, -1], [9, -1, 4, 1, -1, 6], [-1, 2, 8, -1, 10, 12]])
+    p = 13
+    g = ldpc.Graph.qc(a, p)
+    nb = int((a >= 0).sum())
+    assert g.info["blocks"] == nb
+    llr = synth.bpsk_awgn_llr(None, synth.ebn0_to_sigma2(2.0, 0.5), 57, gamma=96, n=6 * p)
+    T = 5
+    w = rand_weights(T, nb, 16)
+    ref = ref_nnms.decode(ref_graph(a, p), llr.astype(np.float64), w[..., 0], w[..., 1], T)
+    check_decode(gpu_nms(g, llr, w), ref, "irregular base")
+    _, gg = gpu_grad(g, llr, w, 2)
+    x = np.ones_like(llr, dtype=np.float64)
+    _, gw, gb = ref_nnms.grad(ref_graph(a, p), llr.astype(np.float64), x, w[..., 0].astype(np.float64),
+                              w[..., 1].astype(np.float64), T)
+    check_grad(gg, gw, gb, "irregular base")
 
 
 def test_paper_scale_gradient():
@@ -184,7 +207,7 @@ def test_paper_scale_gradient():
     s2 = synth.ebn0_to_sigma2(1.75, 0.5)
     g = ldpc.Graph.qc(a, 3060)
     T, ckpt = 12, 4
-    w = rand_weights(T, 3, 15)
+    w = rand_weights(T, NB36, 15)
     llr = synth.bpsk_awgn_llr(None, s2, 909, gamma=16, n=18360)
     _, gg = gpu_grad(g, llr, w, ckpt)
     x = np.ones_like(llr, dtype=np.float64)
@@ -206,7 +229,7 @@ def test_training_improves_on_plain_min_sum():
     g = ldpc.Graph.qc(a, 64)
     T = 6
     print("[gpu] nnms.train p=64", flush=True)
-    plain = nnms.initial_weights(T, 3, scale=1.0, offset=0.0, device=DEV)
+    plain = nnms.initial_weights(T, NB36, scale=1.0, offset=0.0, device=DEV)
     W, hist = nnms.train(g, T=T, ckpt_every=2, frames=64 * 1024, batch=1024, lr=0.02, log_every=8, init=plain)
     assert torch.all(W >= 0)
     assert not torch.allclose(W[..., 0], plain[..., 0])
@@ -223,7 +246,7 @@ def test_training_resumes_from_checkpoint(tmp_path):
     a = synth.draw_qc_shifts(3, 6, 64, 1)
     g = ldpc.Graph.qc(a, 64)
     T = 4
-    init = nnms.initial_weights(T, 3, 0.8, 0.1, device=DEV)
+    init = nnms.initial_weights(T, NB36, 0.8, 0.1, device=DEV)
     print("[gpu] nnms.train checkpoint", flush=True)
     W_full, h_full = nnms.train(g, T=T, ckpt_every=2, frames=6 * 512, batch=512, lr=0.02, init=init, log_every=1)
     path = str(tmp_path / "nnms.pt")
@@ -243,7 +266,7 @@ def test_default_keeps_every_iteration_and_trains_identically():
     g = ldpc.Graph.qc(a, 64)
     T = 5
     assert nnms.choose_ckpt_every(g, 512, T, DEV) == T
-    init = nnms.initial_weights(T, 3, 0.8, 0.1, device=DEV)
+    init = nnms.initial_weights(T, NB36, 0.8, 0.1, device=DEV)
     print("[gpu] nnms.train default checkpoint interval", flush=True)
     W_all, h_all = nnms.train(g, T=T, frames=3 * 512, batch=512, lr=0.02, init=init, log_every=1)
     W_ck, h_ck = nnms.train(g, T=T, ckpt_every=2, frames=3 * 512, batch=512, lr=0.02, init=init, log_every=1)

@@ -145,8 +145,8 @@ def sampled_frames(gamma):
     return np.unique(np.array([0, 1, gamma // 3, gamma // 2, gamma - 2, gamma - 1]).clip(0, gamma - 1))
 
 
-@pytest.mark.parametrize("iters,early", [(3, False), (20, True)])
-def test_mixed_workload_codes_at_full_size_against_reference(iters, early):
+@pytest.mark.parametrize("iters,early,persistent", [(3, False, False), (20, True, False), (20, True, True)])
+def test_mixed_workload_codes_at_full_size_against_reference(iters, early, persistent):
     # the seven codes of the mixed workload at their real circulant sizes
     # (rate 1/2: p = 27, 81, 2700; rate 2/3: p = 72, 2400; rate 5/6: p = 36,
     # 3600) and batch sizes, decoded together by one plan with the layouts
@@ -157,9 +157,12 @@ def test_mixed_workload_codes_at_full_size_against_reference(iters, early):
     graphs, shifts, llr_np = cpu_case(specs, 7000)
     llrs = [torch.from_numpy(x).to(DEV) for x in llr_np]
     plan = ldpc.Plan(graphs, [c["gamma"] for c in specs], iters, early_stop=early)
+    if persistent:
+        plan.set_persistent(True)
     ws = plan.workspace(DEV)
     outs = plan.outputs(DEV)
-    print(f"[gpu] mixed plan at full size iters={iters} early={early}: autotune", flush=True)
+    print(f"[gpu] mixed plan at full size iters={iters} early={early} persistent={persistent}: autotune",
+          flush=True)
     plan.autotune(llrs, outs, ws, trials=1)
     print(f"[gpu] layouts {[ldpc.layout_name(plan.layout(c)) for c in range(len(specs))]}", flush=True)
     outs = plan.decode(llrs, outs=outs, ws=ws)
@@ -174,6 +177,8 @@ def test_mixed_workload_codes_at_full_size_against_reference(iters, early):
         if early:
             assert np.array_equal(o[3].astype(bool), ~H.syndrome(o[1]).any(1))
     assert gated >= 30
+    if persistent:
+        plan.check(ws)
 
 
 def test_graph_replay_matches_eager_decode():
@@ -254,3 +259,105 @@ def test_plan_at_the_code_limit_with_irregular_and_degenerate_codes():
         assert_same(outs, single_code(graphs, llrs, 12, early), f"16 codes early={early}")
     with pytest.raises(Exception):
         ldpc.Plan(graphs + graphs[:1], gammas + [1], 12)
+
+
+# ----------------------------------------------------------------------------
+# one persistent launch per decode
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("early,items", [(True, "2"), (False, "2"), (True, "1"), (True, "7")])
+def test_persistent_launch_matches_single_code_decoder(early, items, monkeypatch):
+    # LDPC_PLAN_TICKET_ITEMS is read when the plan's table is built
+    monkeypatch.setenv("LDPC_PLAN_TICKET_ITEMS", items)
+    specs = synth.MIXED_CODES
+    graphs, llrs = make_case(specs, 1100)
+    plan = ldpc.Plan(graphs, [c["gamma"] for c in specs], 20, early_stop=early)
+    plan.set_persistent(True)
+    ws = plan.workspace(DEV)
+    print(f"[gpu] persistent mixed plan early={early} items={items}", flush=True)
+    ldpc.timing_read()
+    ldpc.timing_enable(True)
+    outs = plan.decode(llrs, ws=ws)
+    torch.cuda.synchronize()
+    ldpc.timing_enable(False)
+    t = ldpc.timing_read()
+    assert t["plan_persistent"][0] == 1 and t["plan_check_node"][0] == 0, t
+    plan.check(ws)
+    assert_same(outs, single_code(graphs, llrs, 20, early), f"persistent early={early} items={items}")
+    # twice in a row on the same workspace (the launch resets its counters)
+    again = plan.decode(llrs, ws=ws)
+    plan.check(ws)
+    assert_same(again, outs, "second persistent decode")
+
+
+def test_persistent_launch_at_the_code_limit():
+    irregular = np.array([[0, 5, -1, 7, 2, -1, 11, 3], [9, -1, 4, 1, -1, 6, 0, -1],
+                          [-1, 2, 8, -1, 10, 12, -1, 5], [3, 7, -1, -1, 1, -1, 9, 0]])
+    tables = [(irregular, 13), (np.array([[0, -1], [3, -1]]), 5),
+              (np.random.default_rng(54).integers(0, 17, size=(3, 18)), 17),
+              (np.random.default_rng(96).integers(0, 13, size=(4, 24)), 13)]
+    for i, c in enumerate(RAGGED + synth.MIXED_CODES[:5]):
+        tables.append((synth.draw_qc_shifts(c["J"], c["L"], c["p"], 70 + i), c["p"]))
+    gammas = [1, 70, 300, 2, 64, 65, 3, 129, 31, 256, 5, 1, 200, 17, 8, 97]
+    graphs = [ldpc.Graph.qc(a, p) for a, p in tables]
+    llrs = [ldpc.awgn_llr(g.n, k, synth.ebn0_to_sigma2(3.0, 0.5), 3100 + i, 0, device=DEV)
+            for i, (g, k) in enumerate(zip(graphs, gammas))]
+    for early in (True, False):
+        print(f"[gpu] persistent 16-code plan early={early}", flush=True)
+        plan = ldpc.Plan(graphs, gammas, 12, early_stop=early)
+        plan.set_persistent(True)
+        ws = plan.workspace(DEV)
+        outs = plan.decode(llrs, ws=ws)
+        plan.check(ws)
+        assert_same(outs, single_code(graphs, llrs, 12, early), f"persistent 16 codes early={early}")
+
+
+def test_persistent_graph_replay_matches_eager_decode():
+    graphs, llrs = make_case(synth.MIXED_CODES, 5100)
+    gammas = [c["gamma"] for c in synth.MIXED_CODES]
+    plan = ldpc.Plan(graphs, gammas, 20, early_stop=True)
+    plan.set_persistent(True)
+    ws = plan.workspace(DEV)
+    eager = [tuple(t.clone() for t in o) for o in plan.decode(llrs, ws=ws)]
+    torch.cuda.synchronize()
+    outs = plan.outputs(DEV)
+    print("[gpu] persistent plan capture", flush=True)
+    plan.capture(llrs, outs, ws)
+    scratch = torch.zeros(1 << 20, device=DEV)
+    for rep in range(3):
+        for o in outs:
+            for t in o:
+                t.zero_()
+        scratch.add_(1.0)                  # eager work between replays
+        torch.cuda.synchronize()
+        print(f"[gpu] persistent plan replay {rep}", flush=True)
+        plan.replay()
+        torch.cuda.synchronize()
+        assert_same(outs, eager, f"persistent replay {rep}")
+    plan.check(ws)
+    # switching back to the phase launches invalidates the graph
+    plan.set_persistent(False)
+    with pytest.raises(ldpc.LdpcError):
+        plan.replay()
+
+
+def test_persistent_wait_expiry_is_reported_and_the_next_decode_is_exact():
+    # a wait limit of 1 us makes the waits for the other workgroups' steps
+    # expire: the launch stops early but exits normally, and the check reports
+    # it; with the default limit the same plan and workspace decode exactly
+    graphs, llrs = make_case(synth.MIXED_CODES, 5200)
+    gammas = [c["gamma"] for c in synth.MIXED_CODES]
+    plan = ldpc.Plan(graphs, gammas, 20, early_stop=True)
+    ws = plan.workspace(DEV)
+    plan.set_persistent(True, wait_limit_us=1)
+    print("[gpu] persistent plan with 1 us waits", flush=True)
+    plan.decode(llrs, ws=ws)
+    with pytest.raises(ldpc.LdpcError) as e:
+        plan.check(ws)
+    assert e.value.status == ldpc.EHIP
+    plan.check(ws)                          # the record was cleared
+    plan.set_persistent(True)
+    print("[gpu] persistent plan with the default wait limit", flush=True)
+    outs = plan.decode(llrs, ws=ws)
+    plan.check(ws)
+    assert_same(outs, single_code(graphs, llrs, 20, True), "after an expired wait")
