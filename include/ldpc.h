@@ -269,7 +269,12 @@ ldpc_status ldpc_nms_train_backward(const ldpc_graph* g, int32_t gamma, int32_t 
  *   LDPC_LAYOUT_G64F4: tiles of 256 frames, 4 frames per lane (row weight
  *     <= 6 and column weight <= 8 only);
  *   LDPC_LAYOUT_G64F2: tiles of 128 frames, 2 frames per lane (row weight
- *     <= 12 and column weight <= 8 only).
+ *     <= 12 and column weight <= 8 only);
+ *   LDPC_LAYOUT_G8F2, _G8F4, _G16F2, _G16F4, _G32F2, _G32F4: groups of 8, 16
+ *     or 32 lanes per row (variable), each lane carrying 2 or 4 consecutive
+ *     frames (tiles of 16 to 128 frames; 64 * frames-per-lane / lanes rows
+ *     per wavefront), so small batches still move 8 or 16 bytes per lane
+ *     and access (same row and column weight limits as G64F2 / G64F4).
  * OR-ing LDPC_LAYOUT_VN2 or LDPC_LAYOUT_VN4 into a one-frame-per-lane
  * layout (G8 .. G64, column weight <= 8) makes each variable-node wavefront
  * handle 2 or 4 groups of variables (fewer, longer waves); LDPC_LAYOUT_CN2
@@ -303,7 +308,7 @@ ldpc_status ldpc_nms_train_backward(const ldpc_graph* g, int32_t gamma, int32_t 
  *
  * ldpc_plan_autotune: one pass of coordinate descent over the codes: each
  * code in turn tries every other allowed layout value (tiles no larger than the
- * next power of two above its batch) while the others stay fixed; each
+ * next power of two at or above its batch) while the others stay fixed; each
  * candidate is timed over `trials` whole decodes of the plan (after one
  * warm-up) on the given buffers (outputs are overwritten); the fastest is
  * kept.  Writes the final time per decode in ms to *best_ms (host, may be
@@ -315,8 +320,9 @@ ldpc_status ldpc_nms_train_backward(const ldpc_graph* g, int32_t gamma, int32_t 
 typedef struct ldpc_plan ldpc_plan;
 #define LDPC_PLAN_MAX_CODES 16
 enum { LDPC_LAYOUT_G8 = 0, LDPC_LAYOUT_G16 = 1, LDPC_LAYOUT_G32 = 2, LDPC_LAYOUT_G64 = 3, LDPC_LAYOUT_G64F4 = 4,
-       LDPC_LAYOUT_G64F2 = 5, LDPC_LAYOUT_VN2 = 16, LDPC_LAYOUT_VN4 = 32, LDPC_LAYOUT_CN2 = 64,
-       LDPC_LAYOUT_CN4 = 128 };
+       LDPC_LAYOUT_G64F2 = 5, LDPC_LAYOUT_G8F2 = 6, LDPC_LAYOUT_G8F4 = 7, LDPC_LAYOUT_G16F2 = 8,
+       LDPC_LAYOUT_G16F4 = 9, LDPC_LAYOUT_G32F2 = 10, LDPC_LAYOUT_G32F4 = 11, LDPC_LAYOUT_VN2 = 16,
+       LDPC_LAYOUT_VN4 = 32, LDPC_LAYOUT_CN2 = 64, LDPC_LAYOUT_CN4 = 128 };
 
 ldpc_status ldpc_plan_create(const ldpc_graph* const* graphs, const int32_t* gammas, int32_t ncodes,
                              int32_t max_iters, int32_t early_stop, ldpc_plan** out);
@@ -450,7 +456,9 @@ const char* ldpc_status_str(ldpc_status s);
  * kernel class; ldpc_timing_read synchronises those events and returns, per
  * class, the launch count and the summed device time in milliseconds, then
  * clears them.  Classes (index into the arrays, capacity >= LDPC_TIMING_CLASSES):
- *   0 ingest, 1 check-node, 2 variable-node, 3 syndrome, 4 output,
+ *   0 ingest, 1 check-node, 2 variable-node, 3 syndrome, 4 output (the
+ *   last variable-node pass of a decode without early stopping, which writes
+ *   the outputs; with early stopping the final transpose),
  *   5 frame status, 6 window ingest, 7 window check-node,
  *   8 window variable-node, 9 pipeline ingest, 10 pipeline check-node,
  *   11 pipeline variable-node, 12 training check-node, 13 training

@@ -1952,7 +1952,8 @@ static void run_block(const ldpc_graph* g, const float* llr, int gamma, int max_
             unsat_reduce_kernel<FPL><<<(unsigned)(tl.tiles * chunks), 256, 0, st>>>(D, P, chunks);
         }
         {
-            timing::Scope ts(2, st);
+            // the last pass of a fixed-iteration decode writes the outputs: timed as class 4
+            timing::Scope ts(!early && P.last ? 4 : 2, st);
             if (early) {
                 LDPC_DV_SWITCH(dvc, (vn_block_early_kernel<DV, FPL><<<vn_grid, kBlock, 0, st>>>(D, P, postw)));
             } else if (P.last) {

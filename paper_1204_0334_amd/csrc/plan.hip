@@ -38,7 +38,11 @@
 
 namespace ldpc {
 
-constexpr int kPlanLayouts = 6;   // G8, G16, G32, G64, G64 with 4 and with 2 frames per lane
+// Base lane layouts: G lanes per row (variable) group, FPL frames per lane,
+// tiles of G * FPL frames.  0-3: G8, G16, G32, G64 with one frame per lane;
+// 4, 5: G64 with 4 and 2; 6-11: G8, G16, G32 with 2 and 4 frames per lane
+// (small tiles whose lanes still move 8 or 16 bytes per access).
+constexpr int kPlanLayouts = 12;
 
 // A code's layout value: base lane layout (bits 0-3), log2 of the number of
 // variable groups each variable-node wave handles (bits 4-5) and of row groups
@@ -47,9 +51,13 @@ __host__ __device__ constexpr int layout_base(int l) { return l & 15; }
 __host__ __device__ constexpr int layout_vpw(int l) { return 1 << ((l >> 4) & 3); }
 __host__ __device__ constexpr int layout_cpw(int l) { return 1 << ((l >> 6) & 3); }
 __host__ __device__ constexpr int layout_g(int l) {
-    return layout_base(l) == 0 ? 8 : layout_base(l) == 1 ? 16 : layout_base(l) == 2 ? 32 : 64;
+    const int b = layout_base(l);
+    return b <= 3 ? 8 << b : b <= 5 ? 64 : b <= 7 ? 8 : b <= 9 ? 16 : 32;
 }
-__host__ __device__ constexpr int layout_fpl(int l) { return layout_base(l) == 4 ? 4 : layout_base(l) == 5 ? 2 : 1; }
+__host__ __device__ constexpr int layout_fpl(int l) {
+    const int b = layout_base(l);
+    return b <= 3 ? 1 : b == 4 ? 4 : b == 5 ? 2 : (b & 1) ? 4 : 2;
+}
 
 struct PlanCode {
     QCDesc D;
@@ -216,7 +224,13 @@ __device__ __forceinline__ uint64_t plan_pick(const uint64_t (&a)[FPL], int i) {
         case 2: { constexpr int G = 32, FPL = 1; __VA_ARGS__; } break;        \
         case 3: { constexpr int G = 64, FPL = 1; __VA_ARGS__; } break;        \
         case 4: { constexpr int G = 64, FPL = 4; __VA_ARGS__; } break;        \
-        default: { constexpr int G = 64, FPL = 2; __VA_ARGS__; } break;       \
+        case 5: { constexpr int G = 64, FPL = 2; __VA_ARGS__; } break;        \
+        case 6: { constexpr int G = 8, FPL = 2; __VA_ARGS__; } break;         \
+        case 7: { constexpr int G = 8, FPL = 4; __VA_ARGS__; } break;         \
+        case 8: { constexpr int G = 16, FPL = 2; __VA_ARGS__; } break;        \
+        case 9: { constexpr int G = 16, FPL = 4; __VA_ARGS__; } break;        \
+        case 10: { constexpr int G = 32, FPL = 2; __VA_ARGS__; } break;       \
+        default: { constexpr int G = 32, FPL = 4; __VA_ARGS__; } break;       \
     }
 // row-weight classes of a plan (at most 24: one kernel serves every code, and
 // its register budget is that of the heaviest variant it contains)
@@ -260,7 +274,7 @@ __device__ __forceinline__ void plan_cn_body(const PlanCode& C, const PlanStep& 
         for (int i = 0; i < FPL; ++i) all = all && (M::ld64(C, fz + i) == ~0ull);
         if (all) return;
     }
-    const size_t lane_off = (G == 64) ? (size_t)lane * FPL : (size_t)f;
+    const size_t lane_off = (size_t)f * FPL;   // lane f of its group: frames f*FPL .. f*FPL+FPL-1
     float* mt = C.msg + (size_t)tile * D.E * Gt + lane_off;
     const float* ut = C.mu + (size_t)tile * D.n * Gt + lane_off;
     // the wave's rows: base row j (uniform), offsets sw*V*R .. within it
@@ -300,23 +314,43 @@ __device__ __forceinline__ void plan_cn_body(const PlanCode& C, const PlanStep& 
 #pragma unroll
             for (int off = 32; off >= FPL; off >>= 1) par ^= __shfl_xor(par, off);
         } else {
-            // one frame per lane: lane f of a group of G lanes takes variables
-            // f, f + G, ... of its row; every lane ends with the wave's word
+            // lane f of a group of G lanes takes the (variable k, word i)
+            // pairs q = f, f + G, ... of its row (k = q / FPL, i = q % FPL);
+            // XOR butterflies over the group give the row's parity words, an
+            // OR over the groups the wave's; lane i < FPL keeps word i
+            uint64_t acc[FPL];
+#pragma unroll
+            for (int i = 0; i < FPL; ++i) acc[i] = 0;
 #pragma unroll
             for (int v = 0; v < V; ++v) {
                 const PlanRow Rw(D, j, d[v] ? srow[v] : 0, d[v] > 0);
-                uint64_t x = 0;
+                uint64_t x[FPL];
 #pragma unroll
-                for (int q = 0; q < (DCMAX + G - 1) / G; ++q) {
-                    const int k = q * G + f;
-                    if (k < d[v]) x ^= M::ld64(C, bt + Rw.var(D, k));
+                for (int i = 0; i < FPL; ++i) x[i] = 0;
+#pragma unroll
+                for (int q0 = 0; q0 < (DCMAX * FPL + G - 1) / G; ++q0) {
+                    const int q = q0 * G + f;
+                    const int k = q / FPL, iq = q - k * FPL;
+                    if (k < d[v]) {
+                        const uint64_t word = M::ld64(C, bt + (size_t)Rw.var(D, k) * FPL + iq);
+#pragma unroll
+                        for (int i = 0; i < FPL; ++i)
+                            if (i == iq) x[i] ^= word;
+                    }
                 }
 #pragma unroll
-                for (int off = G / 2; off >= 1; off >>= 1) x ^= __shfl_xor(x, off);
-                par |= x;
+                for (int i = 0; i < FPL; ++i) {
+#pragma unroll
+                    for (int off = G / 2; off >= 1; off >>= 1) x[i] ^= __shfl_xor(x[i], off);
+                    acc[i] |= x[i];
+                }
             }
 #pragma unroll
-            for (int off = 32; off >= G; off >>= 1) par |= __shfl_xor(par, off);
+            for (int i = 0; i < FPL; ++i) {
+#pragma unroll
+                for (int off = 32; off >= G; off >>= 1) acc[i] |= __shfl_xor(acc[i], off);
+            }
+            par = plan_pick<FPL>(acc, lane);
         }
     }
 #pragma unroll
@@ -364,7 +398,7 @@ __device__ __forceinline__ void plan_vn_body(const PlanCode& C, const PlanStep& 
     if (S.early && rw == 0 && lane < FPL)
         M::st64(C, C.frozen + ((size_t)(S.iter - 1) * C.tiles + tile) * FPL + lane, plan_pick<FPL>(frz, lane));
     if (S.early && all) return;
-    const size_t lane_off = (G == 64) ? (size_t)lane * FPL : (size_t)f;
+    const size_t lane_off = (size_t)f * FPL;   // lane f of its group: frames f*FPL .. f*FPL+FPL-1
     float* mt = C.msg + (size_t)tile * D.E * Gt + lane_off;
     // the wave's variables: base column l (uniform), offsets sw*V*R .. within it
     const int spw = C.vn_wpt / D.L;
@@ -418,20 +452,30 @@ __device__ __forceinline__ void plan_vn_body(const PlanCode& C, const PlanStep& 
                 }
                 if (active[v] && lane < FPL) M::st64(C, bw + lane, mine);
             } else {
-                // bits r*G .. r*G+G-1 of the ballot are the G frames of variable r
+                // bits r*G .. r*G+G-1 of ballot i are the G lanes of variable
+                // r, frames f*FPL + i: word i, bit f; lane f < FPL of the
+                // group stores word f
                 const uint64_t gmask = (1ull << G) - 1ull;
-                uint64_t w = (__ballot(active[v] && L[0] < 0.0f) >> (r * G)) & gmask;
-                if (active[v] && f == 0) {
-                    if (any) w = (w & ~frz[0]) | (M::ld64(C, bw) & frz[0]);
-                    M::st64(C, bw, w);
+                uint64_t mine = 0;
+#pragma unroll
+                for (int i = 0; i < FPL; ++i) {
+                    const uint64_t w = (__ballot(active[v] && L[i] < 0.0f) >> (r * G)) & gmask;
+                    if (f == i) mine = w;
+                }
+                if (active[v] && f < FPL) {
+                    if (any) {
+                        const uint64_t z = plan_pick<FPL>(frz, f);
+                        mine = (mine & ~z) | (M::ld64(C, bw + f) & z);
+                    }
+                    M::st64(C, bw + f, mine);
                 }
             }
             if (active[v]) {
                 float* pw = C.postw + ((size_t)tile * D.n + var[v]) * Gt + lane_off;
 #pragma unroll
                 for (int i = 0; i < FPL; ++i) {
-                    const int bit = (G == 64) ? lane : f;   // frame lane_off + i: word i, bit `bit`
-                    if (!((frz[i] >> bit) & 1ull)) M::stf(C, pw + i, clip30(L[i]));
+                    // frame f*FPL + i: word i, bit f
+                    if (!((frz[i] >> f) & 1ull)) M::stf(C, pw + i, clip30(L[i]));
                 }
             }
         }
@@ -1412,7 +1456,8 @@ ldpc_status ldpc_plan_autotune(ldpc_plan* P, const float* const* llr, float* con
         int keep = start;
         for (int l = 0; l < 192 && status == LDPC_OK; ++l) {
             if (l == start || !layout_allowed(P->graphs[c], l)) continue;
-            if (layout_g(l) > 8 && layout_g(l) / 2 >= P->gammas[c]) continue;   // G at most the next power of two
+            const int tile = layout_g(l) * layout_fpl(l);
+            if (tile > 8 && tile / 2 >= P->gammas[c]) continue;   // tiles at most the next power of two
             P->layouts[c] = l;
             P->table_valid = false;
             double ms = 0.0;

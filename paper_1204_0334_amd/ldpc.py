@@ -30,7 +30,9 @@ _vp, _i32, _i64, _sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c
 OK, EINVAL, EWORKSPACE, EHIP, EUNSUPPORTED, ENOMEM = 0, -1, -2, -3, -4, -5
 GRAPH_QC, GRAPH_CONV = 0, 1
 LAYOUT_G8, LAYOUT_G16, LAYOUT_G32, LAYOUT_G64, LAYOUT_G64F4, LAYOUT_G64F2 = 0, 1, 2, 3, 4, 5
-LAYOUT_NAMES = ["G8", "G16", "G32", "G64", "G64F4", "G64F2"]
+LAYOUT_G8F2, LAYOUT_G8F4, LAYOUT_G16F2, LAYOUT_G16F4, LAYOUT_G32F2, LAYOUT_G32F4 = 6, 7, 8, 9, 10, 11
+LAYOUT_NAMES = ["G8", "G16", "G32", "G64", "G64F4", "G64F2", "G8F2", "G8F4", "G16F2", "G16F4", "G32F2", "G32F4"]
+PLAN_LAYOUTS = len(LAYOUT_NAMES)
 LAYOUT_VN2, LAYOUT_VN4, LAYOUT_CN2, LAYOUT_CN4 = 16, 32, 64, 128
 
 

@@ -312,9 +312,21 @@ def test_plan_creation_and_layout_rules():
     assert ldpc.layout_name(plan.layout(1)) == "G16/VN2/CN4"
     with pytest.raises(ldpc.LdpcError):
         plan.set_layout(6, ldpc.LAYOUT_G64 | ldpc.LAYOUT_CN2)      # 3 x 9: row weight 9
-    for bad in (ldpc.LAYOUT_G64F4 | ldpc.LAYOUT_VN2, ldpc.LAYOUT_G64F4 | ldpc.LAYOUT_CN2, 48, 192, 6, -2):
+    for bad in (ldpc.LAYOUT_G64F4 | ldpc.LAYOUT_VN2, ldpc.LAYOUT_G64F4 | ldpc.LAYOUT_CN2, 48, 192, 12, 15, -2,
+                ldpc.LAYOUT_G16F4 | ldpc.LAYOUT_VN2, ldpc.LAYOUT_G8F2 | ldpc.LAYOUT_CN2):
         with pytest.raises(ldpc.LdpcError):
             plan.set_layout(4, bad)
+    # small groups of lanes with 2 or 4 frames each: the row-weight limits of
+    # 2 and 4 frames per lane
+    for good in (ldpc.LAYOUT_G8F2, ldpc.LAYOUT_G8F4, ldpc.LAYOUT_G16F2, ldpc.LAYOUT_G16F4, ldpc.LAYOUT_G32F2,
+                 ldpc.LAYOUT_G32F4):
+        plan.set_layout(4, good)
+        assert plan.layout(4) == good
+    plan.set_layout(5, ldpc.LAYOUT_G16F2)              # 3 x 9: row weight 9 <= 12
+    with pytest.raises(ldpc.LdpcError):
+        plan.set_layout(5, ldpc.LAYOUT_G16F4)
+    with pytest.raises(ldpc.LdpcError):
+        wide18.set_layout(0, ldpc.LAYOUT_G32F2)        # row weight 18
     plan.set_layout(4, ldpc.LAYOUT_G8)
     assert plan.layout(4) == ldpc.LAYOUT_G8
     plan.set_layout(4, -1)

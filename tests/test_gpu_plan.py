@@ -60,7 +60,7 @@ def test_every_layout_matches_single_code_decoder():
     gammas = [c["gamma"] for c in RAGGED]
     refs = single_code(graphs, llrs, 12, True)
     ws = None
-    for layout in list(range(6)) + [ldpc.LAYOUT_G8 | ldpc.LAYOUT_VN2, ldpc.LAYOUT_G32 | ldpc.LAYOUT_VN4,
+    for layout in list(range(ldpc.PLAN_LAYOUTS)) + [ldpc.LAYOUT_G8 | ldpc.LAYOUT_VN2, ldpc.LAYOUT_G32 | ldpc.LAYOUT_VN4,
                                      ldpc.LAYOUT_G64 | ldpc.LAYOUT_VN2, ldpc.LAYOUT_G64 | ldpc.LAYOUT_VN4,
                                      ldpc.LAYOUT_G8 | ldpc.LAYOUT_CN2, ldpc.LAYOUT_G16 | ldpc.LAYOUT_CN4,
                                      ldpc.LAYOUT_G64 | ldpc.LAYOUT_CN4 | ldpc.LAYOUT_VN4]:
@@ -79,7 +79,8 @@ def test_fixed_iterations_every_layout():
     graphs, llrs = make_case(RAGGED[:5], 3000)
     gammas = [c["gamma"] for c in RAGGED[:5]]
     refs = single_code(graphs, llrs, 3, False)
-    for layout in (0, 2, 3, ldpc.LAYOUT_G64 | ldpc.LAYOUT_VN4, ldpc.LAYOUT_G32 | ldpc.LAYOUT_CN2):
+    for layout in (0, 2, 3, ldpc.LAYOUT_G64 | ldpc.LAYOUT_VN4, ldpc.LAYOUT_G32 | ldpc.LAYOUT_CN2, ldpc.LAYOUT_G8F4,
+                   ldpc.LAYOUT_G16F2, ldpc.LAYOUT_G32F4):
         plan = ldpc.Plan(graphs, gammas, 3, early_stop=False)
         for c in range(len(graphs)):
             try:
@@ -221,8 +222,11 @@ def test_autotune_keeps_results():
     for c, g in enumerate(graphs):
         l = plan.layout(c)
         base = l & 15
-        assert 0 <= base <= 5 and (base != ldpc.LAYOUT_G64F4 or g.info["dc_max"] <= 6)
-        assert base != ldpc.LAYOUT_G64F2 or g.info["dc_max"] <= 12
+        fpl = {ldpc.LAYOUT_G64F4: 4, ldpc.LAYOUT_G8F4: 4, ldpc.LAYOUT_G16F4: 4, ldpc.LAYOUT_G32F4: 4,
+               ldpc.LAYOUT_G64F2: 2, ldpc.LAYOUT_G8F2: 2, ldpc.LAYOUT_G16F2: 2, ldpc.LAYOUT_G32F2: 2}.get(base, 1)
+        assert 0 <= base < ldpc.PLAN_LAYOUTS
+        assert fpl != 4 or g.info["dc_max"] <= 6
+        assert fpl != 2 or g.info["dc_max"] <= 12
         assert (l >> 4) == 0 or base in (0, 1, 2, 3)
         assert (l >> 6) == 0 or g.info["dc_max"] <= 8
     assert_same(plan.decode(llrs, outs=outs, ws=ws), single_code(graphs, llrs, 20, True), "after autotune")
