@@ -1005,33 +1005,63 @@ __global__ void __launch_bounds__(256) nms_loss_reduce_kernel(const float* lpart
 // ---------------------------------------------------------------------------
 
 // src [gamma][ld], columns col0 .. col0+ncols-1  ->  dst[tile*dstride + col*Gt + frame]
-// (frames >= gamma are written as 0).  64 columns x 64 frames per block.
-// Block (0, 0) also clears `zero_count` words at `zero` (flag words of a decode).
-__global__ void __launch_bounds__(256) to_packages_kernel(const float* __restrict__ src, int64_t ld, int64_t col0,
-                                                          int ncols, int gamma, int gpad, int Gt,
-                                                          float* __restrict__ dst, int64_t dstride,
-                                                          uint64_t* __restrict__ zero, int64_t zero_count) {
-    __shared__ float tileS[64][65];
-    const int c0 = blockIdx.x * 64, f0 = blockIdx.y * 64;
-    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-    if (zero && blockIdx.x == 0 && blockIdx.y == 0)
-        for (int64_t i = threadIdx.x; i < zero_count; i += 256) zero[i] = 0ull;
-#pragma unroll 4
-    for (int r = ty; r < 64; r += 4) {
-        const int g = f0 + r, c = c0 + tx;
-        float v = 0.0f;
-        if (g < gamma && c < ncols) v = src[(size_t)g * ld + col0 + c];
-        tileS[r][tx] = v;
-    }
-    __syncthreads();
-#pragma unroll 4
-    for (int r = ty; r < 64; r += 4) {
-        const int c = c0 + r, g = f0 + tx;
-        if (c < ncols && g < gpad) {
-            const int tile = g / Gt, fl = g - tile * Gt;
-            dst[(size_t)tile * dstride + (size_t)c * Gt + fl] = tileS[tx][r];
+// (frames >= gamma are written as 0).  A block of 512 threads covers 256
+// columns x 32 frames (one-dimensional grid, frame chunks fastest): each frame
+// row is read as one 1-KB run (a frame row of n floats is in general not
+// aligned to the 128-byte lines, so short runs fetch the lines they share
+// with the neighbouring block twice), and each column's 32 frames are written
+// as one 128-byte run.  Gt must be a
+// multiple of 32.  Block 0 also clears `zero_count` words at `zero` (flag
+// words of a decode).
+constexpr int kIngCols = 256;
+constexpr int kIngFrames = 32;
+constexpr int kIngBlock = 512;
+
+__global__ void __launch_bounds__(kIngBlock) to_packages_kernel(const float* __restrict__ src, int64_t ld,
+                                                                int64_t col0, int ncols, int gamma, int gpad, int Gt,
+                                                                float* __restrict__ dst, int64_t dstride,
+                                                                uint64_t* __restrict__ zero, int64_t zero_count) {
+    __shared__ float tileS[kIngFrames][kIngCols + 1];
+    constexpr int kWaves = kIngBlock / 64;
+    const int fchunks = (gpad + kIngFrames - 1) / kIngFrames;
+    const int cb = (int)(blockIdx.x / fchunks);
+    const int f0 = (int)(blockIdx.x - (unsigned)cb * fchunks) * kIngFrames, c0 = cb * kIngCols;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (zero && blockIdx.x == 0)
+        for (int64_t i = threadIdx.x; i < zero_count; i += kIngBlock) zero[i] = 0ull;
+    // wave wv reads frame rows wv, wv + 8, ...: 256 consecutive columns each
+#pragma unroll
+    for (int i = 0; i < kIngFrames / kWaves; ++i) {
+        const int r = wv + i * kWaves;
+        const int g = f0 + r;
+#pragma unroll
+        for (int k = 0; k < kIngCols / 64; ++k) {
+            const int c = c0 + lane + 64 * k;
+            float v = 0.0f;
+            if (g < gamma && c < ncols) v = src[(size_t)g * ld + col0 + c];
+            tileS[r][lane + 64 * k] = v;
         }
     }
+    __syncthreads();
+    // lanes 0-31 and 32-63 of a wave write the 32 frames of one column each
+    const int fr = threadIdx.x & (kIngFrames - 1);
+    const int g = f0 + fr;
+    if (g >= gpad) return;
+    const int tile = g / Gt, fl = g - tile * Gt;
+    float* d = dst + (size_t)tile * dstride + fl;
+#pragma unroll
+    for (int j = 0; j < kIngCols * kIngFrames / kIngBlock; ++j) {
+        const int cc = (int)threadIdx.x / kIngFrames + j * (kIngBlock / kIngFrames);
+        const int c = c0 + cc;
+        if (c < ncols) d[(size_t)c * Gt] = tileS[fr][cc];
+    }
+}
+
+// grid of to_packages_kernel for ncols columns and gpad frames: one block per
+// (column chunk, frame chunk), frame chunks fastest
+static dim3 packages_grid(int ncols, int gpad) {
+    const int64_t blocks = (int64_t)((gpad + kIngFrames - 1) / kIngFrames) * ((ncols + kIngCols - 1) / kIngCols);
+    return dim3((unsigned)blocks);
 }
 
 // ---------------------------------------------------------------------------
@@ -1925,8 +1955,8 @@ static void run_block(const ldpc_graph* g, const float* llr, int gamma, int max_
 
     {
         timing::Scope ts(0, st);
-        dim3 grid((g->n + 63) / 64, tl.gpad / 64);
-        to_packages_kernel<<<grid, 256, 0, st>>>(llr, g->n, 0, g->n, gamma, tl.gpad, tl.gt,
+        const dim3 grid = packages_grid(g->n, tl.gpad);
+        to_packages_kernel<<<grid, kIngBlock, 0, st>>>(llr, g->n, 0, g->n, gamma, tl.gpad, tl.gt,
                                                  reinterpret_cast<float*>(ws + lay.mu), (int64_t)g->n * tl.gt,
                                                  P.unsat, (int64_t)(2 * lay.flag_words));
     }
@@ -2073,8 +2103,8 @@ template <int FPL>
 static void train_forward(TrainRun& r, const float* llr, float* loss) {
     {
         timing::Scope ts(0, r.st);
-        dim3 grid((r.g->n + 63) / 64, r.tl.gpad / 64);
-        to_packages_kernel<<<grid, 256, 0, r.st>>>(llr, r.g->n, 0, r.g->n, r.P.gamma, r.tl.gpad, r.tl.gt,
+        const dim3 grid = packages_grid(r.g->n, r.tl.gpad);
+        to_packages_kernel<<<grid, kIngBlock, 0, r.st>>>(llr, r.g->n, 0, r.g->n, r.P.gamma, r.tl.gpad, r.tl.gt,
                                                    reinterpret_cast<float*>(r.ws + r.L.mu),
                                                    (int64_t)r.g->n * r.tl.gt, nullptr, 0);
     }
