@@ -63,8 +63,8 @@ struct PlanCode {
     QCDesc D;
     float* mu;            // [tiles][n][Gt]
     float* msg;           // [tiles][E][Gt]
-    float* postw;         // [tiles][n][Gt]: posterior of the returned iteration
-    uint64_t* bits;       // [tiles][n][FPL] packed decisions
+    float* postw;         // [2][tiles][n][Gt]: posteriors, slot = iteration & 1
+    uint64_t* bits;       // [2][tiles][n][FPL] packed decisions, slot = iteration & 1
     uint64_t* unsat;      // [max_iters+1][tiles][FPL]
     uint64_t* frozen;     // [max_iters+1][tiles][FPL]
     const float* llr;     // caller, [gamma][n]
@@ -81,7 +81,10 @@ struct PlanCode {
     int64_t io0;          // first block in the ingest / output launches
     int vpw;              // variable-node launch: groups of R variables per wave (1, 2 or 4)
     int cpw;              // check-node launch: groups of R rows per wave (1, 2 or 4)
-    uint64_t* badw;       // early stopping: [tiles * cn_wpt][FPL] frames violating each check wave's rows
+    uint64_t* badw;       // early stopping: [2][tiles * cn_wpt][FPL] frames violating each check wave's
+                          // rows, slot = (iteration of the decisions tested) & 1
+    uint32_t* slot;       // [gamma]: slot holding each frame's returned iteration
+    int64_t bits_slot, postw_slot, badw_slot;   // elements per slot
     int64_t red0;         // first block in the flag-reduction launch (red_chunks blocks per tile)
     int red_chunks;       // blocks per tile in the flag-reduction launch
     char* region;         // start of the code's workspace region (mu .. badw lie inside it)
@@ -107,6 +110,8 @@ struct PlainMem {
     static __device__ __forceinline__ void st64(const PlanCode&, uint64_t* p, uint64_t v) { *p = v; }
     static __device__ __forceinline__ float ldf(const PlanCode&, const float* p) { return *p; }
     static __device__ __forceinline__ void stf(const PlanCode&, float* p, float v) { *p = v; }
+    static __device__ __forceinline__ uint32_t ld32(const PlanCode&, const uint32_t* p) { return *p; }
+    static __device__ __forceinline__ void st32(const PlanCode&, uint32_t* p, uint32_t v) { *p = v; }
 };
 
 struct CoherentMem {
@@ -156,6 +161,12 @@ struct CoherentMem {
     }
     static __device__ __forceinline__ void stf(const PlanCode& C, float* p, float v) {
         __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), rsrc(C), off(C, p), 0, kSc1);
+    }
+    static __device__ __forceinline__ uint32_t ld32(const PlanCode& C, const uint32_t* p) {
+        return __builtin_amdgcn_raw_buffer_load_b32(rsrc(C), off(C, p), 0, kSc1);
+    }
+    static __device__ __forceinline__ void st32(const PlanCode& C, uint32_t* p, uint32_t v) {
+        __builtin_amdgcn_raw_buffer_store_b32(v, rsrc(C), off(C, p), 0, kSc1);
     }
 };
 
@@ -255,9 +266,12 @@ __device__ __forceinline__ uint64_t plan_pick(const uint64_t (&a)[FPL], int i) {
 
 // Check-node pass of iteration S.iter for wave lw of code C (in place; the
 // first iteration gathers the channel LLRs).  With early stopping it first
-// skips tiles frozen by iteration iter-2 and ORs the syndrome of iteration
-// iter-1's decisions into unsat[iter-1]; the decision words are loaded right
-// after the messages and the flag update comes after the stores.
+// skips tiles whose frames had all stopped by iteration iter-3 (the last
+// iteration the variable pass before it knew of), and tests the rows against
+// iteration iter-1's decisions (slot (iter-1) & 1), storing the violated
+// frames in the wave's words of badw slot (iter-1) & 1; the decision words
+// are loaded right after the messages and the flag stores come after the
+// message stores.
 template <int DCMAX, int G, int FPL, int V, class M>
 __device__ __forceinline__ void plan_cn_body(const PlanCode& C, const PlanStep& S, int64_t lw, int lane) {
     constexpr int R = 64 / G;
@@ -267,8 +281,8 @@ __device__ __forceinline__ void plan_cn_body(const PlanCode& C, const PlanStep& 
     const int rw = (int)(lw - (int64_t)tile * C.cn_wpt);
     const int r = lane / G, f = lane % G;
     const int nvalid = min(C.gamma - tile * Gt, Gt);
-    if (S.early && S.iter >= 3) {
-        const uint64_t* fz = C.frozen + ((size_t)(S.iter - 2) * C.tiles + tile) * FPL;
+    if (S.early && S.iter >= 4) {
+        const uint64_t* fz = C.frozen + ((size_t)(S.iter - 3) * C.tiles + tile) * FPL;
         bool all = true;
 #pragma unroll
         for (int i = 0; i < FPL; ++i) all = all && (M::ld64(C, fz + i) == ~0ull);
@@ -305,7 +319,7 @@ __device__ __forceinline__ void plan_cn_body(const PlanCode& C, const PlanStep& 
     const bool syn = S.early && S.iter >= 2;
     uint64_t par = 0;
     if (syn) {
-        const uint64_t* bt = C.bits + (size_t)tile * D.n * FPL;
+        const uint64_t* bt = C.bits + ((S.iter - 1) & 1) * C.bits_slot + (size_t)tile * D.n * FPL;
         if constexpr (G == 64 && FPL > 1) {
             // lane k*FPL + f: word f of variable k; lane f ends with parity word f
             const int kk = lane / FPL, ff = lane - kk * FPL;
@@ -363,15 +377,21 @@ __device__ __forceinline__ void plan_cn_body(const PlanCode& C, const PlanStep& 
             if (k < d[v]) M::template st<FPL>(C, mt + (size_t)Rw.pkg(D, k) * Gt, out[k]);
     }
     // the wave's violated frames go to its own words (plain stores; the flag
-    // word of the tile is formed by plan_unsat_kernel)
-    if (syn && lane < FPL) M::st64(C, C.badw + lw * FPL + lane, par & valid_word<FPL>(nvalid, lane));
+    // word of the tile is formed by the flag reduction of the next check launch)
+    if (syn && lane < FPL)
+        M::st64(C, C.badw + ((S.iter - 1) & 1) * C.badw_slot + lw * FPL + lane, par & valid_word<FPL>(nvalid, lane));
 }
 
 // Variable-node pass of iteration S.iter for wave lw of code C: betas (not
 // after the last iteration), and with early stopping or at the last
-// iteration the packed decisions and the posterior of the frames still
-// running (frozen frames keep theirs).  A wave handles V groups of R
-// variables; all their loads are issued before the first result is stored.
+// iteration the packed decisions and the posterior, into slot iter & 1, of
+// every frame not known to have stopped.  With early stopping the pass knows
+// the stops up to iteration iter-2 (unsat[iter-2] is formed by the flag
+// reduction inside this iteration's check launch): a frame that stopped at
+// iter-1 is updated once more, into the other slot, and its returned slot
+// (iter-1) & 1 is left alone from iteration iter+1 on.  A wave handles V
+// groups of R variables; all their loads are issued before the first result
+// is stored.
 template <int DVMAX, int G, int FPL, int V, class M>
 __device__ __forceinline__ void plan_vn_body(const PlanCode& C, const PlanStep& S, int64_t lw, int lane) {
     constexpr int R = 64 / G;
@@ -381,22 +401,22 @@ __device__ __forceinline__ void plan_vn_body(const PlanCode& C, const PlanStep& 
     const int rw = (int)(lw - (int64_t)tile * C.vn_wpt);
     const int r = lane / G, f = lane % G;
     const int nvalid = min(C.gamma - tile * Gt, Gt);
-    // frames frozen before this iteration (padding frames count as frozen)
+    // frames that stopped by iteration iter-2 (padding frames count as stopped)
     uint64_t frz[FPL];
     bool any = false, all = true;
 #pragma unroll
     for (int i = 0; i < FPL; ++i) {
         uint64_t z = ~valid_word<FPL>(nvalid, i);
-        if (S.early && S.iter >= 2) {
-            z |= M::ld64(C, C.frozen + ((size_t)(S.iter - 2) * C.tiles + tile) * FPL + i) |
-                 ~M::ld64(C, C.unsat + ((size_t)(S.iter - 1) * C.tiles + tile) * FPL + i);
+        if (S.early && S.iter >= 3) {
+            z |= M::ld64(C, C.frozen + ((size_t)(S.iter - 3) * C.tiles + tile) * FPL + i) |
+                 ~M::ld64(C, C.unsat + ((size_t)(S.iter - 2) * C.tiles + tile) * FPL + i);
         }
         frz[i] = z;
         any = any || (z & valid_word<FPL>(nvalid, i)) != 0;
         all = all && (z == ~0ull);
     }
-    if (S.early && rw == 0 && lane < FPL)
-        M::st64(C, C.frozen + ((size_t)(S.iter - 1) * C.tiles + tile) * FPL + lane, plan_pick<FPL>(frz, lane));
+    if (S.early && S.iter >= 3 && rw == 0 && lane < FPL)
+        M::st64(C, C.frozen + ((size_t)(S.iter - 2) * C.tiles + tile) * FPL + lane, plan_pick<FPL>(frz, lane));
     if (S.early && all) return;
     const size_t lane_off = (size_t)f * FPL;   // lane f of its group: frames f*FPL .. f*FPL+FPL-1
     float* mt = C.msg + (size_t)tile * D.E * Gt + lane_off;
@@ -440,7 +460,7 @@ __device__ __forceinline__ void plan_vn_body(const PlanCode& C, const PlanStep& 
                 if (k < dv[v]) M::template st<FPL>(C, mt + (size_t)Cc.pkg(D, k) * Gt, b[k]);
         }
         if (S.early || S.last) {
-            uint64_t* bw = C.bits + ((size_t)tile * D.n + (active[v] ? var[v] : 0)) * FPL;
+            uint64_t* bw = C.bits + (S.iter & 1) * C.bits_slot + ((size_t)tile * D.n + (active[v] ? var[v] : 0)) * FPL;
             if constexpr (G == 64) {
                 // word i, bit j <-> frame FPL * j + i
                 uint64_t mine = 0;
@@ -471,7 +491,7 @@ __device__ __forceinline__ void plan_vn_body(const PlanCode& C, const PlanStep& 
                 }
             }
             if (active[v]) {
-                float* pw = C.postw + ((size_t)tile * D.n + var[v]) * Gt + lane_off;
+                float* pw = C.postw + (S.iter & 1) * C.postw_slot + ((size_t)tile * D.n + var[v]) * Gt + lane_off;
 #pragma unroll
                 for (int i = 0; i < FPL; ++i) {
                     // frame f*FPL + i: word i, bit f
@@ -479,6 +499,54 @@ __device__ __forceinline__ void plan_vn_body(const PlanCode& C, const PlanStep& 
                 }
             }
         }
+    }
+}
+
+// unsat[r][tile] |= OR of the tile's check-wave words of iteration r (badw
+// slot r & 1, written by the check launch of iteration r + 1).  Block (code,
+// tile, chunk) reads kPlanRedWords consecutive words of the tile (wave w,
+// word i at w*fpl + i), kPlanRedPerThread independent loads per thread; 256
+// and kPlanRedWords are multiples of fpl, so a thread only meets words of
+// i = threadIdx.x % fpl.  The flag words are cleared at ingest and each block
+// adds its nonzero words with one atomicOr per i; a tile whose frames had
+// all stopped by iteration r-2 skipped that check pass and keeps its zero
+// word.  The blocks run inside the check launch of iteration r + 2 (and,
+// for r = max_iters - 1, before the final syndrome): no launch of their own.
+constexpr int kPlanRedPerThread = 8;
+constexpr int kPlanRedWords = 256 * kPlanRedPerThread;
+
+// Block b of code C's flag reduction of iteration r (256 threads; every
+// early return is uniform over the block).
+template <class M>
+__device__ __forceinline__ void plan_unsat_block(const PlanCode& C, int r, int64_t b, uint64_t (&part)[4][4]) {
+    const int tile = (int)(b / C.red_chunks);
+    const int chunk = (int)(b - (int64_t)tile * C.red_chunks);
+    if (tile >= C.tiles) return;
+    const int fpl = C.fpl;
+    if (r >= 3) {
+        const uint64_t* fz = C.frozen + ((size_t)(r - 2) * C.tiles + tile) * fpl;
+        bool all = true;
+        for (int i = 0; i < fpl; ++i) all = all && (M::ld64(C, fz + i) == ~0ull);
+        if (all) return;
+    }
+    const int64_t nw = (int64_t)C.cn_wpt * fpl;
+    const uint64_t* bw = C.badw + (r & 1) * C.badw_slot + (size_t)tile * nw;
+    const int64_t w0 = (int64_t)chunk * kPlanRedWords + threadIdx.x;
+    uint64_t acc = 0;
+#pragma unroll
+    for (int k = 0; k < kPlanRedPerThread; ++k) {
+        const int64_t w = w0 + (int64_t)k * 256;
+        if (w < nw) acc |= M::ld64(C, bw + w);
+    }
+    for (int off = 32; off >= fpl; off >>= 1) acc |= __shfl_xor(acc, off);
+    const int lane = threadIdx.x & 63;
+    if (lane < fpl) part[threadIdx.x >> 6][lane] = acc;
+    __syncthreads();
+    if ((int)threadIdx.x < fpl) {
+        const int i = threadIdx.x;
+        const uint64_t v = part[0][i] | part[1][i] | part[2][i] | part[3][i];
+        if (v) atomicOr((unsigned long long*)(C.unsat + ((size_t)r * C.tiles + tile) * fpl + i),
+                        (unsigned long long)v);
     }
 }
 
@@ -518,8 +586,18 @@ __device__ __forceinline__ void plan_vn_wave(const PlanCode& C, const PlanStep& 
     }
 }
 
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) plan_cn_kernel(const PlanCode* __restrict__ codes, int ncodes,
-                                                         PlanStep S) {
+// Check-node launch of iteration S.iter: blocks below cn_blocks run the
+// check waves of every code; with early stopping from iteration 3 on, the
+// blocks after them reduce the check words of iteration S.iter - 2.
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4)))
+plan_cn_kernel(const PlanCode* __restrict__ codes, int ncodes, PlanStep S, int64_t cn_blocks) {
+    if ((int64_t)blockIdx.x >= cn_blocks) {
+        __shared__ uint64_t part[4][4];
+        const int64_t b = (int64_t)blockIdx.x - cn_blocks;
+        const PlanCode& C = codes[plan_find(codes, ncodes, b, &PlanCode::red0)];
+        plan_unsat_block<PlainMem>(C, S.iter - 2, b - C.red0, part);
+        return;
+    }
     const int lane = threadIdx.x & 63;
     const int64_t wave = (int64_t)blockIdx.x * kWavesPerBlock + wave_in_block();
     const PlanCode& C = codes[plan_find(codes, ncodes, wave, &PlanCode::cn0)];
@@ -541,57 +619,13 @@ plan_vn_kernel(const PlanCode* __restrict__ codes, int ncodes, PlanStep S) {
     plan_vn_wave<PlainMem>(C, S, lw, lane);
 }
 
-// unsat[iter-1][tile] |= OR of the tile's check-wave words.  Block (code,
-// tile, chunk) reads kPlanRedWords consecutive words of the tile (wave w,
-// word i at w*fpl + i), kPlanRedPerThread independent loads per thread; 256
-// and kPlanRedWords are multiples of fpl, so a thread only meets words of
-// i = threadIdx.x % fpl.  The flag words are cleared at ingest and each block
-// adds its nonzero words with one atomicOr per i; a tile frozen by iteration
-// iter-2 skipped its check pass and keeps its zero word.
-constexpr int kPlanRedPerThread = 8;
-constexpr int kPlanRedWords = 256 * kPlanRedPerThread;
-
-// Block b of code C's flag reduction (256 threads; every early return is
-// uniform over the block).
-template <class M>
-__device__ __forceinline__ void plan_unsat_block(const PlanCode& C, const PlanStep& S, int64_t b,
-                                                 uint64_t (&part)[4][4]) {
-    const int tile = (int)(b / C.red_chunks);
-    const int chunk = (int)(b - (int64_t)tile * C.red_chunks);
-    if (tile >= C.tiles) return;
-    const int fpl = C.fpl;
-    if (S.iter >= 3) {
-        const uint64_t* fz = C.frozen + ((size_t)(S.iter - 2) * C.tiles + tile) * fpl;
-        bool all = true;
-        for (int i = 0; i < fpl; ++i) all = all && (M::ld64(C, fz + i) == ~0ull);
-        if (all) return;
-    }
-    const int64_t nw = (int64_t)C.cn_wpt * fpl;
-    const uint64_t* bw = C.badw + (size_t)tile * nw;
-    const int64_t w0 = (int64_t)chunk * kPlanRedWords + threadIdx.x;
-    uint64_t acc = 0;
-#pragma unroll
-    for (int k = 0; k < kPlanRedPerThread; ++k) {
-        const int64_t w = w0 + (int64_t)k * 256;
-        if (w < nw) acc |= M::ld64(C, bw + w);
-    }
-    for (int off = 32; off >= fpl; off >>= 1) acc |= __shfl_xor(acc, off);
-    const int lane = threadIdx.x & 63;
-    if (lane < fpl) part[threadIdx.x >> 6][lane] = acc;
-    __syncthreads();
-    if ((int)threadIdx.x < fpl) {
-        const int i = threadIdx.x;
-        const uint64_t v = part[0][i] | part[1][i] | part[2][i] | part[3][i];
-        if (v) atomicOr((unsigned long long*)(C.unsat + ((size_t)(S.iter - 1) * C.tiles + tile) * fpl + i),
-                        (unsigned long long)v);
-    }
-}
-
+// The flag reduction of iteration r = S.iter on its own (the last check
+// words, those of iteration max_iters - 1, after the last check launch).
 __global__ void __launch_bounds__(256) plan_unsat_kernel(const PlanCode* __restrict__ codes, int ncodes,
                                                          PlanStep S) {
     __shared__ uint64_t part[4][4];
     const PlanCode& C = codes[plan_find(codes, ncodes, blockIdx.x, &PlanCode::red0)];
-    plan_unsat_block<PlainMem>(C, S, blockIdx.x - C.red0, part);
+    plan_unsat_block<PlainMem>(C, S.iter, blockIdx.x - C.red0, part);
 }
 
 // Syndrome of the final decisions into unsat[max_iters]: one thread per
@@ -609,7 +643,7 @@ __device__ __forceinline__ void plan_syndrome_body(const PlanCode& C, const Plan
     for (int i = 0; i < FPL; ++i) par[i] = 0;
     if (live) {
         const QCRow Rw(D, row);
-        const uint64_t* bt = C.bits + (size_t)tile * D.n * FPL;
+        const uint64_t* bt = C.bits + (S.max_iters & 1) * C.bits_slot + (size_t)tile * D.n * FPL;
         for (int k = 0; k < Rw.d; ++k) {
             const uint64_t* w = bt + (size_t)Rw.var(D, k) * FPL;
 #pragma unroll
@@ -660,7 +694,7 @@ __global__ void __launch_bounds__(kBlock) plan_syndrome_kernel(const PlanCode* _
 // of code C).
 template <class M>
 __device__ __forceinline__ void plan_status_thread(const PlanCode& C, const PlanStep& S, int64_t g) {
-    if (g >= C.gamma || (!C.iters && !C.converged)) return;
+    if (g >= C.gamma) return;
     const int tile = (int)(g / C.Gt), fl = (int)(g - (int64_t)tile * C.Gt);
     const int w = fl % C.fpl, bit = fl / C.fpl;
     int it = S.max_iters, ok = 0;
@@ -677,6 +711,7 @@ __device__ __forceinline__ void plan_status_thread(const PlanCode& C, const Plan
     }
     if (C.iters) C.iters[g] = it;
     if (C.converged) C.converged[g] = (uint8_t)ok;
+    M::st32(C, C.slot + g, (uint32_t)(it & 1));   // the slot that holds iteration `it`
 }
 
 __global__ void __launch_bounds__(kBlock) plan_status_kernel(const PlanCode* __restrict__ codes, int ncodes,
@@ -728,12 +763,16 @@ __device__ __forceinline__ void plan_output_block(const PlanCode& C, int64_t b, 
     const int n = C.D.n, Gt = C.Gt, fpl = C.fpl;
     const int c0 = (int)(b % C.io_vchunks) * 64, f0 = (int)(b / C.io_vchunks) * 64;
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    const int gf = f0 + tx;
+    const uint32_t sl = gf < C.gamma ? M::ld32(C, C.slot + gf) : 0u;   // this thread's frame's slot
+    const float* pw = C.postw + sl * C.postw_slot;
+    const uint64_t* bw = C.bits + sl * C.bits_slot;
     for (int r = ty; r < 64; r += 4) {           // r: variable, tx: frame
         const int c = c0 + r, g = f0 + tx;
         if (c < n && g < C.gamma) {
             const int tile = g / Gt, fl = g - tile * Gt;
-            Ps[r][tx] = M::ldf(C, C.postw + ((size_t)tile * n + c) * Gt + fl);
-            const uint64_t w = M::ld64(C, C.bits + ((size_t)tile * n + c) * fpl + fl % fpl);
+            Ps[r][tx] = M::ldf(C, pw + ((size_t)tile * n + c) * Gt + fl);
+            const uint64_t w = M::ld64(C, bw + ((size_t)tile * n + c) * fpl + fl % fpl);
             Bs[r][tx] = (uint8_t)((w >> (fl / fpl)) & 1ull);
         }
     }
@@ -924,8 +963,8 @@ plan_persistent_kernel(const PlanCode* __restrict__ codes, PersistState* st, Per
                     break;
                 }
                 case kKindUnsat:
-                    if (A.early && iter >= 2) {
-                        plan_unsat_block<CoherentMem>(C, S, it, part);
+                    if (A.early && iter >= 3) {
+                        plan_unsat_block<CoherentMem>(C, iter - 2, it, part);
                         __syncthreads();
                     }
                     break;
@@ -934,9 +973,17 @@ plan_persistent_kernel(const PlanCode* __restrict__ codes, PersistState* st, Per
                     if (lw < (int64_t)C.tiles * C.vn_wpt) plan_vn_wave<CoherentMem>(C, S, lw, lane);
                     break;
                 }
-                case kKindSyn:
-                    plan_syndrome_thread<CoherentMem>(C, S, it * kBlock + threadIdx.x, lane);
+                case kKindSyn: {
+                    // first the flag reduction of iteration max_iters - 1, then the final syndrome
+                    const int64_t nred = (A.early && A.max_iters >= 2) ? (int64_t)C.tiles * C.red_chunks : 0;
+                    if (it < nred) {
+                        plan_unsat_block<CoherentMem>(C, A.max_iters - 1, it, part);
+                        __syncthreads();
+                    } else {
+                        plan_syndrome_thread<CoherentMem>(C, S, (it - nred) * kBlock + threadIdx.x, lane);
+                    }
                     break;
+                }
                 case kKindStatus:
                     plan_status_thread<CoherentMem>(C, S, it * kBlock + threadIdx.x);
                     break;
@@ -1007,7 +1054,8 @@ bool layout_allowed(const ldpc_graph* g, int l) {
 struct CodeRegion {
     int tiles, Gt, cn_wpt;
     int64_t flag_words;
-    size_t mu, msg, postw, bits, flags, badw, total;
+    size_t mu, msg, postw, bits, flags, badw, slot, total;
+    int64_t bits_slot, postw_slot, badw_slot;   // elements per slot (two slots each)
 };
 
 // check-node waves per tile: per base row, enough waves for its p rows
@@ -1024,13 +1072,17 @@ CodeRegion code_region(const ldpc_graph* g, int gamma, int layout, int max_iters
     R.flag_words = (int64_t)(max_iters + 1) * R.tiles * layout_fpl(layout);
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
+    R.postw_slot = (int64_t)gpad * g->n;
+    R.bits_slot = (int64_t)R.tiles * g->n * layout_fpl(layout);
+    R.cn_wpt = plan_cn_wpt(g, layout);
+    R.badw_slot = (int64_t)R.tiles * R.cn_wpt * layout_fpl(layout);
     R.mu = take(gpad * g->n * sizeof(float));
     R.msg = take(gpad * g->E * sizeof(float));
-    R.postw = take(gpad * g->n * sizeof(float));
-    R.bits = take((size_t)R.tiles * g->n * layout_fpl(layout) * sizeof(uint64_t));
+    R.postw = take(2 * (size_t)R.postw_slot * sizeof(float));
+    R.bits = take(2 * (size_t)R.bits_slot * sizeof(uint64_t));
     R.flags = take(2 * (size_t)R.flag_words * sizeof(uint64_t));
-    R.cn_wpt = plan_cn_wpt(g, layout);
-    R.badw = take((size_t)R.tiles * R.cn_wpt * layout_fpl(layout) * sizeof(uint64_t));
+    R.badw = take(2 * (size_t)R.badw_slot * sizeof(uint64_t));
+    R.slot = take(gpad * sizeof(uint32_t));
     R.total = off;
     return R;
 }
@@ -1124,6 +1176,10 @@ void build_table(ldpc_plan* P, const PlanBuffers& B, char* ws) {
         T.bits = reinterpret_cast<uint64_t*>(base + R.bits);
         T.unsat = reinterpret_cast<uint64_t*>(base + R.flags);
         T.badw = reinterpret_cast<uint64_t*>(base + R.badw);
+        T.slot = reinterpret_cast<uint32_t*>(base + R.slot);
+        T.bits_slot = R.bits_slot;
+        T.postw_slot = R.postw_slot;
+        T.badw_slot = R.badw_slot;
         T.frozen = T.unsat + R.flag_words;
         T.region = base;
         T.llr = B.llr[c];
@@ -1177,7 +1233,8 @@ void build_table(ldpc_plan* P, const PlanBuffers& B, char* ws) {
                                        ((int64_t)T.tiles * T.cn_wpt + kWavesPerBlock - 1) / kWavesPerBlock,
                                        P->early ? (int64_t)T.tiles * T.red_chunks : 0,
                                        ((int64_t)T.tiles * T.vn_wpt + kWavesPerBlock - 1) / kWavesPerBlock,
-                                       ((int64_t)T.tiles * g->m + kBlock - 1) / kBlock,
+                                       ((int64_t)T.tiles * g->m + kBlock - 1) / kBlock +
+                                           (P->early && P->max_iters >= 2 ? (int64_t)T.tiles * T.red_chunks : 0),
                                        ((int64_t)T.gamma + kBlock - 1) / kBlock,
                                        io};
         for (int k = 0; k < kKinds; ++k) {
@@ -1255,20 +1312,23 @@ void enqueue(ldpc_plan* P, char* ws, hipStream_t st) {
         S.iter = it;
         S.last = it == P->max_iters;
         {
+            // with early stopping the check launch also reduces the check
+            // words of iteration it - 2 (blocks after the check waves)
             timing::Scope ts(18, st);
-            plan_cn_kernel<<<cn_grid, kBlock, 0, st>>>(T, nc, S);
-        }
-        if (P->early && it >= 2) {
-            timing::Scope ts(20, st);
-            plan_unsat_kernel<<<(unsigned)P->red_blocks, 256, 0, st>>>(T, nc, S);
+            const unsigned red = (P->early && it >= 3) ? (unsigned)P->red_blocks : 0u;
+            plan_cn_kernel<<<cn_grid + red, kBlock, 0, st>>>(T, nc, S, (int64_t)cn_grid);
         }
         {
             timing::Scope ts(19, st);
             plan_vn_kernel<<<vn_grid, kBlock, 0, st>>>(T, nc, S);
         }
     }
-    S.iter = P->max_iters;
     timing::Scope ts(20, st);
+    if (P->early && P->max_iters >= 2) {
+        S.iter = P->max_iters - 1;   // the check words of the last-but-one iteration
+        plan_unsat_kernel<<<(unsigned)P->red_blocks, 256, 0, st>>>(T, nc, S);
+    }
+    S.iter = P->max_iters;
     plan_syndrome_kernel<<<blocks_for(P->syn_threads, kBlock), kBlock, 0, st>>>(T, nc, S);
     plan_status_kernel<<<blocks_for(P->st_threads, kBlock), kBlock, 0, st>>>(T, nc, S);
     plan_output_kernel<<<(unsigned)P->io_blocks, 256, 0, st>>>(T, nc);
