@@ -7,11 +7,16 @@ codewords over BPSK/AWGN at 1.5 dB, FP32 messages.  Inputs are resident in
 device memory before timing starts.
 
 Prints one JSON line: coded Mbit/s (1024 * 18360 bits per step, from the
-timed region of K decodes), the roofline of the dominant kernel (algorithmic
-bytes / average launch time, from HIP events recorded around every launch
-while the same K decodes run again right after the timed region; the events
-are kept out of the timed region because they add gaps between kernels), and
-the FP64 reference decoder timed on the host cores on a bounded sample.
+timed region of K decodes), the roofline of the dominant kernel (from HIP
+events recorded around every launch while the same K decodes run again
+right after the timed region; the events are kept out of the timed region
+because they add gaps between kernels), and the FP64 reference decoder timed
+on the host cores on a bounded sample.  ldpc_decode runs this code on the
+decoder that keeps each frame on one compute unit (one launch per decode,
+bound by the FP32 vector ALUs: its roofline is algorithmic issue slots over
+the launch time); the message-package decoder (edge messages through HBM,
+bound by HBM bandwidth: algorithmic bytes over the launch time) is timed on
+the same frames and reported beside it.
 """
 from __future__ import annotations
 
@@ -99,6 +104,10 @@ def window_algorithmic_bytes(info, W: int, gamma: int):
 # two partial sums, mu + sum and the clip = 4.
 CN_EDGE_SLOTS = 36
 VN_EDGE_SLOTS = 4
+# The block decoder that keeps a frame on one compute unit forms Eq. 4 and 5
+# as L = mu + sum alpha (one addition per edge) and beta = clip(L - alpha)
+# (a subtraction and the clip per edge): 3 slots per variable edge.
+ONCHIP_VN_EDGE_SLOTS = 3
 # non-packed FP32 vector issue rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
 ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 
@@ -764,9 +773,11 @@ def early_stop_sweep(g, gamma, iters, points, steps=5):
 
 
 def gamma_control(g, llr_dev, iters, gamma, steps=5):
-    """The benchmark decode at a larger batch whose working set exceeds the
-    256 MB Infinity Cache (frames repeated from the benchmark batch), with the
-    roofline of its variable-node pass: the HBM-resident figure."""
+    """The benchmark decode at a larger batch (frames repeated from the
+    benchmark batch) on the decoder ldpc_decode currently selects.  For the
+    message-package decoder its working set exceeds the 256 MB Infinity
+    Cache, and the roofline of its variable-node pass is the HBM-resident
+    figure."""
     import torch
 
     from paper_1204_0334_amd import ldpc
@@ -791,16 +802,87 @@ def gamma_control(g, llr_dev, iters, gamma, steps=5):
     ldpc.timing_enable(False)
     per_kernel = ldpc.timing_read()
     del out, ws, x
-    algo = algorithmic_bytes(g.n, g.info["E"], gamma)["variable_node"]
-    launches, kms = per_kernel["variable_node"]
-    avg_s = kms / launches * 1e-3
-    achieved = algo / avg_s / 1e9
-    roof = {"kernel": "variable_node", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "avg_launch_us": round(avg_s * 1e6, 2),
-            "algorithmic_bytes_per_launch": algo,
-            "traffic": measured_traffic("variable_node", TRAFFIC_FILE_4096)}
+    if per_kernel["onchip_decode"][0]:
+        roof = onchip_roofline(per_kernel, g.info["E"], iters, gamma)
+    else:
+        algo = algorithmic_bytes(g.n, g.info["E"], gamma)["variable_node"]
+        launches, kms = per_kernel["variable_node"]
+        avg_s = kms / launches * 1e-3
+        achieved = algo / avg_s / 1e9
+        roof = {"kernel": "variable_node", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "avg_launch_us": round(avg_s * 1e6, 2),
+                "algorithmic_bytes_per_launch": algo,
+                "traffic": measured_traffic("variable_node", TRAFFIC_FILE_4096)}
     return {"gamma": gamma, "ms_per_step": round(ms, 4), "coded_mbps": round(gamma * g.n / (ms * 1e-3) / 1e6, 1),
             "roofline": roof}
+
+
+def onchip_roofline(per_kernel, E: int, iters: int, gamma: int):
+    """ALU roofline of the block decoder that keeps each frame on one compute
+    unit (one launch per decode, no message traffic to HBM): FP32 vector issue
+    slots of Eq. 3-5 per launch (check edge 36, variable edge 3, every edge,
+    every iteration, every frame) over the launch time, against the
+    non-packed FP32 vector issue rate."""
+    launches, ms = per_kernel["onchip_decode"]
+    avg_s = ms / launches * 1e-3
+    ops = iters * E * (CN_EDGE_SLOTS + ONCHIP_VN_EDGE_SLOTS) * gamma
+    achieved = ops / avg_s / 1e12
+    return {"bound": "alu", "achieved": round(achieved, 2), "peak": round(ALU_PEAK_TOPS, 2), "unit": "Top/s",
+            "frac": round(achieved / ALU_PEAK_TOPS, 4), "traffic": None, "kernel": "onchip_decode",
+            "avg_launch_us": round(avg_s * 1e6, 2), "algorithmic_ops_per_launch": ops,
+            "note": "FP32 vector issue slots (transcendentals count 4) against the non-packed FP32 vector "
+                    "rate; each frame's messages stay in registers and LDS of one compute unit"}
+
+
+def package_roofline(per_kernel, n: int, E: int, gamma: int):
+    """HBM roofline of the message-package decoder's dominant kernel."""
+    algo = algorithmic_bytes(n, E, gamma)
+    dom = max(algo, key=lambda k: per_kernel[k][1])
+    launches, ms = per_kernel[dom]
+    avg_s = ms / launches * 1e-3
+    achieved = algo[dom] / avg_s / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom), "kernel": dom,
+            "avg_launch_us": round(avg_s * 1e6, 2), "algorithmic_bytes_per_launch": algo[dom]}
+
+
+def time_block_decode(g, llr, iters, gamma, steps, warmup):
+    """K whole fixed-iteration decodes timed with one event pair (nothing else
+    enqueued in between), then the same K decodes again with a HIP event pair
+    around every kernel launch on the decode stream (per-kernel averages)."""
+    import torch
+
+    from paper_1204_0334_amd import ldpc
+    dev = llr.device
+    n = g.n
+    out = (torch.empty((gamma, n), dtype=torch.float32, device=dev),
+           torch.empty((gamma, n), dtype=torch.uint8, device=dev),
+           torch.empty((gamma,), dtype=torch.int32, device=dev),
+           torch.empty((gamma,), dtype=torch.uint8, device=dev))
+    ws = ldpc.workspace(g, gamma, iters, 0, dev)
+
+    def step():
+        ldpc.decode(g, llr, iters, early_stop=False, out=out, ws=ws)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(steps):
+        step()
+    stop.record()
+    torch.cuda.synchronize()
+    ms_per_step = start.elapsed_time(stop) / steps
+    ldpc.timing_read()
+    ldpc.timing_enable(True)
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    ldpc.timing_enable(False)
+    per_kernel = ldpc.timing_read()
+    conv_rate = float(out[3].float().mean().item())
+    return ms_per_step, per_kernel, conv_rate
 
 
 def main():
@@ -894,53 +976,29 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     llr = torch.from_numpy(llr_h).to(dev)
-    post = torch.empty((gamma, n), dtype=torch.float32, device=dev)
-    bits = torch.empty((gamma, n), dtype=torch.uint8, device=dev)
-    it = torch.empty((gamma,), dtype=torch.int32, device=dev)
-    conv = torch.empty((gamma,), dtype=torch.uint8, device=dev)
-    ws = ldpc.workspace(g, gamma, iters, 0, dev)
-    out = (post, bits, it, conv)
-
-    def step():
-        ldpc.decode(g, llr, iters, early_stop=False, out=out, ws=ws)
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    # timed region: K whole decodes, nothing else enqueued in between
-    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    start.record()
-    for _ in range(args.steps):
-        step()
-    stop.record()
-    torch.cuda.synchronize()
-    total_ms = start.elapsed_time(stop)
-    ms_per_step = total_ms / args.steps
-    # the same K decodes again with a HIP event pair around every kernel launch
-    # (on the decode stream): per-kernel average durations for the roofline
-    ldpc.timing_read()
-    ldpc.timing_enable(True)
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    ldpc.timing_enable(False)
-    per_kernel = ldpc.timing_read()
+    os.environ.pop("LDPC_BLOCK_PATH", None)
+    path = ldpc.decode_path(g)
+    # timed region: K whole decodes on the decoder ldpc_decode selects
+    ms_per_step, per_kernel, conv_rate = time_block_decode(g, llr, iters, gamma, args.steps, args.warmup)
     value = gamma * n / (ms_per_step * 1e-3) / 1e6
-
-    # dominant kernel and its roofline
-    algo = algorithmic_bytes(n, E, gamma)
-    dom = max(algo, key=lambda k: per_kernel[k][1])
-    launches, ms = per_kernel[dom]
-    avg_s = ms / launches * 1e-3
-    achieved = algo[dom] / avg_s / 1e9
-    traffic = measured_traffic(dom)
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
-                "avg_launch_us": round(avg_s * 1e6, 2), "algorithmic_bytes_per_launch": algo[dom]}
+    if path == "onchip":
+        roofline = onchip_roofline(per_kernel, E, iters, gamma)
+    else:
+        roofline = package_roofline(per_kernel, n, E, gamma)
     kernels = {k: {"launches": v[0], "avg_us": round(v[1] / v[0] * 1e3, 2)} for k, v in per_kernel.items() if v[0]}
+    # the message-package decoder on the same frames (LDPC_BLOCK_PATH=packages)
+    packages = None
+    if path == "onchip":
+        os.environ["LDPC_BLOCK_PATH"] = "packages"
+        pk_ms, pk_kernels, _ = time_block_decode(g, llr, iters, gamma, args.steps, args.warmup)
+        packages = {"ms_per_step": round(pk_ms, 4), "coded_mbps": round(gamma * n / (pk_ms * 1e-3) / 1e6, 1),
+                    "roofline": package_roofline(pk_kernels, n, E, gamma),
+                    "kernels": {k: {"launches": v[0], "avg_us": round(v[1] / v[0] * 1e3, 2)}
+                                for k, v in pk_kernels.items() if v[0]}}
+        if args.extras:
+            packages["gamma_control"] = gamma_control(g, llr, iters, 4096)
+        os.environ.pop("LDPC_BLOCK_PATH", None)
 
-    conv_rate = float(conv.float().mean().item())
     learned = None
     if args.fer_frames > 0:
         learned = learned_vs_plain(g, [1.5, 1.75, 2.0, 2.25], train_frames=args.train_frames,
@@ -952,8 +1010,10 @@ def main():
                                "avg_iters_sp30": r["sp30"]["avg_iters"]} for r in learned["points"]]}
     sweep = early_stop_sweep(g, gamma, iters, [1.0, 1.25, 1.5, 1.75, 2.0, 2.25, 2.5]) if args.extras else None
     control = gamma_control(g, llr, iters, 4096) if args.extras else None
-    if control is not None:
+    if control is not None and path != "onchip":
         roofline["gamma_4096"] = control["roofline"]
+    if packages is not None and "gamma_control" in packages:
+        packages["roofline"]["gamma_4096"] = packages["gamma_control"]["roofline"]
     cpu = None if args.no_cpu else cpu_baseline(shifts, p, llr_h, iters, min(args.cpu_sample, gamma))
     line = {
         "metric": METRIC, "value": round(value, 2), "unit": "coded Mbit/s", "n_gpus": 1, "steps": args.steps,
@@ -962,9 +1022,10 @@ def main():
         "config": {"workload": f"(3,6)-regular QC-LDPC, p=3060, n={n}, m={g.info['m']}, E={E}; {gamma} frames; "
                                f"{iters} flooding sum-product iterations, no early stop; random codewords, "
                                f"BPSK/AWGN {spec['ebn0_db']} dB",
-                   "n": n, "gamma": gamma, "iterations": iters, "early_stop": False,
+                   "n": n, "gamma": gamma, "iterations": iters, "early_stop": False, "decoder": path,
                    "frames_converged": round(conv_rate, 4)},
         "roofline": roofline, "cpu_baseline": cpu, "kernels": kernels,
+        "package_decoder": packages,
         "fer_learned_vs_plain": learned,
         "early_stop_per_ebn0": sweep,
         "gamma_control": control,

@@ -170,6 +170,25 @@ ldpc_status ldpc_decode(const ldpc_graph* g, const float* llr, int32_t gamma, in
                         uint8_t* converged, void* workspace, size_t workspace_bytes, void* stream);
 
 /*
+ * Which decoder ldpc_decode (and ldpc_decode_noalloc) runs for g on the
+ * current device: *onchip = 1 when each frame is decoded by one workgroup
+ * on one compute unit, its check-to-variable messages in registers and its
+ * posterior sums in LDS (a (3,6) code up to n = 18,432; codes whose base
+ * has 3 rows of weight <= 9 or 4 rows of weight <= 8, no empty base column,
+ * p <= 3072, two n-float arrays within the device's LDS per workgroup), 0
+ * when it runs the message-package decoder (edge messages in the workspace,
+ * one launch per half-iteration).  Both compute Algorithm 1 with the same
+ * FP32 check rule; the on-chip decoder forms each variable-to-check message
+ * as clip(L - alpha) from the posterior sum instead of summing the other
+ * edges, so the two agree within FP32 rounding, not bit for bit.  Setting
+ * the environment variable LDPC_BLOCK_PATH=packages makes ldpc_decode use
+ * the package decoder for every code (read at each call).  The workspace
+ * argument of ldpc_decode is validated the same way on both paths.
+ * Errors: EINVAL (NULL, convolutional graph).
+ */
+ldpc_status ldpc_decode_path(const ldpc_graph* g, int32_t* onchip);
+
+/*
  * ldpc_decode for callers that cannot allocate device memory: code under HIP
  * graph capture, tight serving loops, harnesses that forbid allocation.  It
  * takes no workspace argument.  Its workspace is a static device array of
@@ -467,10 +486,11 @@ const char* ldpc_status_str(ldpc_status s);
  *   17 plan ingest, 18 plan check-node, 19 plan variable-node, 20 plan
  *   final syndrome, frame status and output, 21 window decoding with the
  *   ring in LDS (one launch per call), 22 plan decode in one persistent
- *   launch.
+ *   launch, 23 block decode with each frame on one compute unit (one launch
+ *   per call).
  * ldpc_kernel_class_name returns a static name for a class index.
  */
-#define LDPC_TIMING_CLASSES 23
+#define LDPC_TIMING_CLASSES 24
 ldpc_status ldpc_timing_enable(int32_t enable);
 ldpc_status ldpc_timing_read(int64_t* launches, double* total_ms, int32_t capacity);
 const char* ldpc_kernel_class_name(int32_t cls);

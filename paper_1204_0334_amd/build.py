@@ -14,7 +14,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libldpc_hip.so")
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("graph.cpp", "decode.hip", "plan.hip")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("graph.cpp", "decode.hip", "plan.hip", "onchip.hip")]
 ARCH = os.environ.get("LDPC_OFFLOAD_ARCH", "gfx950")
 
 

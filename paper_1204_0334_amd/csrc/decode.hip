@@ -46,6 +46,7 @@
 
 #include "device.h"
 #include "internal.h"
+#include "onchip.h"
 
 namespace ldpc {
 
@@ -2406,6 +2407,11 @@ ldpc_status ldpc_workspace_size(const ldpc_graph* g, int32_t gamma, int32_t max_
     return LDPC_OK;
 }
 
+static bool packages_forced() {
+    const char* path = std::getenv("LDPC_BLOCK_PATH");
+    return path && std::strcmp(path, "packages") == 0;
+}
+
 static ldpc_status decode_block(const ldpc_graph* g, const float* llr, int32_t gamma, int32_t max_iters,
                                 int32_t early_stop, float* post, uint8_t* bits, int32_t* iters, uint8_t* converged,
                                 void* workspace, size_t workspace_bytes, void* stream, const float* nms_w) {
@@ -2421,6 +2427,12 @@ static ldpc_status decode_block(const ldpc_graph* g, const float* llr, int32_t g
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     char* ws = reinterpret_cast<char*>(workspace);
     (void)hipGetLastError();
+    // sum-product decodes of codes that fit one compute unit run on chip
+    // (onchip.hip); LDPC_BLOCK_PATH=packages keeps them on this decoder
+    if (!nms_w && !packages_forced()) {
+        const int r = onchip_decode(g, llr, gamma, max_iters, early_stop ? 1 : 0, post, bits, iters, converged, st);
+        if (r != 0) return r > 0 && hipGetLastError() == hipSuccess ? LDPC_OK : LDPC_EHIP;
+    }
     switch (tl.fpl) {
         case 4: run_block<4>(g, llr, gamma, max_iters, early_stop ? 1 : 0, post, bits, iters, converged, ws, lay, tl, st, nms_w); break;
         case 2: run_block<2>(g, llr, gamma, max_iters, early_stop ? 1 : 0, post, bits, iters, converged, ws, lay, tl, st, nms_w); break;
@@ -2443,6 +2455,12 @@ ldpc_status ldpc_decode(const ldpc_graph* g, const float* llr, int32_t gamma, in
                         size_t workspace_bytes, void* stream) {
     return decode_block(g, llr, gamma, max_iters, early_stop, post, bits, iters, converged, workspace, workspace_bytes,
                         stream, nullptr);
+}
+
+ldpc_status ldpc_decode_path(const ldpc_graph* g, int32_t* onchip) {
+    if (!g || !onchip || g->kind != LDPC_GRAPH_QC) return LDPC_EINVAL;
+    *onchip = (!packages_forced() && onchip_fits(g)) ? 1 : 0;
+    return LDPC_OK;
 }
 
 }  // extern "C"
@@ -2685,7 +2703,7 @@ const char* ldpc_kernel_class_name(int32_t cls) {
         "window_variable_node", "pipeline_ingest", "pipeline_check_node", "pipeline_variable_node",
         "train_check_node", "train_variable_node", "train_variable_node_backward", "train_check_node_backward",
         "train_reduce", "plan_ingest", "plan_check_node", "plan_variable_node", "plan_finish",
-        "window_lds", "plan_persistent"};
+        "window_lds", "plan_persistent", "onchip_decode"};
     if (cls < 0 || cls >= LDPC_TIMING_CLASSES) return "unknown";
     return names[cls];
 }

@@ -40,7 +40,7 @@ def layout_name(layout: int) -> str:
     v, c = (layout >> 4) & 3, (layout >> 6) & 3
     return LAYOUT_NAMES[layout & 15] + ("" if v == 0 else f"/VN{1 << v}") + ("" if c == 0 else f"/CN{1 << c}")
 PLAN_MAX_CODES = 16
-TIMING_CLASSES = 23
+TIMING_CLASSES = 24
 MAX_ITERS = 100000
 NOALLOC_SCRATCH_BYTES = 64 * 1024 * 1024
 
@@ -67,6 +67,7 @@ _get_info = _sig("ldpc_graph_get_info", _i32, [_vp, ctypes.POINTER(GraphInfo)])
 _destroy = _sig("ldpc_graph_destroy", None, [_vp])
 _ws_size = _sig("ldpc_workspace_size", _i32, [_vp, _i32, _i32, _i32, ctypes.POINTER(_sz)])
 _decode = _sig("ldpc_decode", _i32, [_vp, _vp, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _sz, _vp])
+_decode_path = _sig("ldpc_decode_path", _i32, [_vp, ctypes.POINTER(_i32)])
 _decode_noalloc = _sig("ldpc_decode_noalloc", _i32, [_vp, _vp, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp])
 _nms_decode = _sig("ldpc_nms_decode", _i32, [_vp, _vp, _i32, _i32, _vp, _i32, _vp, _vp, _vp, _vp, _vp, _sz, _vp])
 _nms_ws_size = _sig("ldpc_nms_train_workspace_size", _i32, [_vp, _i32, _i32, _i32, ctypes.POINTER(_sz)])
@@ -94,7 +95,8 @@ _timing_read = _sig("ldpc_timing_read", _i32, [ctypes.POINTER(_i64), ctypes.POIN
 _class_name = _sig("ldpc_kernel_class_name", ctypes.c_char_p, [_i32])
 
 EXPORTED = ["ldpc_graph_create_qc", "ldpc_graph_create_ldpccc_from_qc", "ldpc_graph_create_ldpccc_sf",
-            "ldpc_graph_get_info", "ldpc_graph_destroy", "ldpc_workspace_size", "ldpc_decode", "ldpc_decode_noalloc",
+            "ldpc_graph_get_info", "ldpc_graph_destroy", "ldpc_workspace_size", "ldpc_decode", "ldpc_decode_path",
+            "ldpc_decode_noalloc",
             "ldpc_nms_decode", "ldpc_nms_train_workspace_size", "ldpc_nms_train_forward",
             "ldpc_nms_train_backward", "ldpc_plan_create", "ldpc_plan_destroy", "ldpc_plan_workspace_size",
             "ldpc_plan_set_layout", "ldpc_plan_get_layout", "ldpc_plan_decode", "ldpc_plan_capture",
@@ -255,6 +257,14 @@ def decode(g: Graph, llr, max_iters: int, early_stop: bool = False, out=None, ws
                    bits.data_ptr(), iters.data_ptr(), conv.data_ptr(), ws.data_ptr(), ws.numel(),
                    _stream_handle(stream)), "ldpc_decode")
     return post, bits, iters, conv
+
+
+def decode_path(g: Graph) -> str:
+    """ldpc_decode_path: "onchip" when ldpc_decode decodes each frame of g on
+    one compute unit on the current device, "packages" otherwise."""
+    v = _i32(0)
+    _check(_decode_path(g.handle, ctypes.byref(v)), "ldpc_decode_path")
+    return "onchip" if v.value else "packages"
 
 
 def decode_noalloc(g: Graph, llr, max_iters: int, early_stop: bool = False, out=None, stream=None):

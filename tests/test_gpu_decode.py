@@ -37,8 +37,21 @@ def rel_err(gpu, ref):
     return np.abs(g - r) / np.maximum(np.abs(r), 1.0)
 
 
+@pytest.fixture(params=["onchip", "packages"])
+def block_path(request, monkeypatch):
+    """Runs a block-code test on both decoders behind ldpc_decode: the
+    default (each frame on one compute unit where the code fits) and the
+    message-package decoder (LDPC_BLOCK_PATH=packages, read at each call)."""
+    if request.param == "packages":
+        monkeypatch.setenv("LDPC_BLOCK_PATH", "packages")
+    else:
+        monkeypatch.delenv("LDPC_BLOCK_PATH", raising=False)
+    return request.param
+
+
 def gpu_decode(g, llr, iters, early):
-    print(f"[gpu] decode n={g.n} gamma={llr.shape[0]} iters={iters} early={early}", flush=True)
+    print(f"[gpu] decode n={g.n} gamma={llr.shape[0]} iters={iters} early={early} path={ldpc.decode_path(g)}",
+          flush=True)
     x = torch.from_numpy(np.ascontiguousarray(llr)).to(DEV)
     post, bits, it, conv = ldpc.decode(g, x, iters, early_stop=early)
     torch.cuda.synchronize()
@@ -78,6 +91,7 @@ def check_parity(gpu, ref, gate_all_posteriors, what):
 # the small (3,6) QC code: n = 384, 64 frames, 2.0 dB
 # ----------------------------------------------------------------------------
 
+@pytest.mark.usefixtures("block_path")
 @pytest.mark.parametrize("iters", [1, 2, 3])
 def test_qc_p64_fixed_iterations_all_frames(iters):
     a, llr, _ = qc_case(3, 6, 64, 1, 64, 2.0, 101)
@@ -87,6 +101,7 @@ def test_qc_p64_fixed_iterations_all_frames(iters):
     check_parity(gpu, ref, True, f"I={iters}")
 
 
+@pytest.mark.usefixtures("block_path")
 def test_qc_p64_twenty_iterations_early_stop():
     a, llr, _ = qc_case(3, 6, 64, 1, 64, 2.0, 101)
     g = ldpc.Graph.qc(a, 64)
@@ -100,6 +115,7 @@ def test_qc_p64_twenty_iterations_early_stop():
     assert gpu["converged"].sum() >= 40
 
 
+@pytest.mark.usefixtures("block_path")
 def test_qc_p64_twenty_iterations_no_early_stop():
     a, llr, _ = qc_case(3, 6, 64, 1, 64, 2.0, 101)
     ref = oracle.decode_block(oracle.qc_parity_check(a, 64), llr, 20)
@@ -108,6 +124,7 @@ def test_qc_p64_twenty_iterations_no_early_stop():
     assert np.all(gpu["iters"] == 20)
 
 
+@pytest.mark.usefixtures("block_path")
 def test_frozen_frames_keep_their_stopping_iteration():
     # a frame stopped at iteration i returns exactly what a fixed i-iteration run returns
     a, llr, _ = qc_case(3, 6, 64, 1, 64, 1.5, 77)
@@ -126,6 +143,7 @@ def test_frozen_frames_keep_their_stopping_iteration():
 # ragged batches, several tiles, irregular codes, degenerate cases
 # ----------------------------------------------------------------------------
 
+@pytest.mark.usefixtures("block_path")
 @pytest.mark.parametrize("gamma", [1, 63, 65, 100, 130, 257, 700])
 def test_ragged_batches(gamma):
     a, llr, _ = qc_case(3, 6, 37, 1, gamma, 1.75, 300 + gamma)
@@ -134,6 +152,7 @@ def test_ragged_batches(gamma):
     check_parity(gpu, ref, True, f"gamma={gamma}")
 
 
+@pytest.mark.usefixtures("block_path")
 def test_irregular_qc_with_zero_blocks():
     a = np.array([[0, 5, -1, 7, 2, -1, 11, 3],
                   [9, -1, 4, 1, -1, 6, 0, -1],
@@ -166,6 +185,7 @@ def two_frames_per_lane(monkeypatch):
     monkeypatch.setenv("LDPC_FRAMES_PER_LANE", "2")
 
 
+@pytest.mark.usefixtures("block_path")
 @pytest.mark.parametrize("iters", [1, 2, 3])
 def test_rate_two_thirds_fixed_iterations_all_frames(iters, two_frames_per_lane):
     # 3 x 9 base: rows of weight 9 (the 12-slot row class, 2 frames per
@@ -176,6 +196,7 @@ def test_rate_two_thirds_fixed_iterations_all_frames(iters, two_frames_per_lane)
     check_parity(gpu_decode(g, llr, iters, False), ref, True, f"3x9 I={iters}")
 
 
+@pytest.mark.usefixtures("block_path")
 def test_rate_two_thirds_twenty_iterations_early_stop(two_frames_per_lane):
     a, llr, _ = qc_case(3, 9, 72, 53, 370, 2.5, 402)
     g = ldpc.Graph.qc(a, 72)
@@ -187,6 +208,7 @@ def test_rate_two_thirds_twenty_iterations_early_stop(two_frames_per_lane):
     assert gpu["converged"].sum() >= 300 and len(set(gpu["iters"].tolist())) >= 3
 
 
+@pytest.mark.usefixtures("block_path")
 def test_rate_two_thirds_one_frame_per_lane():
     # the same rows with one frame per lane (the default tiling for 300 frames)
     a, llr, _ = qc_case(3, 9, 40, 54, 300, 3.0, 403)
@@ -241,6 +263,7 @@ def test_forest_protographs_are_exact_map():
 # batch semantics and invariants (bit-exact)
 # ----------------------------------------------------------------------------
 
+@pytest.mark.usefixtures("block_path")
 def test_batch_and_permutation_invariance_and_determinism():
     a, llr, _ = qc_case(3, 6, 64, 1, 320, 1.5, 55)
     g = ldpc.Graph.qc(a, 64)
@@ -256,6 +279,7 @@ def test_batch_and_permutation_invariance_and_determinism():
         assert np.array_equal(shuf[k], full[k][perm]), k
 
 
+@pytest.mark.usefixtures("block_path")
 def test_decode_on_another_stream_with_buffers_allocated_by_the_binding():
     # workspace and outputs allocated by the binding on the current stream,
     # the decode enqueued on a second stream (default priority): the same
@@ -279,6 +303,7 @@ def test_decode_on_another_stream_with_buffers_allocated_by_the_binding():
             assert torch.equal(a_, b_)
 
 
+@pytest.mark.usefixtures("block_path")
 def test_codeword_symmetry():
     a, llr, cw = qc_case(3, 6, 64, 1, 128, 2.0, 21, codeword="random")
     g = ldpc.Graph.qc(a, 64)
@@ -294,6 +319,7 @@ def test_codeword_symmetry():
 # paper scale: n = 18360, 1024 frames, 20 iterations (the benchmark's call)
 # ----------------------------------------------------------------------------
 
+@pytest.mark.usefixtures("block_path")
 def test_n18360_full_batch_sampled_frames():
     w = synth.workload_inputs("qc36_p3060")
     a, llr = w["shifts"], w["llr"]
@@ -319,6 +345,7 @@ def test_n18360_full_batch_sampled_frames():
     assert not H.syndrome(gpu["bits"][wrong]).any()
 
 
+@pytest.mark.usefixtures("block_path")
 def test_n18360_early_stop_sampled_frames():
     w = synth.workload_inputs("qc36_p3060", gamma=256, ebn0_db=1.25)
     a, llr = w["shifts"], w["llr"]

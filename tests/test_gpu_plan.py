@@ -14,6 +14,14 @@ from paper_1204_0334_amd import ldpc
 
 pytestmark = pytest.mark.gpu
 
+
+@pytest.fixture(autouse=True)
+def package_decoder(monkeypatch):
+    # the plan runs the message-package kernels; ldpc_decode is compared with
+    # it bit for bit, so it must run them too (LDPC_BLOCK_PATH, read per call)
+    monkeypatch.setenv("LDPC_BLOCK_PATH", "packages")
+
+
 DEV = "cuda:0"
 
 RAGGED = [dict(J=3, L=6, p=27, gamma=1, ebn0_db=2.5), dict(J=3, L=6, p=27, gamma=7, ebn0_db=2.5),

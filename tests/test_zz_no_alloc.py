@@ -32,9 +32,21 @@ def same_as_decode(g, llr, iters, early):
     return got
 
 
-def test_noalloc_two_calls_in_a_row_then_another_code():
+@pytest.fixture(params=["packages", "onchip"])
+def block_path(request, monkeypatch):
+    # both decoders behind ldpc_decode; the package decoder is the one whose
+    # kernels use the workspace (the static array), the on-chip one needs none
+    if request.param == "packages":
+        monkeypatch.setenv("LDPC_BLOCK_PATH", "packages")
+    else:
+        monkeypatch.delenv("LDPC_BLOCK_PATH", raising=False)
+    return request.param
+
+
+def test_noalloc_two_calls_in_a_row_then_another_code(block_path):
     a = synth.draw_qc_shifts(3, 6, 3060, 2)
     g = ldpc.Graph.qc(a, 3060)
+    assert ldpc.decode_path(g) == block_path
     assert g.workspace_size(100, 20) <= ldpc.NOALLOC_SCRATCH_BYTES
     s2 = synth.ebn0_to_sigma2(1.5, 0.5)
     first = same_as_decode(g, synth.bpsk_awgn_llr(None, s2, 301, gamma=100, n=g.n), 20, True)
