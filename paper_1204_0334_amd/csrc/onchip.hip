@@ -44,6 +44,7 @@
 
 #include <cstdlib>
 #include <cstring>
+#include <type_traits>
 
 #include "device.h"
 #include "internal.h"
@@ -52,6 +53,8 @@
 namespace ldpc {
 
 constexpr int kOcMaxThreads = 1024;
+constexpr int kOcRows = 4;    // base rows (J) an instantiation may have
+constexpr int kOcSlots = 9;   // edge slots per row an instantiation may have
 
 struct OnchipArgs {
     const float* llr;       // [gamma][n]
@@ -60,20 +63,107 @@ struct OnchipArgs {
     int32_t* iters;         // [gamma] or NULL
     uint8_t* conv;          // [gamma] or NULL
     int max_iters, early;
-    uint32_t first[LDPC_MAX_BLOCKS / 32];   // bit b: edge block b is the lowest nonzero block of its base column
+    // edge slot k of base row j (index j * kOcSlots + k): row (j, s) meets
+    // variable l*p + (s + a) mod p of base column l; held as byte offsets
+    // into the LDS posterior pairs (8 bytes per variable): cb8 = 8 l p and
+    // sh8 = 8 a
+    int32_t cb8[kOcRows * kOcSlots];
+    int32_t sh8[kOcRows * kOcSlots];
+    int32_t deg[kOcRows];   // nonzero blocks of base row j
+    uint64_t first;         // bit j * kOcSlots + k: the lowest nonzero block of its base column
 };
 
-template <int NJ, int NQ, int DC>
-__global__ void __launch_bounds__(kOcMaxThreads) onchip_block_kernel(const QCDesc D, const OnchipArgs A) {
-    extern __shared__ float Lbuf[];   // [2][n]: L of iteration i in Lbuf + (i & 1) * n
+// Byte offset of the posterior pair of the variable that edge slot jk of
+// row (j, s) meets, from s8 = 8 s: one wrap of s + shift (unsigned min picks
+// t - p exactly when t >= p).
+__device__ __forceinline__ uint32_t oc_pair(const OnchipArgs& A, int jk, uint32_t s8, uint32_t p8) {
+    const uint32_t t = s8 + (uint32_t)A.sh8[jk];
+    return (uint32_t)A.cb8[jk] + min(t, t - p8);
+}
+
+__device__ __forceinline__ float lds_at(const float2* L, uint32_t byte) {
+    return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(L) + byte);
+}
+
+__device__ __forceinline__ float* lds_ptr(float2* L, uint32_t byte) {
+    return reinterpret_cast<float*>(reinterpret_cast<char*>(L) + byte);
+}
+
+// One iteration: PAR = it & 1.  L of iteration i lives in component i & 1 of
+// each variable's pair, so this iteration reads component 1 - PAR (the
+// previous iteration's sums) and accumulates into component PAR; both are
+// immediate offsets of one address.  The signs read are the previous
+// iteration's decisions: with flag != NULL, a wave with a violated row sets
+// *flag.
+template <int NJ, int NQ, int DC, bool REG, int PAR>
+__device__ __forceinline__ void oc_iteration(const OnchipArgs& A, float2* L, const float* __restrict__ mu,
+                                             float (&al)[NJ][NQ][DC], uint32_t tid8, uint32_t TB8, uint32_t p8,
+                                             uint32_t* flag) {
+    uint64_t viol = 0;
+    constexpr uint32_t kOld = 4u * (1 - PAR), kNew = 4u * PAR;
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+        const int d = REG ? DC : A.deg[j];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const uint32_t s8 = tid8 + (uint32_t)q * TB8;
+            if (s8 < p8) {
+                uint32_t va[DC];
+                float in[DC][1];
+                uint64_t par = 0;
+#pragma unroll
+                for (int k = 0; k < DC; ++k) {
+                    if (REG || k < d) {
+                        va[k] = oc_pair(A, j * kOcSlots + k, s8, p8);
+                        const float x = lds_at(L, va[k] + kOld);
+                        par ^= __ballot(x < 0.0f);
+                        in[k][0] = clip30(x - al[j][q][k]);
+                    } else {
+                        va[k] = 0;
+                        in[k][0] = 0.0f;
+                    }
+                }
+                viol |= par;
+                float out[DC][1];
+                sp_check<DC, 1>(in, d, out);
+#pragma unroll
+                for (int k = 0; k < DC; ++k) {
+                    if (REG || k < d) {
+                        al[j][q][k] = out[k][0];
+                        const bool first = REG ? (j == 0) : ((A.first >> (j * kOcSlots + k)) & 1ull);
+                        if (first) {
+                            *lds_ptr(L, va[k] + kNew) = mu[va[k] >> 3] + out[k][0];
+                        } else {
+                            // the only update of this variable in this base row: no other
+                            // thread touches it before the barrier, so a plain read and
+                            // write suffice (LDS float atomics ran the decode 4x slower)
+                            float* acc = lds_ptr(L, va[k] + kNew);
+                            *acc = *acc + out[k][0];
+                        }
+                    }
+                }
+            }
+        }
+        // with early stopping (flag != NULL) each wave ORs its verdict on the
+        // previous iteration's syndrome in before the last barrier
+        if (j == NJ - 1 && flag && viol != 0ull && (threadIdx.x & 63) == 0) atomicOr(flag, 1u);
+        __syncthreads();
+    }
+}
+
+// REG: every base row has DC nonzero blocks and every block of base row 0 is
+// nonzero (so every base column starts in base row 0); otherwise the row
+// weights and the first blocks of the columns come from the tables.
+template <int NJ, int NQ, int DC, bool REG>
+__global__ void __launch_bounds__(kOcMaxThreads) onchip_block_kernel(const int n, const int p, const OnchipArgs A) {
+    extern __shared__ float2 Lpair[];   // [n]: (L of even iterations, L of odd iterations)
     __shared__ uint32_t flag[3];
     const int tid = threadIdx.x;
     const int TB = blockDim.x;
-    const int n = D.n, p = D.p;
     const size_t f0 = (size_t)blockIdx.x * n;
     const float* __restrict__ mu = A.llr + f0;
     // L of "iteration 0" is mu, so that iteration 1 reads beta = clip(mu - 0)
-    for (int v = tid; v < n; v += TB) Lbuf[v] = mu[v];
+    for (int v = tid; v < n; v += TB) Lpair[v].x = mu[v];
     if (tid < 3) flag[tid] = 0u;
     float al[NJ][NQ][DC];
 #pragma unroll
@@ -84,105 +174,67 @@ __global__ void __launch_bounds__(kOcMaxThreads) onchip_block_kernel(const QCDes
             for (int k = 0; k < DC; ++k) al[j][q][k] = 0.0f;
     __syncthreads();
 
-    int it = 1, stop = 0;
-    for (; it <= A.max_iters; ++it) {
-        const float* Lo = Lbuf + ((it - 1) & 1) * n;
-        float* Ln = Lbuf + (it & 1) * n;
+    const uint32_t p8 = 8u * (uint32_t)p, TB8 = 8u * (uint32_t)TB;
+    int stop = 0;
+    // each step: iteration it, then the test of the syndrome of it - 1
+    auto step = [&](int it, auto parity) -> bool {
+        constexpr int PAR = decltype(parity)::value;
+        // the edges' offsets do not change between iterations, but holding
+        // them would take as many registers as the alphas: the thread index
+        // passes through an opaque copy so that they are recomputed
+        uint32_t tid8 = 8u * (uint32_t)tid;
+        asm volatile("" : "+v"(tid8));
         const bool syn = A.early && it >= 2;
         if (tid == 0) flag[(it + 1) % 3] = 0u;
-        uint32_t viol = 0;
-#pragma unroll
-        for (int j = 0; j < NJ; ++j) {
-            const int b0 = D.rstart[j];
-            const int d = D.rstart[j + 1] - b0;
-#pragma unroll
-            for (int q = 0; q < NQ; ++q) {
-                const int s = tid + q * TB;
-                if (s < p) {
-                    int vk[DC];
-                    float in[DC][1];
-                    uint32_t par = 0;
-#pragma unroll
-                    for (int k = 0; k < DC; ++k) {
-                        if (k < d) {
-                            const int b = b0 + k;
-                            int t = s + D.eshift[b];
-                            t = t >= p ? t - p : t;
-                            vk[k] = D.ecol[b] * p + t;
-                            const float x = Lo[vk[k]];
-                            par ^= (uint32_t)(x < 0.0f);
-                            in[k][0] = clip30(x - al[j][q][k]);
-                        } else {
-                            vk[k] = 0;
-                            in[k][0] = 0.0f;
-                        }
-                    }
-                    viol |= par;
-                    float out[DC][1];
-                    sp_check<DC, 1>(in, d, out);
-#pragma unroll
-                    for (int k = 0; k < DC; ++k) {
-                        if (k < d) {
-                            al[j][q][k] = out[k][0];
-                            const int b = b0 + k;
-                            const bool first = (A.first[b >> 5] >> (b & 31)) & 1u;
-                            const float base = first ? mu[vk[k]] : Ln[vk[k]];
-                            Ln[vk[k]] = base + out[k][0];
-                        }
-                    }
-                }
-            }
-            if (j == NJ - 1 && syn && __ballot(viol != 0u) != 0ull && (tid & 63) == 0)
-                atomicOr(&flag[it % 3], 1u);
-            __syncthreads();
-        }
+        oc_iteration<NJ, NQ, DC, REG, PAR>(A, Lpair, mu, al, tid8, TB8, p8, syn ? &flag[it % 3] : nullptr);
         if (syn && flag[it % 3] == 0u) {   // the syndrome of iteration it - 1 is zero
             stop = it - 1;
-            break;
+            return true;
         }
+        return false;
+    };
+    for (int it = 1; it <= A.max_iters; it += 2) {
+        if (step(it, std::integral_constant<int, 1>{})) break;
+        if (it + 1 > A.max_iters) break;
+        if (step(it + 1, std::integral_constant<int, 0>{})) break;
     }
 
     int iters_out, conv_out;
-    const float* Lf;
+    const float* Lf = reinterpret_cast<const float*>(Lpair);
+    int comp;
     if (stop) {
-        Lf = Lbuf + (stop & 1) * n;
+        comp = stop & 1;
         iters_out = stop;
         conv_out = 1;
     } else {
         // syndrome of the last iteration (flag word (max + 1) % 3 was cleared in it)
         const int last = A.max_iters;
-        Lf = Lbuf + (last & 1) * n;
-        uint32_t viol = 0;
+        comp = last & 1;
+        uint64_t viol = 0;
 #pragma unroll
         for (int j = 0; j < NJ; ++j) {
-            const int b0 = D.rstart[j];
-            const int d = D.rstart[j + 1] - b0;
+            const int d = REG ? DC : A.deg[j];
 #pragma unroll
             for (int q = 0; q < NQ; ++q) {
-                const int s = tid + q * TB;
-                if (s < p) {
-                    uint32_t par = 0;
+                const uint32_t s8 = 8u * (uint32_t)(tid + q * TB);
+                if (s8 < p8) {
+                    uint64_t par = 0;
 #pragma unroll
-                    for (int k = 0; k < DC; ++k) {
-                        if (k < d) {
-                            const int b = b0 + k;
-                            int t = s + D.eshift[b];
-                            t = t >= p ? t - p : t;
-                            par ^= (uint32_t)(Lf[D.ecol[b] * p + t] < 0.0f);
-                        }
-                    }
+                    for (int k = 0; k < DC; ++k)
+                        if (REG || k < d)
+                            par ^= __ballot(lds_at(Lpair, oc_pair(A, j * kOcSlots + k, s8, p8) + 4u * comp) < 0.0f);
                     viol |= par;
                 }
             }
         }
         const int fw = (last + 1) % 3;
-        if (__ballot(viol != 0u) != 0ull && (tid & 63) == 0) atomicOr(&flag[fw], 1u);
+        if (viol != 0ull && (tid & 63) == 0) atomicOr(&flag[fw], 1u);
         __syncthreads();
         iters_out = last;
         conv_out = flag[fw] == 0u ? 1 : 0;
     }
     for (int v = tid; v < n; v += TB) {
-        const float x = Lf[v];
+        const float x = Lf[2 * v + comp];
         A.post[f0 + v] = clip30(x);
         A.bits[f0 + v] = (uint8_t)(x < 0.0f);
     }
@@ -200,21 +252,25 @@ namespace {
 
 struct Variant {
     int nj, nq, dc;
+    bool reg;
     const void* fn;
 };
 
-template <int NJ, int NQ, int DC>
+template <int NJ, int NQ, int DC, bool REG>
 constexpr Variant variant() {
-    return Variant{NJ, NQ, DC, reinterpret_cast<const void*>(&onchip_block_kernel<NJ, NQ, DC>)};
+    return Variant{NJ, NQ, DC, REG, reinterpret_cast<const void*>(&onchip_block_kernel<NJ, NQ, DC, REG>)};
 }
 
-// (base rows, rows per thread and base row, row-weight capacity); each
-// compiles without spilled vector registers (54 alphas per thread at most:
-// 3 x 1 x 18 would spill, so rows of weight 18 stay with the package decoder)
+// (base rows, rows per thread and base row, row-weight capacity, regular
+// base); each compiles without spilled vector registers (54 alphas per
+// thread at most: rows of weight 18 would spill and stay with the package
+// decoder)
 const Variant kVariants[] = {
-    variant<3, 1, 6>(), variant<3, 2, 6>(), variant<3, 3, 6>(),
-    variant<3, 1, 9>(), variant<3, 2, 9>(),
-    variant<4, 1, 8>(),
+    variant<3, 1, 6, true>(),  variant<3, 2, 6, true>(),  variant<3, 3, 6, true>(),
+    variant<3, 1, 9, true>(),  variant<3, 2, 9, true>(),
+    variant<3, 1, 6, false>(), variant<3, 2, 6, false>(), variant<3, 3, 6, false>(),
+    variant<3, 1, 9, false>(), variant<3, 2, 9, false>(),
+    variant<4, 1, 8, false>(),
 };
 
 struct Choice {
@@ -226,25 +282,31 @@ struct Choice {
 bool choose(const ldpc_graph* g, Choice& c) {
     if (!g || g->kind != LDPC_GRAPH_QC) return false;
     const QCDesc& D = g->qc;
+    if (D.J > kOcRows || D.dc_max > kOcSlots) return false;
     for (int l = 0; l < D.L; ++l)
         if (D.cstart[l + 1] == D.cstart[l]) return false;   // a base column without edges
+    bool reg = D.rstart[1] - D.rstart[0] == D.L;            // base row 0 full: every column starts there
+    for (int j = 0; j < D.J; ++j) reg = reg && (D.rstart[j + 1] - D.rstart[j] == D.dc_max);
     int dev = 0, limit = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&limit, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) {
         (void)hipGetLastError();
         return false;
     }
-    const size_t lds = (size_t)2 * D.n * sizeof(float);
+    const size_t lds = (size_t)D.n * sizeof(float2);
     if (lds + 64 > (size_t)limit) return false;
     const Variant* best = nullptr;
     int best_tb = 0;
     for (const Variant& v : kVariants) {
         if (v.nj != D.J || v.dc < D.dc_max) continue;
+        if (v.reg && !(reg && v.dc == D.dc_max)) continue;
         const int per = (D.p + v.nq - 1) / v.nq;
         const int tb = (per + 63) / 64 * 64;
         if (tb > kOcMaxThreads) continue;
-        // fewest rows per thread, then the smallest row-weight capacity
-        if (!best || v.nq < best->nq || (v.nq == best->nq && v.dc < best->dc)) {
+        // fewest rows per thread, then a regular variant, then the smallest row-weight capacity
+        const bool better = !best || v.nq < best->nq ||
+                            (v.nq == best->nq && (v.reg > best->reg || (v.reg == best->reg && v.dc < best->dc)));
+        if (better) {
             best = &v;
             best_tb = tb;
         }
@@ -276,16 +338,23 @@ int onchip_decode(const ldpc_graph* g, const float* llr, int gamma, int max_iter
     A.conv = converged;
     A.max_iters = max_iters;
     A.early = early;
-    for (int l = 0; l < D.L; ++l) {
-        const int b = D.cedge[D.cstart[l]];   // edge blocks of a column ascend by base row
-        A.first[b >> 5] |= 1u << (b & 31);
+    for (int j = 0; j < D.J; ++j) {
+        A.deg[j] = D.rstart[j + 1] - D.rstart[j];
+        for (int k = 0; k < A.deg[j]; ++k) {
+            const int b = D.rstart[j] + k;
+            A.cb8[j * kOcSlots + k] = 8 * D.ecol[b] * D.p;
+            A.sh8[j * kOcSlots + k] = 8 * D.eshift[b];
+            if (D.cedge[D.cstart[D.ecol[b]]] == b)   // edge blocks of a column ascend by base row
+                A.first |= 1ull << (j * kOcSlots + k);
+        }
     }
     if (hipFuncSetAttribute(c.v->fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c.lds) != hipSuccess) {
         (void)hipGetLastError();
         return 0;
     }
     timing::Scope ts(23, st);
-    void* args[] = {const_cast<QCDesc*>(&D), &A};
+    int n = D.n, p = D.p;
+    void* args[] = {&n, &p, &A};
     return hipLaunchKernel(c.v->fn, dim3((unsigned)gamma), dim3((unsigned)c.tb), args, c.lds, st) == hipSuccess ? 1 : -1;
 }
 
