@@ -108,8 +108,12 @@ VN_EDGE_SLOTS = 4
 # as L = mu + sum alpha (one addition per edge) and beta = clip(L - alpha)
 # (a subtraction and the clip per edge): 3 slots per variable edge.
 ONCHIP_VN_EDGE_SLOTS = 3
-# non-packed FP32 vector issue rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
-ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# FP32 vector issue rate: 256 CUs x 128 FP32 lanes x 2.4 GHz = 78.6 T lane
+# operations/s (MI355X's 157.3 TFLOP/s FP32 vector figure counts an FMA as
+# two).  The kernels use no packed-FP32 instructions; plain VOP2/VOP3 FP32
+# instructions of wave64 issue at this rate on gfx950 (a multiply-only loop
+# measured 61 T lane-ops/s), transcendentals at a quarter of it (18.6 T/s).
+ALU_PEAK_TOPS = 256 * 128 * 2.4e9 / 1e12
 
 
 def window_algorithmic_ops(info, W: int, K: int, gamma: int):
@@ -236,8 +240,8 @@ def bench_window(args, pipeline: bool = False):
         roofline = {"bound": "alu", "achieved": round(achieved, 2), "peak": round(ALU_PEAK_TOPS, 2), "unit": "Top/s",
                     "frac": round(achieved / ALU_PEAK_TOPS, 4), "traffic": None, "kernel": "window_lds",
                     "avg_launch_us": round(avg_s * 1e6, 2), "algorithmic_ops_per_launch": ops,
-                    "note": "FP32 vector issue slots (transcendentals count 4) against the non-packed "
-                            "FP32 vector rate; messages stay in LDS"}
+                    "note": "FP32 vector issue slots (transcendentals count 4) against the FP32 vector "
+                            "issue rate (256 CUs x 128 lanes x 2.4 GHz); messages stay in LDS"}
     elif pipeline:
         # the ring of 68 frames x 512 streams (about 74 MB) stays in the
         # L2 / Infinity Cache, so algorithmic bytes overstate what crosses the
@@ -821,8 +825,8 @@ def onchip_roofline(per_kernel, E: int, iters: int, gamma: int):
     """ALU roofline of the block decoder that keeps each frame on one compute
     unit (one launch per decode, no message traffic to HBM): FP32 vector issue
     slots of Eq. 3-5 per launch (check edge 36, variable edge 3, every edge,
-    every iteration, every frame) over the launch time, against the
-    non-packed FP32 vector issue rate."""
+    every iteration, every frame) over the launch time, against the FP32
+    vector issue rate."""
     launches, ms = per_kernel["onchip_decode"]
     avg_s = ms / launches * 1e-3
     ops = iters * E * (CN_EDGE_SLOTS + ONCHIP_VN_EDGE_SLOTS) * gamma
@@ -830,8 +834,9 @@ def onchip_roofline(per_kernel, E: int, iters: int, gamma: int):
     return {"bound": "alu", "achieved": round(achieved, 2), "peak": round(ALU_PEAK_TOPS, 2), "unit": "Top/s",
             "frac": round(achieved / ALU_PEAK_TOPS, 4), "traffic": None, "kernel": "onchip_decode",
             "avg_launch_us": round(avg_s * 1e6, 2), "algorithmic_ops_per_launch": ops,
-            "note": "FP32 vector issue slots (transcendentals count 4) against the non-packed FP32 vector "
-                    "rate; each frame's messages stay in registers and LDS of one compute unit"}
+            "note": "FP32 vector issue slots (transcendentals count 4) against the FP32 vector issue rate "
+                    "(256 CUs x 128 lanes x 2.4 GHz); each frame's messages stay in registers and LDS of one "
+                    "compute unit"}
 
 
 def package_roofline(per_kernel, n: int, E: int, gamma: int):

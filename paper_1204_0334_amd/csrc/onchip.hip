@@ -81,6 +81,8 @@ __device__ __forceinline__ uint32_t oc_pair(const OnchipArgs& A, int jk, uint32_
     return (uint32_t)A.cb8[jk] + min(t, t - p8);
 }
 
+// The posterior pairs start at LDS address 0 (the kernel has no static LDS),
+// so a pair's byte offset is its address and the component an immediate.
 __device__ __forceinline__ float lds_at(const float2* L, uint32_t byte) {
     return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(L) + byte);
 }
@@ -89,18 +91,96 @@ __device__ __forceinline__ float* lds_ptr(float2* L, uint32_t byte) {
     return reinterpret_cast<float*>(reinterpret_cast<char*>(L) + byte);
 }
 
+// Messages and sums are carried in base-2 units (LLR times log2(e)), so that
+// exp and log of Eq. 3 are the hardware's 2^x and log2 without a scaling
+// multiply on either side; the channel LLRs are scaled once when read and the
+// posteriors unscaled when written.  The clip at 30 becomes a clip at
+// 30 log2(e).
+constexpr float kClip2 = 43.2808512266689f;   // 30 * log2(e)
+
+__device__ __forceinline__ float clip2(float x) { return __builtin_amdgcn_fmed3f(x, -kClip2, kClip2); }
+
+// Horizontal step (Eq. 3) of one row in base-2 units, in[k] = beta of edge k
+// (|beta| <= 30 log2 e, slots k >= d ignored): each input as the pair
+// (t, q) = (tanh(|beta|/2), 1 - tanh(|beta|/2)) from e = 2^-|beta|,
+// q = 2e / (1 + e), t = 1 - q; exclusive products by a forward-backward
+// sweep over pairs combined as (t_a t_b, q_a + t_a q_b); |alpha_k| =
+// log2((1 + P) / Q).  The same rule as the package decoder's sp_check, with
+// the first and last steps of each sweep written out (no products with the
+// identity pair).
+template <int DC>
+__device__ __forceinline__ void oc_check(const float (&in)[DC], int d, float (&out)[DC]) {
+    float t[DC], q[DC];
+    uint32_t sgn = 0;
+#pragma unroll
+    for (int k = 0; k < DC; ++k) {
+        if (k < d) {
+            const float e = __builtin_amdgcn_exp2f(-fabsf(in[k]));
+            const float r = __builtin_amdgcn_rcpf(1.0f + e);
+            q[k] = 2.0f * (e * r);
+            t[k] = 1.0f - q[k];
+            sgn ^= __float_as_uint(in[k]);
+        } else {
+            t[k] = 1.0f;
+            q[k] = 0.0f;
+        }
+    }
+    // suffix pairs: (sP[k], sQ[k]) over edges k+1 .. DC-1 (sP[DC-1] = 1, sQ[DC-1] = 0)
+    float sP[DC], sQ[DC];
+    sP[DC - 1] = 1.0f;
+    sQ[DC - 1] = 0.0f;
+    if constexpr (DC >= 2) {
+        sP[DC - 2] = t[DC - 1];
+        sQ[DC - 2] = q[DC - 1];
+    }
+#pragma unroll
+    for (int k = DC - 3; k >= 0; --k) {
+        sP[k] = sP[k + 1] * t[k + 1];
+        sQ[k] = fmaf(sQ[k + 1], t[k + 1], q[k + 1]);
+    }
+    // prefix pair (P, Q) over edges 0 .. k-1, combined with the suffix
+    float P = t[0], Q = q[0];
+    float eP[DC], eQ[DC];
+    eP[0] = sP[0];
+    eQ[0] = sQ[0];
+#pragma unroll
+    for (int k = 1; k < DC; ++k) {
+        if (k == DC - 1) {
+            eP[k] = P;
+            eQ[k] = Q;
+        } else {
+            eP[k] = P * sP[k];
+            eQ[k] = fmaf(sQ[k], P, Q);
+            Q = fmaf(q[k], P, Q);
+            P = P * t[k];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < DC; ++k) {
+        const float mag = __builtin_amdgcn_logf((1.0f + eP[k]) * __builtin_amdgcn_rcpf(eQ[k]));
+        out[k] = __uint_as_float(__float_as_uint(mag) | ((sgn ^ __float_as_uint(in[k])) & 0x80000000u));
+    }
+}
+
+// Regular bases with rows of weight <= 6 keep the scaled channel LLRs of the
+// thread's base-row-0 edges in registers (the 3 x 9 rows would spill them);
+// the others read them from the frame's LLRs in L2 when a sum starts.
+constexpr bool oc_mu_in_regs(bool reg, int dc) { return reg && dc <= 6; }
+
 // One iteration: PAR = it & 1.  L of iteration i lives in component i & 1 of
 // each variable's pair, so this iteration reads component 1 - PAR (the
 // previous iteration's sums) and accumulates into component PAR; both are
 // immediate offsets of one address.  The signs read are the previous
 // iteration's decisions: with flag != NULL, a wave with a violated row sets
-// *flag.
+// *flag.  mu0: with oc_mu_in_regs, the scaled channel LLRs of the thread's
+// base-row-0 edges (their variables' sums start there).
 template <int NJ, int NQ, int DC, bool REG, int PAR>
 __device__ __forceinline__ void oc_iteration(const OnchipArgs& A, float2* L, const float* __restrict__ mu,
-                                             float (&al)[NJ][NQ][DC], uint32_t tid8, uint32_t TB8, uint32_t p8,
-                                             uint32_t* flag) {
+                                             float (&al)[NJ][NQ][DC], const float (&mu0)[NQ][DC], uint32_t tid8,
+                                             uint32_t TB8, uint32_t p8, uint32_t* flag) {
     uint64_t viol = 0;
     constexpr uint32_t kOld = 4u * (1 - PAR), kNew = 4u * PAR;
+    constexpr bool kMuInRegs = oc_mu_in_regs(REG, DC);
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
         const int d = REG ? DC : A.deg[j];
@@ -109,7 +189,7 @@ __device__ __forceinline__ void oc_iteration(const OnchipArgs& A, float2* L, con
             const uint32_t s8 = tid8 + (uint32_t)q * TB8;
             if (s8 < p8) {
                 uint32_t va[DC];
-                float in[DC][1];
+                float in[DC];
                 uint64_t par = 0;
 #pragma unroll
                 for (int k = 0; k < DC; ++k) {
@@ -117,28 +197,33 @@ __device__ __forceinline__ void oc_iteration(const OnchipArgs& A, float2* L, con
                         va[k] = oc_pair(A, j * kOcSlots + k, s8, p8);
                         const float x = lds_at(L, va[k] + kOld);
                         par ^= __ballot(x < 0.0f);
-                        in[k][0] = clip30(x - al[j][q][k]);
+                        in[k] = clip2(x - al[j][q][k]);
                     } else {
                         va[k] = 0;
-                        in[k][0] = 0.0f;
+                        in[k] = 0.0f;
                     }
                 }
                 viol |= par;
-                float out[DC][1];
-                sp_check<DC, 1>(in, d, out);
+                float out[DC];
+                oc_check<DC>(in, d, out);
 #pragma unroll
                 for (int k = 0; k < DC; ++k) {
                     if (REG || k < d) {
-                        al[j][q][k] = out[k][0];
+                        al[j][q][k] = out[k];
+                        float* acc = lds_ptr(L, va[k] + kNew);
                         const bool first = REG ? (j == 0) : ((A.first >> (j * kOcSlots + k)) & 1ull);
-                        if (first) {
-                            *lds_ptr(L, va[k] + kNew) = mu[va[k] >> 3] + out[k][0];
+                        if (first && kMuInRegs) {
+                            *acc = mu0[q][k] + out[k];
+                        } else if (first) {
+                            // mu of variable v at byte 4 v of the frame (va = 8 v)
+                            const float m = *reinterpret_cast<const float*>(
+                                reinterpret_cast<const char*>(mu) + (va[k] >> 1));
+                            *acc = m * kLog2e + out[k];
                         } else {
                             // the only update of this variable in this base row: no other
                             // thread touches it before the barrier, so a plain read and
                             // write suffice (LDS float atomics ran the decode 4x slower)
-                            float* acc = lds_ptr(L, va[k] + kNew);
-                            *acc = *acc + out[k][0];
+                            *acc = *acc + out[k];
                         }
                     }
                 }
@@ -154,18 +239,33 @@ __device__ __forceinline__ void oc_iteration(const OnchipArgs& A, float2* L, con
 // REG: every base row has DC nonzero blocks and every block of base row 0 is
 // nonzero (so every base column starts in base row 0); otherwise the row
 // weights and the first blocks of the columns come from the tables.
-template <int NJ, int NQ, int DC, bool REG>
-__global__ void __launch_bounds__(kOcMaxThreads) onchip_block_kernel(const int n, const int p, const OnchipArgs A) {
-    extern __shared__ float2 Lpair[];   // [n]: (L of even iterations, L of odd iterations)
-    __shared__ uint32_t flag[3];
+template <int NJ, int NQ, int DC, bool REG, int MAXT>
+__global__ void __launch_bounds__(MAXT) onchip_block_kernel(const int n, const int p, const OnchipArgs A) {
+    // dynamic LDS: [n] posterior pairs (L of even iterations, L of odd
+    // iterations), then three flag words
+    extern __shared__ float2 Lpair[];
+    uint32_t* flag = reinterpret_cast<uint32_t*>(Lpair + n);
     const int tid = threadIdx.x;
     const int TB = blockDim.x;
     const size_t f0 = (size_t)blockIdx.x * n;
     const float* __restrict__ mu = A.llr + f0;
     // L of "iteration 0" is mu, so that iteration 1 reads beta = clip(mu - 0)
-    for (int v = tid; v < n; v += TB) Lpair[v].x = mu[v];
+    for (int v = tid; v < n; v += TB) Lpair[v].x = mu[v] * kLog2e;
     if (tid < 3) flag[tid] = 0u;
+    const uint32_t p8 = 8u * (uint32_t)p, TB8 = 8u * (uint32_t)TB;
     float al[NJ][NQ][DC];
+    float mu0[NQ][DC];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const uint32_t s8 = 8u * (uint32_t)tid + (uint32_t)q * TB8;
+#pragma unroll
+        for (int k = 0; k < DC; ++k) {
+            mu0[q][k] = 0.0f;
+            if (oc_mu_in_regs(REG, DC) && s8 < p8)
+                mu0[q][k] = *reinterpret_cast<const float*>(reinterpret_cast<const char*>(mu) +
+                                                            (oc_pair(A, k, s8, p8) >> 1)) * kLog2e;
+        }
+    }
 #pragma unroll
     for (int j = 0; j < NJ; ++j)
 #pragma unroll
@@ -174,7 +274,6 @@ __global__ void __launch_bounds__(kOcMaxThreads) onchip_block_kernel(const int n
             for (int k = 0; k < DC; ++k) al[j][q][k] = 0.0f;
     __syncthreads();
 
-    const uint32_t p8 = 8u * (uint32_t)p, TB8 = 8u * (uint32_t)TB;
     int stop = 0;
     // each step: iteration it, then the test of the syndrome of it - 1
     auto step = [&](int it, auto parity) -> bool {
@@ -186,7 +285,7 @@ __global__ void __launch_bounds__(kOcMaxThreads) onchip_block_kernel(const int n
         asm volatile("" : "+v"(tid8));
         const bool syn = A.early && it >= 2;
         if (tid == 0) flag[(it + 1) % 3] = 0u;
-        oc_iteration<NJ, NQ, DC, REG, PAR>(A, Lpair, mu, al, tid8, TB8, p8, syn ? &flag[it % 3] : nullptr);
+        oc_iteration<NJ, NQ, DC, REG, PAR>(A, Lpair, mu, al, mu0, tid8, TB8, p8, syn ? &flag[it % 3] : nullptr);
         if (syn && flag[it % 3] == 0u) {   // the syndrome of iteration it - 1 is zero
             stop = it - 1;
             return true;
@@ -216,7 +315,7 @@ __global__ void __launch_bounds__(kOcMaxThreads) onchip_block_kernel(const int n
             const int d = REG ? DC : A.deg[j];
 #pragma unroll
             for (int q = 0; q < NQ; ++q) {
-                const uint32_t s8 = 8u * (uint32_t)(tid + q * TB);
+                const uint32_t s8 = 8u * (uint32_t)tid + (uint32_t)q * TB8;
                 if (s8 < p8) {
                     uint64_t par = 0;
 #pragma unroll
@@ -234,7 +333,9 @@ __global__ void __launch_bounds__(kOcMaxThreads) onchip_block_kernel(const int n
         conv_out = flag[fw] == 0u ? 1 : 0;
     }
     for (int v = tid; v < n; v += TB) {
-        const float x = Lf[2 * v + comp];
+        // back to natural units; a nonzero x keeps its sign (|x| ln 2 never
+        // rounds to zero), so the decision is that of the sums above
+        const float x = Lf[2 * v + comp] * kLn2;
         A.post[f0 + v] = clip30(x);
         A.bits[f0 + v] = (uint8_t)(x < 0.0f);
     }
@@ -253,12 +354,13 @@ namespace {
 struct Variant {
     int nj, nq, dc;
     bool reg;
+    int maxt;
     const void* fn;
 };
 
-template <int NJ, int NQ, int DC, bool REG>
+template <int NJ, int NQ, int DC, bool REG, int MAXT = kOcMaxThreads>
 constexpr Variant variant() {
-    return Variant{NJ, NQ, DC, REG, reinterpret_cast<const void*>(&onchip_block_kernel<NJ, NQ, DC, REG>)};
+    return Variant{NJ, NQ, DC, REG, MAXT, reinterpret_cast<const void*>(&onchip_block_kernel<NJ, NQ, DC, REG, MAXT>)};
 }
 
 // (base rows, rows per thread and base row, row-weight capacity, regular
@@ -293,8 +395,8 @@ bool choose(const ldpc_graph* g, Choice& c) {
         (void)hipGetLastError();
         return false;
     }
-    const size_t lds = (size_t)D.n * sizeof(float2);
-    if (lds + 64 > (size_t)limit) return false;
+    const size_t lds = (size_t)D.n * sizeof(float2) + 3 * sizeof(uint32_t);   // pairs, flags
+    if (lds > (size_t)limit) return false;
     const Variant* best = nullptr;
     int best_tb = 0;
     for (const Variant& v : kVariants) {
@@ -302,7 +404,7 @@ bool choose(const ldpc_graph* g, Choice& c) {
         if (v.reg && !(reg && v.dc == D.dc_max)) continue;
         const int per = (D.p + v.nq - 1) / v.nq;
         const int tb = (per + 63) / 64 * 64;
-        if (tb > kOcMaxThreads) continue;
+        if (tb > v.maxt) continue;
         // fewest rows per thread, then a regular variant, then the smallest row-weight capacity
         const bool better = !best || v.nq < best->nq ||
                             (v.nq == best->nq && (v.reg > best->reg || (v.reg == best->reg && v.dc < best->dc)));
