@@ -171,10 +171,11 @@ constexpr bool oc_mu_in_regs(bool reg, int dc) { return reg && dc <= 6; }
 // each variable's pair, so this iteration reads component 1 - PAR (the
 // previous iteration's sums) and accumulates into component PAR; both are
 // immediate offsets of one address.  The signs read are the previous
-// iteration's decisions: with flag != NULL, a wave with a violated row sets
-// *flag.  mu0: with oc_mu_in_regs, the scaled channel LLRs of the thread's
+// iteration's decisions: with SYN and flag != NULL, a wave with a violated
+// row sets *flag (SYN = false compiles the test out, for decodes without
+// early stopping).  mu0: with oc_mu_in_regs, the scaled channel LLRs of the thread's
 // base-row-0 edges (their variables' sums start there).
-template <int NJ, int NQ, int DC, bool REG, int PAR>
+template <int NJ, int NQ, int DC, bool REG, int PAR, bool SYN>
 __device__ __forceinline__ void oc_iteration(const OnchipArgs& A, float2* L, const float* __restrict__ mu,
                                              float (&al)[NJ][NQ][DC], const float (&mu0)[NQ][DC], uint32_t tid8,
                                              uint32_t TB8, uint32_t p8, uint32_t* flag) {
@@ -196,7 +197,7 @@ __device__ __forceinline__ void oc_iteration(const OnchipArgs& A, float2* L, con
                     if (REG || k < d) {
                         va[k] = oc_pair(A, j * kOcSlots + k, s8, p8);
                         const float x = lds_at(L, va[k] + kOld);
-                        par ^= __ballot(x < 0.0f);
+                        if (SYN) par ^= __ballot(x < 0.0f);
                         in[k] = clip2(x - al[j][q][k]);
                     } else {
                         va[k] = 0;
@@ -231,7 +232,7 @@ __device__ __forceinline__ void oc_iteration(const OnchipArgs& A, float2* L, con
         }
         // with early stopping (flag != NULL) each wave ORs its verdict on the
         // previous iteration's syndrome in before the last barrier
-        if (j == NJ - 1 && flag && viol != 0ull && (threadIdx.x & 63) == 0) atomicOr(flag, 1u);
+        if (SYN && j == NJ - 1 && flag && viol != 0ull && (threadIdx.x & 63) == 0) atomicOr(flag, 1u);
         __syncthreads();
     }
 }
@@ -276,26 +277,40 @@ __global__ void __launch_bounds__(MAXT) onchip_block_kernel(const int n, const i
 
     int stop = 0;
     // each step: iteration it, then the test of the syndrome of it - 1
-    auto step = [&](int it, auto parity) -> bool {
+    auto step = [&](int it, auto parity, auto early) -> bool {
         constexpr int PAR = decltype(parity)::value;
+        constexpr bool SYN = decltype(early)::value;
         // the edges' offsets do not change between iterations, but holding
         // them would take as many registers as the alphas: the thread index
         // passes through an opaque copy so that they are recomputed
         uint32_t tid8 = 8u * (uint32_t)tid;
         asm volatile("" : "+v"(tid8));
-        const bool syn = A.early && it >= 2;
+        const bool syn = SYN && it >= 2;
         if (tid == 0) flag[(it + 1) % 3] = 0u;
-        oc_iteration<NJ, NQ, DC, REG, PAR>(A, Lpair, mu, al, mu0, tid8, TB8, p8, syn ? &flag[it % 3] : nullptr);
+        oc_iteration<NJ, NQ, DC, REG, PAR, SYN>(A, Lpair, mu, al, mu0, tid8, TB8, p8,
+                                                syn ? &flag[it % 3] : nullptr);
         if (syn && flag[it % 3] == 0u) {   // the syndrome of iteration it - 1 is zero
             stop = it - 1;
             return true;
         }
         return false;
     };
-    for (int it = 1; it <= A.max_iters; it += 2) {
-        if (step(it, std::integral_constant<int, 1>{})) break;
-        if (it + 1 > A.max_iters) break;
-        if (step(it + 1, std::integral_constant<int, 0>{})) break;
+    using Odd = std::integral_constant<int, 1>;
+    using Even = std::integral_constant<int, 0>;
+    if (A.early) {
+        using On = std::true_type;
+        for (int it = 1; it <= A.max_iters; it += 2) {
+            if (step(it, Odd{}, On{})) break;
+            if (it + 1 > A.max_iters) break;
+            if (step(it + 1, Even{}, On{})) break;
+        }
+    } else {
+        using Off = std::false_type;
+        for (int it = 1; it <= A.max_iters; it += 2) {
+            step(it, Odd{}, Off{});
+            if (it + 1 > A.max_iters) break;
+            step(it + 1, Even{}, Off{});
+        }
     }
 
     int iters_out, conv_out;
