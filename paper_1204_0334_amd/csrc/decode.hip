@@ -44,13 +44,17 @@
 #include <mutex>
 #include <vector>
 
+#include "check2.h"
 #include "device.h"
 #include "internal.h"
 #include "onchip.h"
 
 namespace ldpc {
 
-// Convolutional code.  A launch works on a list of "units": check layers
+// Convolutional code.  Its decoders (window and pipeline, ring kernels and
+// the window kernel with the ring in LDS) carry messages in base-2 units
+// (check2.h): channel LLRs are scaled by log2(e) at ingest and posteriors
+// unscaled at output.  A launch works on a list of "units": check layers
 // (check-node launches) or code positions (variable-node launches), with
 // everything that depends on the unit precomputed on the host: its ring slot,
 // its class (index mod T) and the range of positions / layers it exchanges
@@ -1106,7 +1110,7 @@ __global__ void __launch_bounds__(kBlock) conv_cn_kernel(const ConvDesc D, const
 #pragma unroll
         for (int f = 0; f < FPL; ++f) {
             if (ok) {
-                tq_of(in[k][f], t[f][k], q[f][k]);
+                tq2_of(in[k][f], t[f][k], q[f][k]);
                 sgn[f] ^= __float_as_uint(in[k][f]) & 0x80000000u;
             } else {
                 t[f][k] = 1.0f;
@@ -1118,7 +1122,7 @@ __global__ void __launch_bounds__(kBlock) conv_cn_kernel(const ConvDesc D, const
 #pragma unroll
     for (int f = 0; f < FPL; ++f) {
         float mag[DCMAX];
-        boxplus_fb<DCMAX>(t[f], q[f], mag);
+        boxplus2_fb<DCMAX>(t[f], q[f], mag);
 #pragma unroll
         for (int k = 0; k < DCMAX; ++k) {
             const uint32_t sg = sgn[f] ^ (__float_as_uint(in[k][f]) & 0x80000000u);
@@ -1164,7 +1168,7 @@ __device__ __forceinline__ void conv_vn_column(const ConvDesc& D, const ConvSlot
         float pre = 0.0f;
 #pragma unroll
         for (int k = 0; k < DVMAX; ++k) {
-            b[k][f] = clip30(mu[f] + (pre + suf[k]));
+            b[k][f] = clip2(mu[f] + (pre + suf[k]));
             pre += a[k][f];
         }
         L[f] = mu[f] + pre;
@@ -1236,7 +1240,7 @@ __global__ void __launch_bounds__(kOutBlock) conv_vn_out_kernel(const ConvDesc D
     const int64_t oc = (int64_t)U.pos[U.out_unit] * D.c + c0 + var;
     const int nvalid = min(P.gamma - tile * Gt, Gt);
     for (int fr = threadIdx.x / kOutVars; fr < nvalid; fr += kOutBlock / kOutVars) {
-        const float L = Ls[var][fr];
+        const float L = Ls[var][fr] * kLn2F;   // base-2 units to an LLR
         const size_t o = (size_t)(tile * Gt + fr) * ld + oc;
         post[o] = clip30(L);
         bits_out[o] = (uint8_t)(L < 0.0f);
@@ -1276,9 +1280,9 @@ __global__ void __launch_bounds__(kIngestBlock) conv_ingest_kernel(const ConvDes
         const int t = t0 + pu;
         const int q = rem / D.p, uu = rem - q * D.p;
         const int slot = t % U.ring;
-        const float mu = tileS[tx][r];
+        const float mu = tileS[tx][r] * kLog2eF;   // base-2 units
         P.mu[((size_t)tile * U.ring * D.c + (size_t)slot * D.c + rem) * Gt + fl] = mu;
-        const float b = clip30(mu);
+        const float b = clip2(mu);
         const int jc = t % D.T;
         for (int k = 0; k < nslots; ++k) {
             const int dd = S.vn_dd[k], rr = S.vn_rr[k];
@@ -1383,9 +1387,9 @@ __global__ void __launch_bounds__(kWinBlock) window_lds_kernel(const ConvDesc D,
                 const int t = in_lo + pu;
                 const int q = rem / D.p, uu = rem - q * D.p;
                 const int slot = t % R;
-                const float m = x[(int64_t)t * D.c + rem];
+                const float m = x[(int64_t)t * D.c + rem] * kLog2eF;   // base-2 units
                 mu[slot * D.c + rem] = m;
-                const float b = clip30(m);
+                const float b = clip2(m);
                 const int jc = t % D.T;
                 for (int k = 0; k < nvs; ++k) {
                     const int dd = S.vn_dd[k], rr = S.vn_rr[k];
@@ -1455,10 +1459,10 @@ __global__ void __launch_bounds__(kWinBlock) window_lds_kernel(const ConvDesc D,
                     for (int e = 0; e < DCMAX; ++e) in[e] = msg[o[e] + so];
 #pragma unroll
                     for (int e = 0; e < DCMAX; ++e) {
-                        tq_of(in[e], t[e], q[e]);
+                        tq2_of(in[e], t[e], q[e]);
                         sgn ^= __float_as_uint(in[e]) & 0x80000000u;
                     }
-                    boxplus_fb<DCMAX>(t, q, mag);
+                    boxplus2_fb<DCMAX>(t, q, mag);
 #pragma unroll
                     for (int e = 0; e < DCMAX; ++e) {
                         const uint32_t sg = sgn ^ (__float_as_uint(in[e]) & 0x80000000u);
@@ -1479,7 +1483,7 @@ __global__ void __launch_bounds__(kWinBlock) window_lds_kernel(const ConvDesc D,
 #pragma unroll
             for (int e = 0; e < DCMAX; ++e) {
                 if (idx[e] >= 0) {
-                    tq_of(in[e], t[e], q[e]);
+                    tq2_of(in[e], t[e], q[e]);
                     sgn ^= __float_as_uint(in[e]) & 0x80000000u;
                 } else {
                     t[e] = 1.0f;
@@ -1487,7 +1491,7 @@ __global__ void __launch_bounds__(kWinBlock) window_lds_kernel(const ConvDesc D,
                 }
             }
             float mag[DCMAX];
-            boxplus_fb<DCMAX>(t, q, mag);
+            boxplus2_fb<DCMAX>(t, q, mag);
 #pragma unroll
             for (int e = 0; e < DCMAX; ++e) {
                 if (idx[e] >= 0 && u >= cdd[e]) {     // position s + u - dd is not frozen
@@ -1534,12 +1538,12 @@ __global__ void __launch_bounds__(kWinBlock) window_lds_kernel(const ConvDesc D,
                     float pre = 0.0f;
 #pragma unroll
                     for (int e = 0; e < DVMAX; ++e) {
-                        const float b = clip30(m + (pre + suf[e]));
+                        const float b = clip2(m + (pre + suf[e]));
                         pre += a[e];
                         msg[idx[e]] = b;
                     }
                     if (out && u == 0) {
-                        const float L = m + pre;
+                        const float L = (m + pre) * kLn2F;
                         const size_t o = frame_off + (size_t)s * D.c + rem;
                         post[o] = clip30(L);
                         bits_out[o] = (uint8_t)(L < 0.0f);
@@ -1565,12 +1569,12 @@ __global__ void __launch_bounds__(kWinBlock) window_lds_kernel(const ConvDesc D,
             float pre = 0.0f;
 #pragma unroll
             for (int e = 0; e < DVMAX; ++e) {
-                const float b = clip30(m + (pre + suf[e]));
+                const float b = clip2(m + (pre + suf[e]));
                 pre += a[e];
                 if (idx[e] >= 0) msg[idx[e]] = b;
             }
             if (out && u == 0) {
-                const float L = m + pre;
+                const float L = (m + pre) * kLn2F;
                 const size_t o = frame_off + (size_t)s * D.c + rem;
                 post[o] = clip30(L);
                 bits_out[o] = (uint8_t)(L < 0.0f);
@@ -1641,13 +1645,13 @@ __global__ void __launch_bounds__(kWinBlock) window_lds_kernel(const ConvDesc D,
                         float pre_sum = 0.0f;
 #pragma unroll
                         for (int e = 0; e < DVMAX; ++e) {
-                            const float b = clip30(m + (pre_sum + suf[e]));
+                            const float b = clip2(m + (pre_sum + suf[e]));
                             pre_sum += a[e];
                             const int v = vix[j][e];
                             if (v != -1) msg[v >= 0 ? v : -2 - v] = b;
                         }
                         if (k == K && cu0 + j * cstep == 0) {
-                            const float L = m + pre_sum;
+                            const float L = (m + pre_sum) * kLn2F;
                             const size_t o = frame_off + (size_t)s * D.c + crem0;
                             post[o] = clip30(L);
                             bits_out[o] = (uint8_t)(L < 0.0f);

@@ -17,8 +17,8 @@
 //     beta = clip(L_v - alpha_e) (Eq. 4 written as "all but the own edge")
 //     from the previous iteration's sum and the edge's own alpha, so no beta
 //     is stored;
-//   * the check update (Eq. 3) is the same FP32 (t, 1 - t) forward-backward
-//     form as the package decoder (sp_check in device.h).
+//   * the check update (Eq. 3) is the FP32 (t, 1 - t) forward-backward form
+//     of the package decoder, in base-2 units (check2.h).
 //
 // One iteration, for base rows j = 0 .. J-1 in turn (a workgroup barrier
 // after each): every thread updates its rows of base row j from L_old
@@ -46,6 +46,7 @@
 #include <cstring>
 #include <type_traits>
 
+#include "check2.h"
 #include "device.h"
 #include "internal.h"
 #include "onchip.h"
@@ -91,76 +92,9 @@ __device__ __forceinline__ float* lds_ptr(float2* L, uint32_t byte) {
     return reinterpret_cast<float*>(reinterpret_cast<char*>(L) + byte);
 }
 
-// Messages and sums are carried in base-2 units (LLR times log2(e)), so that
-// exp and log of Eq. 3 are the hardware's 2^x and log2 without a scaling
-// multiply on either side; the channel LLRs are scaled once when read and the
-// posteriors unscaled when written.  The clip at 30 becomes a clip at
-// 30 log2(e).
-constexpr float kClip2 = 43.2808512266689f;   // 30 * log2(e)
-
-__device__ __forceinline__ float clip2(float x) { return __builtin_amdgcn_fmed3f(x, -kClip2, kClip2); }
-
-// Horizontal step (Eq. 3) of one row in base-2 units, in[k] = beta of edge k
-// (|beta| <= 30 log2 e, slots k >= d ignored): each input as the pair
-// (t, q) = (tanh(|beta|/2), 1 - tanh(|beta|/2)) from e = 2^-|beta|,
-// q = 2e / (1 + e), t = 1 - q; exclusive products by a forward-backward
-// sweep over pairs combined as (t_a t_b, q_a + t_a q_b); |alpha_k| =
-// log2((1 + P) / Q).  The same rule as the package decoder's sp_check, with
-// the first and last steps of each sweep written out (no products with the
-// identity pair).
-template <int DC>
-__device__ __forceinline__ void oc_check(const float (&in)[DC], int d, float (&out)[DC]) {
-    float t[DC], q[DC];
-    uint32_t sgn = 0;
-#pragma unroll
-    for (int k = 0; k < DC; ++k) {
-        if (k < d) {
-            const float e = __builtin_amdgcn_exp2f(-fabsf(in[k]));
-            const float r = __builtin_amdgcn_rcpf(1.0f + e);
-            q[k] = 2.0f * (e * r);
-            t[k] = 1.0f - q[k];
-            sgn ^= __float_as_uint(in[k]);
-        } else {
-            t[k] = 1.0f;
-            q[k] = 0.0f;
-        }
-    }
-    // suffix pairs: (sP[k], sQ[k]) over edges k+1 .. DC-1 (sP[DC-1] = 1, sQ[DC-1] = 0)
-    float sP[DC], sQ[DC];
-    sP[DC - 1] = 1.0f;
-    sQ[DC - 1] = 0.0f;
-    if constexpr (DC >= 2) {
-        sP[DC - 2] = t[DC - 1];
-        sQ[DC - 2] = q[DC - 1];
-    }
-#pragma unroll
-    for (int k = DC - 3; k >= 0; --k) {
-        sP[k] = sP[k + 1] * t[k + 1];
-        sQ[k] = fmaf(sQ[k + 1], t[k + 1], q[k + 1]);
-    }
-    // prefix pair (P, Q) over edges 0 .. k-1, combined with the suffix
-    float P = t[0], Q = q[0];
-    float eP[DC], eQ[DC];
-    eP[0] = sP[0];
-    eQ[0] = sQ[0];
-#pragma unroll
-    for (int k = 1; k < DC; ++k) {
-        if (k == DC - 1) {
-            eP[k] = P;
-            eQ[k] = Q;
-        } else {
-            eP[k] = P * sP[k];
-            eQ[k] = fmaf(sQ[k], P, Q);
-            Q = fmaf(q[k], P, Q);
-            P = P * t[k];
-        }
-    }
-#pragma unroll
-    for (int k = 0; k < DC; ++k) {
-        const float mag = __builtin_amdgcn_logf((1.0f + eP[k]) * __builtin_amdgcn_rcpf(eQ[k]));
-        out[k] = __uint_as_float(__float_as_uint(mag) | ((sgn ^ __float_as_uint(in[k])) & 0x80000000u));
-    }
-}
+// Messages and sums are carried in base-2 units (check2.h): the channel
+// LLRs are scaled by log2(e) once when read and the posteriors unscaled when
+// written.
 
 // Regular bases with rows of weight <= 6 keep the scaled channel LLRs of the
 // thread's base-row-0 edges in registers (the 3 x 9 rows would spill them);
@@ -206,7 +140,7 @@ __device__ __forceinline__ void oc_iteration(const OnchipArgs& A, float2* L, con
                 }
                 viol |= par;
                 float out[DC];
-                oc_check<DC>(in, d, out);
+                check2_row<DC>(in, d, out);
 #pragma unroll
                 for (int k = 0; k < DC; ++k) {
                     if (REG || k < d) {
@@ -219,7 +153,7 @@ __device__ __forceinline__ void oc_iteration(const OnchipArgs& A, float2* L, con
                             // mu of variable v at byte 4 v of the frame (va = 8 v)
                             const float m = *reinterpret_cast<const float*>(
                                 reinterpret_cast<const char*>(mu) + (va[k] >> 1));
-                            *acc = m * kLog2e + out[k];
+                            *acc = m * kLog2eF + out[k];
                         } else {
                             // the only update of this variable in this base row: no other
                             // thread touches it before the barrier, so a plain read and
@@ -251,7 +185,7 @@ __global__ void __launch_bounds__(MAXT) onchip_block_kernel(const int n, const i
     const size_t f0 = (size_t)blockIdx.x * n;
     const float* __restrict__ mu = A.llr + f0;
     // L of "iteration 0" is mu, so that iteration 1 reads beta = clip(mu - 0)
-    for (int v = tid; v < n; v += TB) Lpair[v].x = mu[v] * kLog2e;
+    for (int v = tid; v < n; v += TB) Lpair[v].x = mu[v] * kLog2eF;
     if (tid < 3) flag[tid] = 0u;
     const uint32_t p8 = 8u * (uint32_t)p, TB8 = 8u * (uint32_t)TB;
     float al[NJ][NQ][DC];
@@ -264,7 +198,7 @@ __global__ void __launch_bounds__(MAXT) onchip_block_kernel(const int n, const i
             mu0[q][k] = 0.0f;
             if (oc_mu_in_regs(REG, DC) && s8 < p8)
                 mu0[q][k] = *reinterpret_cast<const float*>(reinterpret_cast<const char*>(mu) +
-                                                            (oc_pair(A, k, s8, p8) >> 1)) * kLog2e;
+                                                            (oc_pair(A, k, s8, p8) >> 1)) * kLog2eF;
         }
     }
 #pragma unroll
@@ -350,7 +284,7 @@ __global__ void __launch_bounds__(MAXT) onchip_block_kernel(const int n, const i
     for (int v = tid; v < n; v += TB) {
         // back to natural units; a nonzero x keeps its sign (|x| ln 2 never
         // rounds to zero), so the decision is that of the sums above
-        const float x = Lf[2 * v + comp] * kLn2;
+        const float x = Lf[2 * v + comp] * kLn2F;
         A.post[f0 + v] = clip30(x);
         A.bits[f0 + v] = (uint8_t)(x < 0.0f);
     }
