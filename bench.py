@@ -36,13 +36,18 @@ METRIC = "coded Mbit/s at 20 BP iters (n=18360, Γ=1024) + %HBM peak; FER learne
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_qc36_p3060.json")
 TRAFFIC_FILE_4096 = os.path.join(ROOT, "profiles", "traffic_qc36_p3060_g4096.json")
 TRAFFIC_FILE_PIPELINE = os.path.join(ROOT, "profiles", "traffic_cc36_p512_pipeline.json")
+TRAFFIC_FILE_ONCHIP = os.path.join(ROOT, "profiles", "traffic_onchip_qc36_p3060.json")
+# sources a counter record stays valid for: the package kernels (and the
+# convolutional-code kernels) live in decode.hip, the on-chip decoder in onchip.hip
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1204_0334_amd", "csrc", f)
-                  for f in ("decode.hip", "device.h", "internal.h")]
+                  for f in ("decode.hip", "check2.h", "device.h", "internal.h")]
+ONCHIP_SOURCES = [os.path.join(ROOT, "paper_1204_0334_amd", "csrc", f)
+                  for f in ("onchip.hip", "check2.h", "device.h", "internal.h")]
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(files=KERNEL_SOURCES) -> str:
     h = hashlib.sha256()
-    for p in KERNEL_SOURCES:
+    for p in files:
         with open(p, "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -56,7 +61,7 @@ def algorithmic_bytes(n: int, E: int, gamma: int):
     return {"check_node": 8 * E * gamma, "variable_node": (8 * E + 4 * n) * gamma}
 
 
-def measured_traffic(kernel: str, path: str = TRAFFIC_FILE):
+def measured_traffic(kernel: str, path: str = TRAFFIC_FILE, files=KERNEL_SOURCES):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
     was taken on the current kernel sources."""
     try:
@@ -64,7 +69,7 @@ def measured_traffic(kernel: str, path: str = TRAFFIC_FILE):
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("source_hash") != kernel_source_hash():
+    if t.get("source_hash") != kernel_source_hash(files):
         return None
     k = t.get("kernels", {}).get(kernel)
     return None if k is None else k.get("bytes_per_launch")
@@ -807,7 +812,7 @@ def gamma_control(g, llr_dev, iters, gamma, steps=5):
     per_kernel = ldpc.timing_read()
     del out, ws, x
     if per_kernel["onchip_decode"][0]:
-        roof = onchip_roofline(per_kernel, g.info["E"], iters, gamma)
+        roof = onchip_roofline(per_kernel, g.info["E"], iters, gamma, traffic_path=None)
     else:
         algo = algorithmic_bytes(g.n, g.info["E"], gamma)["variable_node"]
         launches, kms = per_kernel["variable_node"]
@@ -821,7 +826,7 @@ def gamma_control(g, llr_dev, iters, gamma, steps=5):
             "roofline": roof}
 
 
-def onchip_roofline(per_kernel, E: int, iters: int, gamma: int):
+def onchip_roofline(per_kernel, E: int, iters: int, gamma: int, traffic_path=TRAFFIC_FILE_ONCHIP):
     """ALU roofline of the block decoder that keeps each frame on one compute
     unit (one launch per decode, no message traffic to HBM): FP32 vector issue
     slots of Eq. 3-5 per launch (check edge 36, variable edge 3, every edge,
@@ -832,7 +837,9 @@ def onchip_roofline(per_kernel, E: int, iters: int, gamma: int):
     ops = iters * E * (CN_EDGE_SLOTS + ONCHIP_VN_EDGE_SLOTS) * gamma
     achieved = ops / avg_s / 1e12
     return {"bound": "alu", "achieved": round(achieved, 2), "peak": round(ALU_PEAK_TOPS, 2), "unit": "Top/s",
-            "frac": round(achieved / ALU_PEAK_TOPS, 4), "traffic": None, "kernel": "onchip_decode",
+            "frac": round(achieved / ALU_PEAK_TOPS, 4),
+            "traffic": measured_traffic("onchip_decode", traffic_path, ONCHIP_SOURCES) if traffic_path else None,
+            "kernel": "onchip_decode",
             "avg_launch_us": round(avg_s * 1e6, 2), "algorithmic_ops_per_launch": ops,
             "note": "FP32 vector issue slots (transcendentals count 4) against the FP32 vector issue rate "
                     "(256 CUs x 128 lanes x 2.4 GHz); each frame's messages stay in registers and LDS of one "
