@@ -503,7 +503,8 @@ def bench_plan(args):
     """Mixed batch through the multi-code plan: 7 QC codes (3 x 6, 3 x 9,
     3 x 18 bases; p from 27 to 3600; 8 to 1024 frames each; 1.75-3.5 dB), 20
     iterations with early stop, one HIP graph per decode (layouts autotuned
-    before timing).  Also times the same batch decoded code by code with
+    before timing; codes that fit a compute unit run the on-chip decoder in a
+    parallel branch).  Also times the same batch decoded code by code with
     ldpc_decode, and the fixed-work (no early stop) plan for the roofline."""
     import torch
 
@@ -583,15 +584,29 @@ def bench_plan(args):
     torch.cuda.synchronize()
     ldpc.timing_enable(False)
     per_kernel = ldpc.timing_read()
+    # the phase launches carry only the codes that do not run on chip
+    paths = [ldpc.decode_path(g) for g in graphs]
+    pk = [i for i, q in enumerate(paths) if q == "packages"]
     E = [g.info["E"] for g in graphs]
     ns = [g.n for g in graphs]
-    algo = {"plan_check_node": sum(8 * e * x for e, x in zip(E, gammas)),
-            "plan_variable_node": sum(((iters - 1) * (8 * e + 4 * n) + 4 * e + 8 * n + n / 8) * x / iters
-                                      for e, n, x in zip(E, ns, gammas))}
+    algo = {"plan_check_node": sum(8 * E[i] * gammas[i] for i in pk),
+            "plan_variable_node": sum(((iters - 1) * (8 * E[i] + 4 * ns[i]) + 4 * E[i] + 8 * ns[i] + ns[i] / 8)
+                                      * gammas[i] / iters for i in pk)}
     dom = max(algo, key=lambda k: per_kernel[k][1])
     launches, kms = per_kernel[dom]
     avg_s = kms / launches * 1e-3
     achieved = algo[dom] / avg_s / 1e9
+    onchip = None
+    oc = [i for i, q in enumerate(paths) if q == "onchip"]
+    if oc and per_kernel["onchip_decode"][0]:
+        # fixed work: every iteration of every frame of the on-chip codes,
+        # over their launches' summed time (they run beside the phase launches)
+        slots = sum(iters * E[i] * (CN_EDGE_SLOTS + ONCHIP_VN_EDGE_SLOTS) * gammas[i] for i in oc)
+        t_s = per_kernel["onchip_decode"][1] * 1e-3 / args.steps
+        onchip = {"bound": "alu", "codes": [i for i in oc], "achieved": round(slots / t_s / 1e12, 2),
+                  "peak": round(ALU_PEAK_TOPS, 2), "unit": "Top/s",
+                  "frac": round(slots / t_s / 1e12 / ALU_PEAK_TOPS, 4),
+                  "launch_us_per_decode": round(t_s * 1e6, 1)}
     cpu = None
     if not args.no_cpu:
         import oracle
@@ -629,7 +644,9 @@ def bench_plan(args):
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
                      "avg_launch_us": round(avg_s * 1e6, 2), "algorithmic_bytes_per_launch": round(algo[dom]),
-                     "note": "fixed-work pass (no early stop) with the tuned layouts"},
+                     "codes": pk, "onchip": onchip,
+                     "note": "fixed-work pass (no early stop) with the tuned layouts, over the codes of the phase "
+                             "launches; codes that fit a compute unit run the on-chip decoder beside them"},
         "cpu_baseline": cpu,
         "kernels": {c: {"launches": v[0], "avg_us": round(v[1] / v[0] * 1e3, 2)} for c, v in per_kernel.items()
                     if v[0]},

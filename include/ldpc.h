@@ -275,11 +275,17 @@ ldpc_status ldpc_nms_train_backward(const ldpc_graph* g, int32_t gamma, int32_t 
 
 /*
  * Multi-code plan: frames of several QC graphs, each with its own batch size,
- * decoded together by the flooding sum-product decoder of ldpc_decode
+ * decoded together by the flooding sum-product decoders of ldpc_decode
  * (Algorithm 1, Eq. 3-6; same arithmetic, so each code's outputs equal
- * ldpc_decode's bit for bit).  One check-node launch and one variable-node
- * launch per iteration cover all codes; the whole decode can be captured
- * once into a HIP graph and replayed.
+ * ldpc_decode's bit for bit).  Codes that ldpc_decode would decode on chip
+ * (ldpc_decode_path; not in persistent mode) run that decoder, one launch
+ * per code on a stream forked from the caller's and joined back before the
+ * decode ends; for the others, one check-node launch and one variable-node
+ * launch per iteration cover all codes.  The whole decode can be captured
+ * once into a HIP graph (the on-chip launches as a parallel branch) and
+ * replayed; which codes run on chip is decided when the plan binds its
+ * buffers, so a change of LDPC_BLOCK_PATH between calls rebuilds the table
+ * and invalidates a captured graph.
  *
  * Layout of a code (frames per tile and rows per wavefront):
  *   LDPC_LAYOUT_G8, _G16, _G32: tiles of 8, 16 or 32 frames, a wavefront

@@ -15,6 +15,10 @@ namespace ldpc {
 // weight and circulant size, and two posterior arrays of n floats in LDS).
 bool onchip_fits(const ldpc_graph* g);
 
+// Whether ldpc_decode decodes g on chip: the graph fits and the environment
+// variable LDPC_BLOCK_PATH is not "packages" (the rule ldpc_decode applies).
+bool onchip_selected(const ldpc_graph* g);
+
 // Enqueues the whole decode (arguments as ldpc_decode; outputs written
 // directly in the caller's layout).  Returns 1 once launched, 0 (having
 // enqueued nothing) when the graph does not fit, -1 when the launch failed.

@@ -376,6 +376,12 @@ bool onchip_fits(const ldpc_graph* g) {
     return choose(g, c);
 }
 
+bool onchip_selected(const ldpc_graph* g) {
+    const char* path = std::getenv("LDPC_BLOCK_PATH");
+    if (path && std::strcmp(path, "packages") == 0) return false;
+    return onchip_fits(g);
+}
+
 int onchip_decode(const ldpc_graph* g, const float* llr, int gamma, int max_iters, int early, float* post,
                   uint8_t* bits, int32_t* iters, uint8_t* converged, hipStream_t st) {
     Choice c;

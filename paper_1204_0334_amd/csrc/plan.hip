@@ -35,6 +35,7 @@
 
 #include "device.h"
 #include "internal.h"
+#include "onchip.h"
 
 namespace ldpc {
 
@@ -1122,6 +1123,12 @@ struct ldpc_plan {
     int persist_grid = 0;                 // workgroups: what fits the device at once
     size_t state_off = 0;                 // PersistState in the workspace
     PersistArgs pa{};
+    // codes decoded by the on-chip block decoder (onchip.hip) instead of the
+    // phase launches: decided when the table is built (phase launches only,
+    // as ldpc_decode decides), launched on a stream forked from the caller's
+    std::vector<uint8_t> onchip;
+    hipStream_t side = nullptr;
+    hipEvent_t fork_ev = nullptr, join_ev = nullptr;
     // graph
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
@@ -1160,8 +1167,16 @@ int persist_items_per_ticket() {
 }
 
 // fill the host table for the current layouts and buffers
+std::vector<uint8_t> onchip_choice(const ldpc_plan* P) {
+    std::vector<uint8_t> v(P->ncodes, 0);
+    if (!P->persistent)
+        for (int c = 0; c < P->ncodes; ++c) v[c] = onchip_selected(P->graphs[c]) ? 1 : 0;
+    return v;
+}
+
 void build_table(ldpc_plan* P, const PlanBuffers& B, char* ws) {
     P->table.assign(P->ncodes, PlanCode{});
+    P->onchip = onchip_choice(P);
     int64_t cn = 0, vn = 0, syn = 0, st = 0, io = 0, red = 0;
     for (int c = 0; c < P->ncodes; ++c) {
         const ldpc_graph* g = P->graphs[c];
@@ -1210,6 +1225,7 @@ void build_table(ldpc_plan* P, const PlanBuffers& B, char* ws) {
         T.io0 = io;
         T.red0 = red;
         T.red_chunks = (int)(((int64_t)T.cn_wpt * T.fpl + kPlanRedWords - 1) / kPlanRedWords);
+        if (P->onchip[c]) continue;   // no work in the phase launches: an empty range in each
         cn += (int64_t)T.tiles * T.cn_wpt;
         vn += (int64_t)T.tiles * T.vn_wpt;
         syn += ((int64_t)T.tiles * g->m + 63) / 64 * 64;
@@ -1262,6 +1278,7 @@ void build_table(ldpc_plan* P, const PlanBuffers& B, char* ws) {
 
 bool same_buffers(const ldpc_plan* P, const PlanBuffers& B, const void* ws) {
     if (!P->table_valid || P->table_ws != ws) return false;
+    if (P->onchip != onchip_choice(P)) return false;
     for (int c = 0; c < P->ncodes; ++c) {
         const PlanCode& T = P->table[c];
         if (T.llr != B.llr[c] || T.post != B.post[c] || T.bits_out != B.bits[c]) return false;
@@ -1275,6 +1292,18 @@ bool same_buffers(const ldpc_plan* P, const PlanBuffers& B, const void* ws) {
 ldpc_status upload_table(ldpc_plan* P, const PlanBuffers& B, char* ws, hipStream_t st) {
     if (same_buffers(P, B, ws)) return LDPC_OK;
     build_table(P, B, ws);
+    bool any = false;
+    for (uint8_t o : P->onchip) any = any || o;
+    if (any && !P->side) {
+        // default priority, like every stream of the library
+        if (hipStreamCreateWithFlags(&P->side, hipStreamNonBlocking) != hipSuccess) {
+            P->side = nullptr;
+            return LDPC_EHIP;
+        }
+        if (hipEventCreateWithFlags(&P->fork_ev, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&P->join_ev, hipEventDisableTiming) != hipSuccess)
+            return LDPC_EHIP;
+    }
     // the table, then the persistent launch's counters (zero)
     std::vector<char> host(P->state_off + sizeof(PersistState), 0);
     std::memcpy(host.data(), P->table.data(), P->table.size() * sizeof(PlanCode));
@@ -1289,8 +1318,11 @@ ldpc_status upload_table(ldpc_plan* P, const PlanBuffers& B, char* ws, hipStream
 
 unsigned blocks_for(int64_t units, int per_block) { return (unsigned)((units + per_block - 1) / per_block); }
 
-// enqueue one whole decode of the plan on st (table already on the device)
-void enqueue(ldpc_plan* P, char* ws, hipStream_t st) {
+void enqueue_phases(ldpc_plan* P, const PlanCode* T, hipStream_t st);
+
+// enqueue one whole decode of the plan on st (table already on the device);
+// false when an on-chip launch could not be made
+bool enqueue(ldpc_plan* P, char* ws, hipStream_t st) {
     const PlanCode* T = reinterpret_cast<const PlanCode*>(ws);
     const int nc = P->ncodes;
     if (P->persistent) {
@@ -1299,8 +1331,32 @@ void enqueue(ldpc_plan* P, char* ws, hipStream_t st) {
         timing::Scope ts(22, st);
         plan_persistent_kernel<<<(unsigned)std::min<int64_t>(P->persist_grid, A.total), kBlock, 0, st>>>(
             T, reinterpret_cast<PersistState*>(ws + P->state_off), A);
-        return;
+        return true;
     }
+    bool ok = true;
+    // codes on chip: one launch each on the side stream, forked from st and
+    // joined back at the end (under capture, a parallel branch of the graph)
+    bool any_onchip = false;
+    for (uint8_t o : P->onchip) any_onchip = any_onchip || o;
+    if (any_onchip) {
+        (void)hipEventRecord(P->fork_ev, st);
+        (void)hipStreamWaitEvent(P->side, P->fork_ev, 0);
+        for (int c = 0; c < nc; ++c) {
+            if (!P->onchip[c]) continue;
+            const PlanCode& H = P->table[c];
+            ok = ok && onchip_decode(P->graphs[c], H.llr, H.gamma, P->max_iters, P->early, H.post, H.bits_out,
+                                     H.iters, H.converged, P->side) > 0;
+        }
+        (void)hipEventRecord(P->join_ev, P->side);
+    }
+    if (P->cn_waves > 0) enqueue_phases(P, T, st);
+    if (any_onchip) (void)hipStreamWaitEvent(st, P->join_ev, 0);
+    return ok;
+}
+
+// the phase launches of the codes that are not decoded on chip
+void enqueue_phases(ldpc_plan* P, const PlanCode* T, hipStream_t st) {
+    const int nc = P->ncodes;
     PlanStep S{0, 0, P->early, P->max_iters};
     {
         timing::Scope ts(17, st);
@@ -1390,6 +1446,9 @@ void ldpc_plan_destroy(ldpc_plan* P) {
     if (!P) return;
     drop_graph(P);
     if (P->cap_stream) (void)hipStreamDestroy(P->cap_stream);
+    if (P->side) (void)hipStreamDestroy(P->side);
+    if (P->fork_ev) (void)hipEventDestroy(P->fork_ev);
+    if (P->join_ev) (void)hipEventDestroy(P->join_ev);
     delete P;
 }
 
@@ -1429,8 +1488,8 @@ ldpc_status ldpc_plan_decode(ldpc_plan* P, const float* const* llr, float* const
     ldpc_status up = upload_table(P, B, ws, st);
     if (up != LDPC_OK) return up;
     if (P->persistent && P->pa.total == 0) return LDPC_EUNSUPPORTED;
-    enqueue(P, ws, st);
-    return hipGetLastError() == hipSuccess ? LDPC_OK : LDPC_EHIP;
+    const bool ok = enqueue(P, ws, st);
+    return ok && hipGetLastError() == hipSuccess ? LDPC_OK : LDPC_EHIP;
 }
 
 ldpc_status ldpc_plan_capture(ldpc_plan* P, const float* const* llr, float* const* post, uint8_t* const* bits,
@@ -1454,8 +1513,9 @@ ldpc_status ldpc_plan_capture(ldpc_plan* P, const float* const* llr, float* cons
     const bool timing_was = timing::set_enabled(false);
     hipError_t e = hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        enqueue(P, ws, P->cap_stream);
+        const bool ok = enqueue(P, ws, P->cap_stream);
         e = hipStreamEndCapture(P->cap_stream, &P->graph);
+        if (e == hipSuccess && !ok) e = hipErrorLaunchFailure;
     }
     timing::set_enabled(timing_was);
     if (e == hipSuccess) e = hipGraphInstantiate(&P->exec, P->graph, nullptr, nullptr, 0);
@@ -1497,10 +1557,11 @@ ldpc_status ldpc_plan_autotune(ldpc_plan* P, const float* const* llr, float* con
         ldpc_status up = upload_table(P, B, ws, st);
         if (up != LDPC_OK) return up;
         if (P->persistent && P->pa.total == 0) return LDPC_EUNSUPPORTED;
-        enqueue(P, ws, st);
+        bool ok = enqueue(P, ws, st);
         float ms = 0.0f;
         if (hipEventRecord(e0, st) != hipSuccess) return LDPC_EHIP;
-        for (int t = 0; t < trials; ++t) enqueue(P, ws, st);
+        for (int t = 0; t < trials; ++t) ok = enqueue(P, ws, st) && ok;
+        if (!ok) return LDPC_EHIP;
         if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
             hipEventElapsedTime(&ms, e0, e1) != hipSuccess || hipGetLastError() != hipSuccess)
             return LDPC_EHIP;
@@ -1512,6 +1573,7 @@ ldpc_status ldpc_plan_autotune(ldpc_plan* P, const float* const* llr, float* con
     double best = 0.0;
     ldpc_status status = measure(best);
     for (int c = 0; c < P->ncodes && status == LDPC_OK; ++c) {
+        if (P->onchip[c]) continue;   // decoded on chip: its lane layout is not used
         const int start = P->layouts[c];
         int keep = start;
         for (int l = 0; l < 192 && status == LDPC_OK; ++l) {

@@ -373,3 +373,50 @@ def test_persistent_wait_expiry_is_reported_and_the_next_decode_is_exact():
     outs = plan.decode(llrs, ws=ws)
     plan.check(ws)
     assert_same(outs, single_code(graphs, llrs, 20, True), "after an expired wait")
+
+
+# ----------------------------------------------------------------------------
+# codes that fit one compute unit run the on-chip block decoder inside the
+# plan (a parallel branch next to the phase launches), as ldpc_decode runs
+# them: the plan's outputs equal ldpc_decode's, bit for bit, on both decoders
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("early", [True, False])
+def test_plan_runs_on_chip_codes_as_the_single_code_decoder(early, monkeypatch):
+    monkeypatch.delenv("LDPC_BLOCK_PATH", raising=False)
+    specs = synth.MIXED_CODES
+    print(f"[gpu] mixed plan with on-chip codes early={early}", flush=True)
+    graphs, llrs = make_case(specs, 7000)
+    paths = [ldpc.decode_path(g) for g in graphs]
+    assert paths.count("onchip") >= 3 and paths.count("packages") >= 2
+    plan = ldpc.Plan(graphs, [c["gamma"] for c in specs], 20, early_stop=early)
+    ws = plan.workspace(DEV)
+    outs = plan.decode(llrs, ws=ws)
+    refs = single_code(graphs, llrs, 20, early)
+    assert_same(outs, refs, "mixed, on-chip codes")
+    # graph replay: three replays with eager work and synchronisation between
+    outs2 = [tuple(torch.empty_like(t) for t in o) for o in outs]
+    plan.capture(llrs, outs2, ws)
+    for rep in range(3):
+        for o in outs2:
+            for t in o:
+                t.zero_()
+        plan.replay()
+        torch.cuda.synchronize()
+        assert_same(outs2, refs, f"replay {rep}")
+        junk = torch.randn(1 << 20, device=DEV).sum()
+        torch.cuda.synchronize()
+        del junk
+    # the same plan after forcing the package decoder: every code in the phase launches
+    monkeypatch.setenv("LDPC_BLOCK_PATH", "packages")
+    assert_same(plan.decode(llrs, ws=ws), single_code(graphs, llrs, 20, early), "mixed, package decoder")
+
+
+def test_plan_of_on_chip_codes_only(monkeypatch):
+    # no code left for the phase launches: the plan is the on-chip launches alone
+    monkeypatch.delenv("LDPC_BLOCK_PATH", raising=False)
+    specs = [c for c in synth.MIXED_CODES if c["L"] == 6][:2]
+    graphs, llrs = make_case(specs, 8000)
+    assert all(ldpc.decode_path(g) == "onchip" for g in graphs)
+    plan = ldpc.Plan(graphs, [c["gamma"] for c in specs], 15, early_stop=True)
+    assert_same(plan.decode(llrs), single_code(graphs, llrs, 15, True), "on-chip codes only")
