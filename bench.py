@@ -99,19 +99,23 @@ def window_algorithmic_bytes(info, W: int, gamma: int):
     return {"window_check_node": cn * gamma / L, "window_variable_node": vn * gamma / L}
 
 
-# Issue slots of the FP32 vector ALUs per edge update (a transcendental --
-# exp, log, reciprocal -- runs at a quarter of the rate, so it counts 4):
-# check edge in the (t, q) form of Eq. 3: 20 plain operations (|beta|, the
-# exponent's scaling, 1 + e, 1 - e, two products, e + e; sign extraction
-# and product; two sweep steps; four for the exclusive pair and its
-# magnitude; the sign of alpha) and 4 transcendentals (exp and reciprocal of
-# the input pair, reciprocal and log of the output) = 36; variable edge: the
-# two partial sums, mu + sum and the clip = 4.
-CN_EDGE_SLOTS = 36
+# Issue slots of the FP32 vector ALUs (a transcendental -- exp2, log2,
+# reciprocal -- issues at a quarter of the rate, so it counts 4) for the
+# check rule the decoders run: Eq. 3 in base-2 units in the (t, q) form.
+# A row of weight d takes, over its edges: the input pairs 4d (1 + e,
+# e * r, q = 2 e r, t = 1 - q), the sign product d - 1, the suffix sweep
+# 2 (d - 2), the prefix sweep with the exclusive complements 3 (d - 2), the
+# output pairs 2d (1 + P, times 1/Q), the output signs 2d: 14d - 11 plain
+# operations, and 4d transcendentals (2^-|x| and 1/(1 + e) of each input,
+# 1/Q and log2 of each output): 30d - 11 slots.  Variable side per edge: the
+# on-chip block decoder forms L = mu + sum alpha and beta = clip(L - alpha)
+# (3: the addition, the subtraction, the clip); the window decoder sums the
+# other edges by prefix and suffix (4: two partial sums, mu + sum, the clip).
+def check_row_slots(d: int) -> int:
+    return 30 * d - 11
+
+
 VN_EDGE_SLOTS = 4
-# The block decoder that keeps a frame on one compute unit forms Eq. 4 and 5
-# as L = mu + sum alpha (one addition per edge) and beta = clip(L - alpha)
-# (a subtraction and the clip per edge): 3 slots per variable edge.
 ONCHIP_VN_EDGE_SLOTS = 3
 # FP32 vector issue rate: 256 CUs x 128 FP32 lanes x 2.4 GHz = 78.6 T lane
 # operations/s (MI355X's 157.3 TFLOP/s FP32 vector figure counts an FMA as
@@ -134,7 +138,10 @@ def window_algorithmic_ops(info, W: int, K: int, gamma: int):
         act = range(s, min(s + W, L))
         e_cn = sum(per_pair for t in lay for d in range(ms + 1) if 0 <= t - d < L)
         e_vn = sum(per_pair for t in act for d in range(ms + 1) if t + d < layers)
-        total += K * (CN_EDGE_SLOTS * e_cn + VN_EDGE_SLOTS * e_vn)
+        # rows of the full weight (ms + 1) Lb; rows at the chain's ends have
+        # fewer edges and are counted at the full rows' cost per edge
+        dfull = (ms + 1) * info["Lb"]
+        total += K * (check_row_slots(dfull) * e_cn / dfull + VN_EDGE_SLOTS * e_vn)
     return total * gamma
 
 
@@ -601,7 +608,8 @@ def bench_plan(args):
     if oc and per_kernel["onchip_decode"][0]:
         # fixed work: every iteration of every frame of the on-chip codes,
         # over their launches' summed time (they run beside the phase launches)
-        slots = sum(iters * E[i] * (CN_EDGE_SLOTS + ONCHIP_VN_EDGE_SLOTS) * gammas[i] for i in oc)
+        slots = sum(iters * gammas[i] * (onchip_row_slots(shifts[i], specs[i]["p"]) + ONCHIP_VN_EDGE_SLOTS * E[i])
+                    for i in oc)
         t_s = per_kernel["onchip_decode"][1] * 1e-3 / args.steps
         onchip = {"bound": "alu", "codes": [i for i in oc], "achieved": round(slots / t_s / 1e12, 2),
                   "peak": round(ALU_PEAK_TOPS, 2), "unit": "Top/s",
@@ -798,7 +806,7 @@ def early_stop_sweep(g, gamma, iters, points, steps=5):
     return rows
 
 
-def gamma_control(g, llr_dev, iters, gamma, steps=5):
+def gamma_control(g, shifts, llr_dev, iters, gamma, steps=5):
     """The benchmark decode at a larger batch (frames repeated from the
     benchmark batch) on the decoder ldpc_decode currently selects.  For the
     message-package decoder its working set exceeds the 256 MB Infinity
@@ -829,7 +837,7 @@ def gamma_control(g, llr_dev, iters, gamma, steps=5):
     per_kernel = ldpc.timing_read()
     del out, ws, x
     if per_kernel["onchip_decode"][0]:
-        roof = onchip_roofline(per_kernel, g.info["E"], iters, gamma, traffic_path=None)
+        roof = onchip_roofline(per_kernel, shifts, g.info["p"], g.info["E"], iters, gamma, traffic_path=None)
     else:
         algo = algorithmic_bytes(g.n, g.info["E"], gamma)["variable_node"]
         launches, kms = per_kernel["variable_node"]
@@ -843,24 +851,32 @@ def gamma_control(g, llr_dev, iters, gamma, steps=5):
             "roofline": roof}
 
 
-def onchip_roofline(per_kernel, E: int, iters: int, gamma: int, traffic_path=TRAFFIC_FILE_ONCHIP):
+def onchip_row_slots(shifts, p: int) -> int:
+    """Check-rule issue slots of one iteration of one frame of the QC code
+    with this shift table: p rows of each base row, check_row_slots(weight)
+    each (the weight: the base row's nonzero blocks)."""
+    import numpy as np
+    return sum(p * check_row_slots(int(d)) for d in (np.asarray(shifts) >= 0).sum(1))
+
+
+def onchip_roofline(per_kernel, shifts, p: int, E: int, iters: int, gamma: int, traffic_path=TRAFFIC_FILE_ONCHIP):
     """ALU roofline of the block decoder that keeps each frame on one compute
     unit (one launch per decode, no message traffic to HBM): FP32 vector issue
-    slots of Eq. 3-5 per launch (check edge 36, variable edge 3, every edge,
-    every iteration, every frame) over the launch time, against the FP32
-    vector issue rate."""
+    slots of Eq. 3-5 per launch (check_row_slots per row, 3 per variable
+    edge; every iteration, every frame) over the launch time, against the
+    FP32 vector issue rate."""
     launches, ms = per_kernel["onchip_decode"]
     avg_s = ms / launches * 1e-3
-    ops = iters * E * (CN_EDGE_SLOTS + ONCHIP_VN_EDGE_SLOTS) * gamma
+    ops = iters * gamma * (onchip_row_slots(shifts, p) + ONCHIP_VN_EDGE_SLOTS * E)
     achieved = ops / avg_s / 1e12
     return {"bound": "alu", "achieved": round(achieved, 2), "peak": round(ALU_PEAK_TOPS, 2), "unit": "Top/s",
             "frac": round(achieved / ALU_PEAK_TOPS, 4),
             "traffic": measured_traffic("onchip_decode", traffic_path, ONCHIP_SOURCES) if traffic_path else None,
             "kernel": "onchip_decode",
             "avg_launch_us": round(avg_s * 1e6, 2), "algorithmic_ops_per_launch": ops,
-            "note": "FP32 vector issue slots (transcendentals count 4) against the FP32 vector issue rate "
-                    "(256 CUs x 128 lanes x 2.4 GHz); each frame's messages stay in registers and LDS of one "
-                    "compute unit"}
+            "note": "FP32 vector issue slots of the check rule (30 d - 11 per row of weight d, transcendentals "
+                    "count 4) and 3 per variable edge, against the FP32 vector issue rate (256 CUs x 128 lanes x "
+                    "2.4 GHz); each frame's messages stay in registers and LDS of one compute unit"}
 
 
 def package_roofline(per_kernel, n: int, E: int, gamma: int):
@@ -1011,7 +1027,7 @@ def main():
     ms_per_step, per_kernel, conv_rate = time_block_decode(g, llr, iters, gamma, args.steps, args.warmup)
     value = gamma * n / (ms_per_step * 1e-3) / 1e6
     if path == "onchip":
-        roofline = onchip_roofline(per_kernel, E, iters, gamma)
+        roofline = onchip_roofline(per_kernel, shifts, p, E, iters, gamma)
     else:
         roofline = package_roofline(per_kernel, n, E, gamma)
     kernels = {k: {"launches": v[0], "avg_us": round(v[1] / v[0] * 1e3, 2)} for k, v in per_kernel.items() if v[0]}
@@ -1025,7 +1041,7 @@ def main():
                     "kernels": {k: {"launches": v[0], "avg_us": round(v[1] / v[0] * 1e3, 2)}
                                 for k, v in pk_kernels.items() if v[0]}}
         if args.extras:
-            packages["gamma_control"] = gamma_control(g, llr, iters, 4096)
+            packages["gamma_control"] = gamma_control(g, shifts, llr, iters, 4096)
         os.environ.pop("LDPC_BLOCK_PATH", None)
 
     learned = None
@@ -1038,7 +1054,7 @@ def main():
                                "fer_sp30": r["sp30"]["fer"], "avg_iters_learned": r["learned_nms"]["avg_iters"],
                                "avg_iters_sp30": r["sp30"]["avg_iters"]} for r in learned["points"]]}
     sweep = early_stop_sweep(g, gamma, iters, [1.0, 1.25, 1.5, 1.75, 2.0, 2.25, 2.5]) if args.extras else None
-    control = gamma_control(g, llr, iters, 4096) if args.extras else None
+    control = gamma_control(g, shifts, llr, iters, 4096) if args.extras else None
     if control is not None and path != "onchip":
         roofline["gamma_4096"] = control["roofline"]
     if packages is not None and "gamma_control" in packages:
