@@ -1334,7 +1334,10 @@ __device__ __forceinline__ int div_small(int a, int b, float inv_b) {
     return q;
 }
 
-template <int DCMAX, int DVMAX>
+// FIX: the host has checked that the block size is a multiple of the rows
+// per layer and of the columns per position, so only the paths that split a
+// thread's rows and columns once are compiled (fewer live registers).
+template <int DCMAX, int DVMAX, bool FIX>
 __global__ void __launch_bounds__(kWinBlock) window_lds_kernel(const ConvDesc D, const ConvSlots S, int R, int W,
                                                                int K, const float* __restrict__ llr,
                                                                float* __restrict__ post, uint8_t* __restrict__ bits_out) {
@@ -1367,7 +1370,7 @@ __global__ void __launch_bounds__(kWinBlock) window_lds_kernel(const ConvDesc D,
     // position), a thread's rows (columns) r = threadIdx.x + j * kWinBlock
     // all have the same offset within their layer (position) and consecutive
     // units kWinBlock / per apart: split once here.
-    const bool rows_fixed = kWinBlock % per == 0, cols_fixed = kWinBlock % D.c == 0;
+    const bool rows_fixed = FIX || kWinBlock % per == 0, cols_fixed = FIX || kWinBlock % D.c == 0;
     const int rstep = rows_fixed ? kWinBlock / per : 1, cstep = cols_fixed ? kWinBlock / D.c : 1;
     const int ru0 = threadIdx.x / per, rrem0 = threadIdx.x - ru0 * per;
     const int rr0 = rrem0 / D.p, so0 = rrem0 - rr0 * D.p;
@@ -2350,14 +2353,20 @@ static bool launch_window_lds(const ldpc_graph* g, const float* llr, int gamma, 
     // row and column indices of a window stay below 2^22 (div_small)
     const int wl = std::min(W, g->positions + g->ms);
     if ((int64_t)wl * std::max(g->Jb, g->Lb) * g->p >= ((int64_t)1 << 22)) return false;
-    const void* fn = reinterpret_cast<const void*>(&window_lds_kernel<DC, DV>);
+    const bool fix = kWinBlock % (g->Jb * g->p) == 0 && kWinBlock % (g->Lb * g->p) == 0;
+    const void* fn = fix ? reinterpret_cast<const void*>(&window_lds_kernel<DC, DV, true>)
+                         : reinterpret_cast<const void*>(&window_lds_kernel<DC, DV, false>);
     if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) {
         (void)hipGetLastError();
         return false;
     }
     timing::Scope ts(21, st);
-    window_lds_kernel<DC, DV><<<(unsigned)gamma, kWinBlock, bytes, st>>>(g->cv, conv_slots(g), R, W, K, llr, post,
-                                                                         bits);
+    if (fix)
+        window_lds_kernel<DC, DV, true><<<(unsigned)gamma, kWinBlock, bytes, st>>>(g->cv, conv_slots(g), R, W, K, llr,
+                                                                                   post, bits);
+    else
+        window_lds_kernel<DC, DV, false><<<(unsigned)gamma, kWinBlock, bytes, st>>>(g->cv, conv_slots(g), R, W, K,
+                                                                                    llr, post, bits);
     return true;
 }
 
