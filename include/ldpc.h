@@ -170,8 +170,8 @@ ldpc_status ldpc_decode(const ldpc_graph* g, const float* llr, int32_t gamma, in
                         uint8_t* converged, void* workspace, size_t workspace_bytes, void* stream);
 
 /*
- * Which decoder ldpc_decode (and ldpc_decode_noalloc) runs for g on the
- * current device: *onchip = 1 when each frame is decoded by one workgroup
+ * Which decoder ldpc_decode (and ldpc_decode_noalloc, ldpc_nms_decode) runs
+ * for g on the current device: *onchip = 1 when each frame is decoded by one workgroup
  * on one compute unit, its check-to-variable messages in registers and its
  * posterior sums in LDS (a (3,6) code up to n = 18,432; codes whose base
  * has 3 rows of weight <= 9 or 4 rows of weight <= 8, no empty base column,
@@ -229,8 +229,10 @@ ldpc_status ldpc_decode_noalloc(const ldpc_graph* g, const float* llr, int32_t g
  *            class
  *   iters    iterations, 1..LDPC_MAX_ITERS (the weight rows used)
  * Other arguments as for ldpc_decode (workspace from
- * ldpc_workspace_size(g, gamma, iters, 0)).  Errors: those of ldpc_decode,
- * and EINVAL for NULL weights.
+ * ldpc_workspace_size(g, gamma, iters, 0)).  Like ldpc_decode it decodes a
+ * code that fits one compute unit on chip (ldpc_decode_path; the rule above
+ * in base-2 units there, within FP32 rounding of the package decoder's).
+ * Errors: those of ldpc_decode, and EINVAL for NULL weights.
  */
 ldpc_status ldpc_nms_decode(const ldpc_graph* g, const float* llr, int32_t gamma, int32_t iters,
                             const float* weights, int32_t early_stop, float* post, uint8_t* bits,

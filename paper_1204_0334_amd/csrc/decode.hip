@@ -2440,10 +2440,12 @@ static ldpc_status decode_block(const ldpc_graph* g, const float* llr, int32_t g
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     char* ws = reinterpret_cast<char*>(workspace);
     (void)hipGetLastError();
-    // sum-product decodes of codes that fit one compute unit run on chip
-    // (onchip.hip); LDPC_BLOCK_PATH=packages keeps them on this decoder
-    if (!nms_w && !packages_forced()) {
-        const int r = onchip_decode(g, llr, gamma, max_iters, early_stop ? 1 : 0, post, bits, iters, converged, st);
+    // decodes of codes that fit one compute unit run on chip (onchip.hip),
+    // sum-product and learned min-sum alike; LDPC_BLOCK_PATH=packages keeps
+    // them on this decoder
+    if (!packages_forced()) {
+        const int r = onchip_decode(g, llr, gamma, max_iters, early_stop ? 1 : 0, post, bits, iters, converged, st,
+                                    nms_w);
         if (r != 0) return r > 0 && hipGetLastError() == hipSuccess ? LDPC_OK : LDPC_EHIP;
     }
     switch (tl.fpl) {

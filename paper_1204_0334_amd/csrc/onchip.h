@@ -20,9 +20,11 @@ bool onchip_fits(const ldpc_graph* g);
 bool onchip_selected(const ldpc_graph* g);
 
 // Enqueues the whole decode (arguments as ldpc_decode; outputs written
-// directly in the caller's layout).  Returns 1 once launched, 0 (having
-// enqueued nothing) when the graph does not fit, -1 when the launch failed.
+// directly in the caller's layout; nms_w: NULL for sum-product, else the
+// learned min-sum weights of ldpc_nms_decode).  Returns 1 once launched, 0
+// (having enqueued nothing) when the graph does not fit, -1 when the launch
+// failed.
 int onchip_decode(const ldpc_graph* g, const float* llr, int gamma, int max_iters, int early, float* post,
-                  uint8_t* bits, int32_t* iters, uint8_t* converged, hipStream_t st);
+                  uint8_t* bits, int32_t* iters, uint8_t* converged, hipStream_t st, const float* nms_w = nullptr);
 
 }  // namespace ldpc

@@ -72,6 +72,11 @@ struct OnchipArgs {
     int32_t sh8[kOcRows * kOcSlots];
     int32_t deg[kOcRows];   // nonzero blocks of base row j
     uint64_t first;         // bit j * kOcSlots + k: the lowest nonzero block of its base column
+    // learned min-sum (RULE 1): weights [iters][blocks][2] (scale, offset in
+    // natural units), the number of blocks, the first block of each base row
+    const float* nms_w;
+    int32_t nb;
+    int32_t rb0[kOcRows];
 };
 
 // Byte offset of the posterior pair of the variable that edge slot jk of
@@ -96,6 +101,41 @@ __device__ __forceinline__ float* lds_ptr(float2* L, uint32_t byte) {
 // LLRs are scaled by log2(e) once when read and the posteriors unscaled when
 // written.
 
+// Learned min-sum rule (the package decoder's RULE 1) in base-2 units:
+// alpha_k = w_k s_k max(m_k - b_k, 0), m_k the smallest |beta| of the row's
+// other edges (|beta| <= 30 log2 e already), s_k the product of their signs
+// (negative iff beta < 0); w[2k], w[2k+1] = (scale, offset) of slot k's
+// block, the offset in natural units (scaled here).
+template <int DC>
+__device__ __forceinline__ void nms2_row(const float (&in)[DC], int d, const float* __restrict__ w,
+                                         float (&out)[DC]) {
+    float min1 = __builtin_inff(), min2 = __builtin_inff();
+    int idx1 = -1;
+    uint32_t parity = 0;
+#pragma unroll
+    for (int k = 0; k < DC; ++k) {
+        if (k < d) {
+            const float m = fabsf(in[k]);
+            if (m < min1) {
+                min2 = min1;
+                min1 = m;
+                idx1 = k;
+            } else if (m < min2) {
+                min2 = m;
+            }
+            parity ^= (uint32_t)(in[k] < 0.0f);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < DC; ++k) {
+        if (k < d) {
+            const float m = k == idx1 ? min2 : min1;
+            const float a = w[2 * k] * fmaxf(m - w[2 * k + 1] * kLog2eF, 0.0f);
+            out[k] = (parity ^ (uint32_t)(in[k] < 0.0f)) ? -a : a;
+        }
+    }
+}
+
 // Regular bases with rows of weight <= 6 keep the scaled channel LLRs of the
 // thread's base-row-0 edges in registers (the 3 x 9 rows would spill them);
 // the others read them from the frame's LLRs in L2 when a sum starts.
@@ -109,10 +149,10 @@ constexpr bool oc_mu_in_regs(bool reg, int dc) { return reg && dc <= 6; }
 // row sets *flag (SYN = false compiles the test out, for decodes without
 // early stopping).  mu0: with oc_mu_in_regs, the scaled channel LLRs of the thread's
 // base-row-0 edges (their variables' sums start there).
-template <int NJ, int NQ, int DC, bool REG, int PAR, bool SYN>
+template <int NJ, int NQ, int DC, bool REG, int RULE, int PAR, bool SYN>
 __device__ __forceinline__ void oc_iteration(const OnchipArgs& A, float2* L, const float* __restrict__ mu,
                                              float (&al)[NJ][NQ][DC], const float (&mu0)[NQ][DC], uint32_t tid8,
-                                             uint32_t TB8, uint32_t p8, uint32_t* flag) {
+                                             uint32_t TB8, uint32_t p8, uint32_t* flag, const float* wit) {
     uint64_t viol = 0;
     constexpr uint32_t kOld = 4u * (1 - PAR), kNew = 4u * PAR;
     constexpr bool kMuInRegs = oc_mu_in_regs(REG, DC);
@@ -140,7 +180,10 @@ __device__ __forceinline__ void oc_iteration(const OnchipArgs& A, float2* L, con
                 }
                 viol |= par;
                 float out[DC];
-                check2_row<DC>(in, d, out);
+                if constexpr (RULE == 0)
+                    check2_row<DC>(in, d, out);
+                else
+                    nms2_row<DC>(in, d, wit + 2 * A.rb0[j], out);
 #pragma unroll
                 for (int k = 0; k < DC; ++k) {
                     if (REG || k < d) {
@@ -174,7 +217,7 @@ __device__ __forceinline__ void oc_iteration(const OnchipArgs& A, float2* L, con
 // REG: every base row has DC nonzero blocks and every block of base row 0 is
 // nonzero (so every base column starts in base row 0); otherwise the row
 // weights and the first blocks of the columns come from the tables.
-template <int NJ, int NQ, int DC, bool REG, int MAXT>
+template <int NJ, int NQ, int DC, bool REG, int RULE, int MAXT>
 __global__ void __launch_bounds__(MAXT) onchip_block_kernel(const int n, const int p, const OnchipArgs A) {
     // dynamic LDS: [n] posterior pairs (L of even iterations, L of odd
     // iterations), then three flag words
@@ -221,8 +264,9 @@ __global__ void __launch_bounds__(MAXT) onchip_block_kernel(const int n, const i
         asm volatile("" : "+v"(tid8));
         const bool syn = SYN && it >= 2;
         if (tid == 0) flag[(it + 1) % 3] = 0u;
-        oc_iteration<NJ, NQ, DC, REG, PAR, SYN>(A, Lpair, mu, al, mu0, tid8, TB8, p8,
-                                                syn ? &flag[it % 3] : nullptr);
+        const float* wit = RULE == 1 ? A.nms_w + (size_t)(it - 1) * A.nb * 2 : nullptr;
+        oc_iteration<NJ, NQ, DC, REG, RULE, PAR, SYN>(A, Lpair, mu, al, mu0, tid8, TB8, p8,
+                                                      syn ? &flag[it % 3] : nullptr, wit);
         if (syn && flag[it % 3] == 0u) {   // the syndrome of iteration it - 1 is zero
             stop = it - 1;
             return true;
@@ -303,13 +347,14 @@ namespace {
 struct Variant {
     int nj, nq, dc;
     bool reg;
-    int maxt;
+    int rule, maxt;
     const void* fn;
 };
 
-template <int NJ, int NQ, int DC, bool REG, int MAXT = kOcMaxThreads>
+template <int NJ, int NQ, int DC, bool REG, int RULE = 0, int MAXT = kOcMaxThreads>
 constexpr Variant variant() {
-    return Variant{NJ, NQ, DC, REG, MAXT, reinterpret_cast<const void*>(&onchip_block_kernel<NJ, NQ, DC, REG, MAXT>)};
+    return Variant{NJ, NQ, DC, REG, RULE, MAXT,
+                   reinterpret_cast<const void*>(&onchip_block_kernel<NJ, NQ, DC, REG, RULE, MAXT>)};
 }
 
 // (base rows, rows per thread and base row, row-weight capacity, regular
@@ -322,6 +367,12 @@ const Variant kVariants[] = {
     variant<3, 1, 6, false>(), variant<3, 2, 6, false>(), variant<3, 3, 6, false>(),
     variant<3, 1, 9, false>(), variant<3, 2, 9, false>(),
     variant<4, 1, 8, false>(),
+    // learned min-sum
+    variant<3, 1, 6, true, 1>(),  variant<3, 2, 6, true, 1>(),  variant<3, 3, 6, true, 1>(),
+    variant<3, 1, 9, true, 1>(),  variant<3, 2, 9, true, 1>(),
+    variant<3, 1, 6, false, 1>(), variant<3, 2, 6, false, 1>(), variant<3, 3, 6, false, 1>(),
+    variant<3, 1, 9, false, 1>(), variant<3, 2, 9, false, 1>(),
+    variant<4, 1, 8, false, 1>(),
 };
 
 struct Choice {
@@ -330,7 +381,7 @@ struct Choice {
     size_t lds;
 };
 
-bool choose(const ldpc_graph* g, Choice& c) {
+bool choose(const ldpc_graph* g, int rule, Choice& c) {
     if (!g || g->kind != LDPC_GRAPH_QC) return false;
     const QCDesc& D = g->qc;
     if (D.J > kOcRows || D.dc_max > kOcSlots) return false;
@@ -349,7 +400,7 @@ bool choose(const ldpc_graph* g, Choice& c) {
     const Variant* best = nullptr;
     int best_tb = 0;
     for (const Variant& v : kVariants) {
-        if (v.nj != D.J || v.dc < D.dc_max) continue;
+        if (v.rule != rule || v.nj != D.J || v.dc < D.dc_max) continue;
         if (v.reg && !(reg && v.dc == D.dc_max)) continue;
         const int per = (D.p + v.nq - 1) / v.nq;
         const int tb = (per + 63) / 64 * 64;
@@ -373,7 +424,7 @@ bool choose(const ldpc_graph* g, Choice& c) {
 
 bool onchip_fits(const ldpc_graph* g) {
     Choice c;
-    return choose(g, c);
+    return choose(g, 0, c);
 }
 
 bool onchip_selected(const ldpc_graph* g) {
@@ -383,9 +434,9 @@ bool onchip_selected(const ldpc_graph* g) {
 }
 
 int onchip_decode(const ldpc_graph* g, const float* llr, int gamma, int max_iters, int early, float* post,
-                  uint8_t* bits, int32_t* iters, uint8_t* converged, hipStream_t st) {
+                  uint8_t* bits, int32_t* iters, uint8_t* converged, hipStream_t st, const float* nms_w) {
     Choice c;
-    if (!choose(g, c)) return 0;
+    if (!choose(g, nms_w ? 1 : 0, c)) return 0;
     const QCDesc& D = g->qc;
     OnchipArgs A{};
     A.llr = llr;
@@ -395,8 +446,11 @@ int onchip_decode(const ldpc_graph* g, const float* llr, int gamma, int max_iter
     A.conv = converged;
     A.max_iters = max_iters;
     A.early = early;
+    A.nms_w = nms_w;
+    A.nb = D.nb;
     for (int j = 0; j < D.J; ++j) {
         A.deg[j] = D.rstart[j + 1] - D.rstart[j];
+        A.rb0[j] = D.rstart[j];
         for (int k = 0; k < A.deg[j]; ++k) {
             const int b = D.rstart[j] + k;
             A.cb8[j * kOcSlots + k] = 8 * D.ecol[b] * D.p;

@@ -47,8 +47,21 @@ def ref_graph(a, p):
 NB36, NB318 = 18, 54   # edge classes (circulant blocks) of the 3 x 6 and 3 x 18 bases
 
 
+@pytest.fixture(params=["onchip", "packages"])
+def block_path(request, monkeypatch):
+    """Runs a decoding test on both decoders behind ldpc_nms_decode: the
+    default (each frame on one compute unit where the code fits) and the
+    message-package decoder (LDPC_BLOCK_PATH=packages, read at each call)."""
+    if request.param == "packages":
+        monkeypatch.setenv("LDPC_BLOCK_PATH", "packages")
+    else:
+        monkeypatch.delenv("LDPC_BLOCK_PATH", raising=False)
+    return request.param
+
+
 def gpu_nms(g, llr, w, early=False):
-    print(f"[gpu] nms_decode n={g.n} gamma={llr.shape[0]} T={w.shape[0]} early={early}", flush=True)
+    print(f"[gpu] nms_decode n={g.n} gamma={llr.shape[0]} T={w.shape[0]} early={early} path={ldpc.decode_path(g)}",
+          flush=True)
     x = torch.from_numpy(np.ascontiguousarray(llr)).to(DEV)
     wt = torch.from_numpy(np.ascontiguousarray(w)).to(DEV)
     post, bits, it, conv = ldpc.nms_decode(g, x, wt, early_stop=early)
@@ -67,6 +80,7 @@ def check_decode(gpu, ref, what):
     assert err.max() <= TOL, f"{what}: posterior error {err.max():.3e}"
 
 
+@pytest.mark.usefixtures("block_path")
 @pytest.mark.parametrize("T,gamma", [(1, 64), (3, 64), (12, 64), (12, 200), (4, 1), (5, 65)])
 def test_nms_decode_matches_reference(T, gamma):
     a, llr = case(3, 6, 64, 1, gamma, 2.0, 101)
@@ -85,6 +99,7 @@ def test_nms_decode_wide_rows():
     check_decode(gpu_nms(ldpc.Graph.qc(a, 36), llr, w), ref, "3x18")
 
 
+@pytest.mark.usefixtures("block_path")
 def test_nms_early_stop_returns_the_stopping_iteration():
     a, llr = case(3, 6, 64, 1, 64, 2.0, 101)
     g = ldpc.Graph.qc(a, 64)
@@ -178,6 +193,7 @@ def test_gradient_wide_rows():
     check_grad(gg, gw, gb, "3x18")
 
 
+@pytest.mark.usefixtures("block_path")
 def test_irregular_base_decode_and_gradient():
     # zero blocks: base rows with 4 and 5 blocks, columns with 1 to 3, so an
     # edge slot of a row is not its block's base column
