@@ -70,6 +70,12 @@ struct OnchipArgs {
     // sh8 = 8 a
     int32_t cb8[kOcRows * kOcSlots];
     int32_t sh8[kOcRows * kOcSlots];
+    // regular bases with rows of weight <= 6 (oc_mu_in_regs) store base
+    // column l rotated by base row 0's shift a_0l: variable (l, t) at pair
+    // l p + (t - a_0l) mod p, so a row of base row 0 meets its variables at
+    // l p + s (no wrap); rot8[l] = 8 a_0l, 0 otherwise, and sh8 holds the
+    // shifts relative to it
+    int32_t rot8[kOcSlots];
     int32_t deg[kOcRows];   // nonzero blocks of base row j
     uint64_t first;         // bit j * kOcSlots + k: the lowest nonzero block of its base column
     // learned min-sum (RULE 1): weights [iters][blocks][2] (scale, offset in
@@ -82,6 +88,8 @@ struct OnchipArgs {
 // Byte offset of the posterior pair of the variable that edge slot jk of
 // row (j, s) meets, from s8 = 8 s: one wrap of s + shift (unsigned min picks
 // t - p exactly when t >= p).
+__device__ __forceinline__ uint32_t oc_wrap8(uint32_t t, uint32_t p8) { return min(t, t - p8); }
+
 __device__ __forceinline__ uint32_t oc_pair(const OnchipArgs& A, int jk, uint32_t s8, uint32_t p8) {
     const uint32_t t = s8 + (uint32_t)A.sh8[jk];
     return (uint32_t)A.cb8[jk] + min(t, t - p8);
@@ -169,7 +177,9 @@ __device__ __forceinline__ void oc_iteration(const OnchipArgs& A, float2* L, con
 #pragma unroll
                 for (int k = 0; k < DC; ++k) {
                     if (REG || k < d) {
-                        va[k] = oc_pair(A, j * kOcSlots + k, s8, p8);
+                        // rotated columns: base row 0 meets pair l p + s
+                        va[k] = (kMuInRegs && j == 0) ? (uint32_t)A.cb8[k] + s8
+                                                      : oc_pair(A, j * kOcSlots + k, s8, p8);
                         const float x = lds_at(L, va[k] + kOld);
                         if (SYN) par ^= __ballot(x < 0.0f);
                         in[k] = clip2(x - al[j][q][k]);
@@ -228,7 +238,19 @@ __global__ void __launch_bounds__(MAXT) onchip_block_kernel(const int n, const i
     const size_t f0 = (size_t)blockIdx.x * n;
     const float* __restrict__ mu = A.llr + f0;
     // L of "iteration 0" is mu, so that iteration 1 reads beta = clip(mu - 0)
-    for (int v = tid; v < n; v += TB) Lpair[v].x = mu[v] * kLog2eF;
+    if constexpr (oc_mu_in_regs(REG, DC)) {
+        // rotated columns (pair l p + u holds variable l p + (u + a_0l) mod p)
+        for (int l = 0; l < DC; ++l) {
+            const int rot = A.rot8[l] >> 3;
+            for (int u = tid; u < p; u += TB) {
+                int t = u + rot;
+                t = t >= p ? t - p : t;
+                Lpair[l * p + u].x = mu[l * p + t] * kLog2eF;
+            }
+        }
+    } else {
+        for (int v = tid; v < n; v += TB) Lpair[v].x = mu[v] * kLog2eF;
+    }
     if (tid < 3) flag[tid] = 0u;
     const uint32_t p8 = 8u * (uint32_t)p, TB8 = 8u * (uint32_t)TB;
     float al[NJ][NQ][DC];
@@ -241,7 +263,8 @@ __global__ void __launch_bounds__(MAXT) onchip_block_kernel(const int n, const i
             mu0[q][k] = 0.0f;
             if (oc_mu_in_regs(REG, DC) && s8 < p8)
                 mu0[q][k] = *reinterpret_cast<const float*>(reinterpret_cast<const char*>(mu) +
-                                                            (oc_pair(A, k, s8, p8) >> 1)) * kLog2eF;
+                                                            ((A.cb8[k] + oc_wrap8(s8 + A.rot8[k], p8)) >> 1)) *
+                            kLog2eF;
         }
     }
 #pragma unroll
@@ -325,12 +348,24 @@ __global__ void __launch_bounds__(MAXT) onchip_block_kernel(const int n, const i
         iters_out = last;
         conv_out = flag[fw] == 0u ? 1 : 0;
     }
-    for (int v = tid; v < n; v += TB) {
-        // back to natural units; a nonzero x keeps its sign (|x| ln 2 never
-        // rounds to zero), so the decision is that of the sums above
-        const float x = Lf[2 * v + comp] * kLn2F;
+    // back to natural units; a nonzero x keeps its sign (|x| ln 2 never
+    // rounds to zero), so the decision is that of the sums above
+    auto put = [&](int v, int pair) {
+        const float x = Lf[2 * pair + comp] * kLn2F;
         A.post[f0 + v] = clip30(x);
         A.bits[f0 + v] = (uint8_t)(x < 0.0f);
+    };
+    if constexpr (oc_mu_in_regs(REG, DC)) {
+        for (int l = 0; l < DC; ++l) {
+            const int rot = A.rot8[l] >> 3;
+            for (int u = tid; u < p; u += TB) {
+                int t = u + rot;
+                t = t >= p ? t - p : t;
+                put(l * p + t, l * p + u);
+            }
+        }
+    } else {
+        for (int v = tid; v < n; v += TB) put(v, v);
     }
     if (tid == 0) {
         if (A.iters) A.iters[blockIdx.x] = iters_out;
@@ -448,13 +483,20 @@ int onchip_decode(const ldpc_graph* g, const float* llr, int gamma, int max_iter
     A.early = early;
     A.nms_w = nms_w;
     A.nb = D.nb;
+    // the kernel stores columns rotated by base row 0's shifts when it keeps
+    // mu in registers (regular bases, rows of weight <= 6: base row 0 holds
+    // one block of every column, in column order)
+    int rot[kOcSlots] = {0};
+    if (oc_mu_in_regs(c.v->reg, c.v->dc))
+        for (int k = 0; k < D.rstart[1]; ++k) rot[D.ecol[k]] = D.eshift[k];
+    for (int l = 0; l < kOcSlots; ++l) A.rot8[l] = 8 * rot[l];
     for (int j = 0; j < D.J; ++j) {
         A.deg[j] = D.rstart[j + 1] - D.rstart[j];
         A.rb0[j] = D.rstart[j];
         for (int k = 0; k < A.deg[j]; ++k) {
             const int b = D.rstart[j] + k;
             A.cb8[j * kOcSlots + k] = 8 * D.ecol[b] * D.p;
-            A.sh8[j * kOcSlots + k] = 8 * D.eshift[b];
+            A.sh8[j * kOcSlots + k] = 8 * ((D.eshift[b] - rot[D.ecol[b]] + D.p) % D.p);
             if (D.cedge[D.cstart[D.ecol[b]]] == b)   // edge blocks of a column ascend by base row
                 A.first |= 1ull << (j * kOcSlots + k);
         }
