@@ -279,7 +279,7 @@ ldpc_status ldpc_nms_train_backward(const ldpc_graph* g, int32_t gamma, int32_t 
  * Multi-code plan: frames of several QC graphs, each with its own batch size,
  * decoded together by the flooding sum-product decoders of ldpc_decode
  * (Algorithm 1, Eq. 3-6; same arithmetic, so each code's outputs equal
- * ldpc_decode's bit for bit).  Codes that ldpc_decode would decode on chip
+ * ldpc_decode's bit for bit, except in the split layouts below).  Codes that ldpc_decode would decode on chip
  * (ldpc_decode_path; not in persistent mode) run that decoder, one launch
  * per code on a stream forked from the caller's and joined back before the
  * decode ends; for the others, one check-node launch and one variable-node
@@ -306,7 +306,16 @@ ldpc_status ldpc_nms_train_backward(const ldpc_graph* g, int32_t gamma, int32_t 
  * layout (G8 .. G64, column weight <= 8) makes each variable-node wavefront
  * handle 2 or 4 groups of variables (fewer, longer waves); LDPC_LAYOUT_CN2
  * (row weight <= 8) or LDPC_LAYOUT_CN4 (row weight <= 6) does the same for
- * the check-node wavefronts.
+ * the check-node wavefronts.  OR-ing LDPC_LAYOUT_SPLIT2, _SPLIT4 or _SPLIT8
+ * into G8, G16 or G32 (lanes per group times lanes per row at most 64; row
+ * weight at least twice the lanes per row) spreads each check row's edges
+ * over 2, 4 or 8 lanes of the check-node wavefront (Eq. 3 with the (t, q)
+ * products of each lane's edges combined across the lanes by shuffles), so
+ * that a heavy row of a small batch is not one lane's chain; the
+ * variable-node pass is that of the base layout.  These layouts form the
+ * products of Eq. 3 in another order than ldpc_decode: their results equal
+ * ldpc_decode's to FP32 rounding, not bit for bit (every other layout is
+ * bit-equal).
  * Graphs in a plan have row weight <= 24 (EUNSUPPORTED otherwise): one
  * kernel serves all codes and carries the registers of its heaviest case.
  * The default is the smallest tile >= gamma (for large batches G64F4, else
@@ -349,7 +358,8 @@ typedef struct ldpc_plan ldpc_plan;
 enum { LDPC_LAYOUT_G8 = 0, LDPC_LAYOUT_G16 = 1, LDPC_LAYOUT_G32 = 2, LDPC_LAYOUT_G64 = 3, LDPC_LAYOUT_G64F4 = 4,
        LDPC_LAYOUT_G64F2 = 5, LDPC_LAYOUT_G8F2 = 6, LDPC_LAYOUT_G8F4 = 7, LDPC_LAYOUT_G16F2 = 8,
        LDPC_LAYOUT_G16F4 = 9, LDPC_LAYOUT_G32F2 = 10, LDPC_LAYOUT_G32F4 = 11, LDPC_LAYOUT_VN2 = 16,
-       LDPC_LAYOUT_VN4 = 32, LDPC_LAYOUT_CN2 = 64, LDPC_LAYOUT_CN4 = 128 };
+       LDPC_LAYOUT_VN4 = 32, LDPC_LAYOUT_CN2 = 64, LDPC_LAYOUT_CN4 = 128, LDPC_LAYOUT_SPLIT2 = 256,
+       LDPC_LAYOUT_SPLIT4 = 512, LDPC_LAYOUT_SPLIT8 = 768 };
 
 ldpc_status ldpc_plan_create(const ldpc_graph* const* graphs, const int32_t* gammas, int32_t ncodes,
                              int32_t max_iters, int32_t early_stop, ldpc_plan** out);

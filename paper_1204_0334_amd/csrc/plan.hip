@@ -24,7 +24,9 @@
 // caller's workspace; a launch's waves find their code by scanning that
 // table (a handful of entries).  The arithmetic per frame is the single-code
 // decoder's (shared helpers sp_check / sp_variable, same edge order), so a
-// plan returns bit for bit what ldpc_decode returns for each code.
+// plan returns bit for bit what ldpc_decode returns for each code; the split
+// layouts (a check row's edges over several lanes) agree with it to FP32
+// rounding.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -47,10 +49,14 @@ constexpr int kPlanLayouts = 12;
 
 // A code's layout value: base lane layout (bits 0-3), log2 of the number of
 // variable groups each variable-node wave handles (bits 4-5) and of row groups
-// per check-node wave (bits 6-7); groups only with one frame per lane.
+// per check-node wave (bits 6-7); groups only with one frame per lane; log2
+// of the number of lanes that share each check row's edges (bits 8-9, split
+// layouts: G8, G16 or G32 with one frame per lane and one row group).
+constexpr int kLayoutValues = 1024;
 __host__ __device__ constexpr int layout_base(int l) { return l & 15; }
 __host__ __device__ constexpr int layout_vpw(int l) { return 1 << ((l >> 4) & 3); }
 __host__ __device__ constexpr int layout_cpw(int l) { return 1 << ((l >> 6) & 3); }
+__host__ __device__ constexpr int layout_split(int l) { return 1 << ((l >> 8) & 3); }
 __host__ __device__ constexpr int layout_g(int l) {
     const int b = layout_base(l);
     return b <= 3 ? 8 << b : b <= 5 ? 64 : b <= 7 ? 8 : b <= 9 ? 16 : 32;
@@ -82,6 +88,7 @@ struct PlanCode {
     int64_t io0;          // first block in the ingest / output launches
     int vpw;              // variable-node launch: groups of R variables per wave (1, 2 or 4)
     int cpw;              // check-node launch: groups of R rows per wave (1, 2 or 4)
+    int split;            // check-node launch: lanes sharing each row's edges (1, 2, 4 or 8)
     uint64_t* badw;       // early stopping: [2][tiles * cn_wpt][FPL] frames violating each check wave's
                           // rows, slot = (iteration of the decisions tested) & 1
     uint32_t* slot;       // [gamma]: slot holding each frame's returned iteration
@@ -383,6 +390,135 @@ __device__ __forceinline__ void plan_cn_body(const PlanCode& C, const PlanStep& 
         M::st64(C, C.badw + ((S.iter - 1) & 1) * C.badw_slot + lw * FPL + lane, par & valid_word<FPL>(nvalid, lane));
 }
 
+// Check-node pass of a split layout: each row's edges are spread over H
+// lanes, so that a heavy row with few frames is not one lane's chain of d
+// loads and d-step sweeps.  Lane = (r * H + h) * G + f: row r of the wave's
+// R = 64 / (G H) rows, part h of its edges (slots h, h + H, h + 2H, ...),
+// frame f of the tile (one frame per lane; the message layout is that of
+// the base layout, so the variable-node pass is unchanged).  Eq. 3 in the
+// (t, q) form of sp_check: each lane combines its slots' pairs into one
+// pair, takes the pairs of the row's other parts by shuffles (lanes
+// lane + (h' - h) G) and combines those before and after its own into a
+// prefix and a suffix, then runs the forward-backward sweep over its own
+// slots starting from them; the sign is the XOR over the H lanes.  The
+// products are therefore formed in another order than sp_check's sweep
+// over the whole row: the results agree with it to FP32 rounding, not bit
+// for bit.  Early stopping as in plan_cn_body: the row's decision words
+// are spread over its G H lanes and combined by XOR butterflies, the rows
+// of the wave by OR.
+template <int DCMAX, int G, int H, class M>
+__device__ __forceinline__ void plan_cn_split_body(const PlanCode& C, const PlanStep& S, int64_t lw, int lane) {
+    constexpr int R = 64 / (G * H);
+    constexpr int Gt = G;
+    constexpr int KL = (DCMAX + H - 1) / H;
+    static_assert(R >= 1 && KL >= 1, "a wave holds at least one row");
+    const QCDesc& D = C.D;
+    const int tile = (int)(lw / C.cn_wpt);
+    const int rw = (int)(lw - (int64_t)tile * C.cn_wpt);
+    const int f = lane % G, h = (lane / G) % H, r = lane / (G * H);
+    const int nvalid = min(C.gamma - tile * Gt, Gt);
+    if (S.early && S.iter >= 4) {
+        const uint64_t* fz = C.frozen + ((size_t)(S.iter - 3) * C.tiles + tile);
+        if (M::ld64(C, fz) == ~0ull) return;
+    }
+    float* mt = C.msg + (size_t)tile * D.E * Gt + f;
+    const float* ut = C.mu + (size_t)tile * D.n * Gt + f;
+    const int spw = C.cn_wpt / D.J;
+    const int j = rw / spw, sw = rw - j * spw;
+    const int srow = sw * R + r;
+    const bool active = srow < D.p;
+    const PlanRow Rw(D, j, active ? srow : 0, active);
+    const int d = Rw.d;
+    float in[KL];
+#pragma unroll
+    for (int i = 0; i < KL; ++i) {
+        const int k = h + H * i;
+        in[i] = 0.0f;
+        if (k < d) {
+            const float* s = S.iter == 1 ? ut + (size_t)Rw.var(D, k) * Gt : mt + (size_t)Rw.pkg(D, k) * Gt;
+            float v[1];
+            M::template ld<1>(C, s, v);
+            in[i] = v[0];
+        }
+    }
+    const bool syn = S.early && S.iter >= 2;
+    uint64_t par = 0;
+    if (syn) {
+        // lane gi of the row's G H lanes takes variables gi, gi + G H, ...
+        const uint64_t* bt = C.bits + ((S.iter - 1) & 1) * C.bits_slot + (size_t)tile * D.n;
+        const int gi = lane % (G * H);
+#pragma unroll
+        for (int q0 = 0; q0 < (DCMAX + G * H - 1) / (G * H); ++q0) {
+            const int k = q0 * G * H + gi;
+            if (k < d) par ^= M::ld64(C, bt + Rw.var(D, k));
+        }
+#pragma unroll
+        for (int off = G * H / 2; off >= 1; off >>= 1) par ^= __shfl_xor(par, off);
+#pragma unroll
+        for (int off = 32; off >= G * H; off >>= 1) par |= __shfl_xor(par, off);
+    }
+    float t[KL], q[KL];
+    uint32_t sgn = 0;
+#pragma unroll
+    for (int i = 0; i < KL; ++i) {
+        if (h + H * i < d) {
+            tq_of(in[i], t[i], q[i]);
+            sgn ^= __float_as_uint(in[i]) & 0x80000000u;
+        } else {
+            t[i] = 1.0f;
+            q[i] = 0.0f;
+        }
+    }
+    // this part's pair, slots in ascending order
+    float P = t[0], Q = q[0];
+#pragma unroll
+    for (int i = 1; i < KL; ++i) {
+        Q = fmaf(q[i], P, Q);
+        P = P * t[i];
+    }
+#pragma unroll
+    for (int off = G; off < G * H; off <<= 1) sgn ^= __shfl_xor(sgn, off);
+    // prefix over parts h' < h and suffix over parts h' > h, each ascending
+    float aP = 1.0f, aQ = 0.0f, cP = 1.0f, cQ = 0.0f;
+    const int part0 = lane - h * G;
+#pragma unroll
+    for (int hh = 0; hh < H; ++hh) {
+        const float Ph = __shfl(P, part0 + hh * G);
+        const float Qh = __shfl(Q, part0 + hh * G);
+        if (hh < h) {
+            aQ = fmaf(Qh, aP, aQ);
+            aP = aP * Ph;
+        } else if (hh > h) {
+            cQ = fmaf(Qh, cP, cQ);
+            cP = cP * Ph;
+        }
+    }
+    // suffix pairs of the own slots, each followed by the later parts
+    float sP[KL], sQ[KL];
+#pragma unroll
+    for (int i = KL - 1; i >= 0; --i) {
+        sP[i] = cP;
+        sQ[i] = cQ;
+        cQ = fmaf(cQ, t[i], q[i]);
+        cP = cP * t[i];
+    }
+#pragma unroll
+    for (int i = 0; i < KL; ++i) {
+        const int k = h + H * i;
+        const float eP = aP * sP[i];
+        const float eQ = fmaf(sQ[i], aP, aQ);
+        const float mag = kLn2 * __builtin_amdgcn_logf((1.0f + eP) * __builtin_amdgcn_rcpf(eQ));
+        aQ = fmaf(q[i], aP, aQ);
+        aP = aP * t[i];
+        if (k < d) {
+            const float o[1] = {__uint_as_float(__float_as_uint(mag) | (sgn ^ (__float_as_uint(in[i]) & 0x80000000u)))};
+            M::template st<1>(C, mt + (size_t)Rw.pkg(D, k) * Gt, o);
+        }
+    }
+    if (syn && lane == 0)
+        M::st64(C, C.badw + ((S.iter - 1) & 1) * C.badw_slot + lw, par & valid_word<1>(nvalid, 0));
+}
+
 // Variable-node pass of iteration S.iter for wave lw of code C: betas (not
 // after the last iteration), and with early stopping or at the last
 // iteration the packed decisions and the posterior, into slot iter & 1, of
@@ -554,7 +690,17 @@ __device__ __forceinline__ void plan_unsat_block(const PlanCode& C, int r, int64
 // One wave of the check-node pass (every layout and row-weight class).
 template <class M>
 __device__ __forceinline__ void plan_cn_wave(const PlanCode& C, const PlanStep& S, int64_t lw, int lane) {
-    if (C.cpw == 1) {
+    if (C.split > 1) {
+        PLAN_LAYOUT_SWITCH(C.layout, PLAN_DC_SWITCH(C.dcc, if constexpr (FPL == 1 && G <= 32) {
+            if (C.split == 2) {
+                plan_cn_split_body<DC, G, 2, M>(C, S, lw, lane);
+            } else if (C.split == 4) {
+                if constexpr (DC >= 8 && G <= 16) plan_cn_split_body<DC, G, 4, M>(C, S, lw, lane);
+            } else {
+                if constexpr (DC >= 16 && G == 8) plan_cn_split_body<DC, G, 8, M>(C, S, lw, lane);
+            }
+        }));
+    } else if (C.cpw == 1) {
         PLAN_LAYOUT_SWITCH(C.layout, PLAN_DC_SWITCH(C.dcc, if constexpr (FPL == 1 || DC <= (FPL == 4 ? 6 : 12)) {
             plan_cn_body<DC, G, FPL, 1, M>(C, S, lw, lane);
         }));
@@ -1043,8 +1189,13 @@ int plan_dv_class(int d) {
 }
 
 bool layout_allowed(const ldpc_graph* g, int l) {
-    if (l < 0 || l >= 256 || layout_base(l) >= kPlanLayouts || ((l >> 4) & 3) == 3 || ((l >> 6) & 3) == 3)
+    if (l < 0 || l >= kLayoutValues || layout_base(l) >= kPlanLayouts || ((l >> 4) & 3) == 3 || ((l >> 6) & 3) == 3)
         return false;
+    if (const int H = layout_split(l); H > 1) {
+        // G8, G16, G32 with one frame per lane and one row group per check
+        // wave; at least two edges per lane (the kernel's instantiations)
+        if (layout_base(l) > 2 || layout_cpw(l) > 1 || layout_g(l) * H > 64 || g->dc_max < 2 * H) return false;
+    }
     if (layout_vpw(l) > 1 && (layout_fpl(l) != 1 || g->dv_max > 8)) return false;
     if (layout_cpw(l) > 1 && (layout_fpl(l) != 1 || g->dc_max > (layout_cpw(l) == 2 ? 8 : 6))) return false;
     if (layout_fpl(l) == 4) return g->dc_max <= 6 && g->dv_max <= 8;
@@ -1061,7 +1212,7 @@ struct CodeRegion {
 
 // check-node waves per tile: per base row, enough waves for its p rows
 int plan_cn_wpt(const ldpc_graph* g, int l) {
-    const int rows = (64 / layout_g(l)) * layout_cpw(l);
+    const int rows = (64 / (layout_g(l) * layout_split(l))) * layout_cpw(l);
     return g->J * ((g->p + rows - 1) / rows);
 }
 
@@ -1213,6 +1364,7 @@ void build_table(ldpc_plan* P, const PlanBuffers& B, char* ws) {
         const int rows_per_wave = 64 / layout_g(l);
         T.vpw = layout_vpw(l);
         T.cpw = layout_cpw(l);
+        T.split = layout_split(l);
         // waves per tile: per base row (column), enough waves for its p rows (variables)
         T.cn_wpt = plan_cn_wpt(g, l);
         T.vn_wpt = g->L * ((g->p + rows_per_wave * T.vpw - 1) / (rows_per_wave * T.vpw));
@@ -1432,7 +1584,7 @@ ldpc_status ldpc_plan_create(const ldpc_graph* const* graphs, const int32_t* gam
     for (int c = 0; c < ncodes; ++c) {
         P->layouts[c] = default_layout(graphs[c], gammas[c]);
         size_t most = 0;
-        for (int l = 0; l < 192; ++l)
+        for (int l = 0; l < kLayoutValues; ++l)
             if (layout_allowed(graphs[c], l)) most = std::max(most, code_region(graphs[c], gammas[c], l, max_iters).total);
         P->region_off.push_back(off);
         off = align256(off + most);
@@ -1576,7 +1728,7 @@ ldpc_status ldpc_plan_autotune(ldpc_plan* P, const float* const* llr, float* con
         if (P->onchip[c]) continue;   // decoded on chip: its lane layout is not used
         const int start = P->layouts[c];
         int keep = start;
-        for (int l = 0; l < 192 && status == LDPC_OK; ++l) {
+        for (int l = 0; l < kLayoutValues && status == LDPC_OK; ++l) {
             if (l == start || !layout_allowed(P->graphs[c], l)) continue;
             const int tile = layout_g(l) * layout_fpl(l);
             if (tile > 8 && tile / 2 >= P->gammas[c]) continue;   // tiles at most the next power of two

@@ -34,11 +34,13 @@ LAYOUT_G8F2, LAYOUT_G8F4, LAYOUT_G16F2, LAYOUT_G16F4, LAYOUT_G32F2, LAYOUT_G32F4
 LAYOUT_NAMES = ["G8", "G16", "G32", "G64", "G64F4", "G64F2", "G8F2", "G8F4", "G16F2", "G16F4", "G32F2", "G32F4"]
 PLAN_LAYOUTS = len(LAYOUT_NAMES)
 LAYOUT_VN2, LAYOUT_VN4, LAYOUT_CN2, LAYOUT_CN4 = 16, 32, 64, 128
+LAYOUT_SPLIT2, LAYOUT_SPLIT4, LAYOUT_SPLIT8 = 256, 512, 768
 
 
 def layout_name(layout: int) -> str:
-    v, c = (layout >> 4) & 3, (layout >> 6) & 3
-    return LAYOUT_NAMES[layout & 15] + ("" if v == 0 else f"/VN{1 << v}") + ("" if c == 0 else f"/CN{1 << c}")
+    v, c, h = (layout >> 4) & 3, (layout >> 6) & 3, (layout >> 8) & 3
+    return (LAYOUT_NAMES[layout & 15] + ("" if v == 0 else f"/VN{1 << v}") + ("" if c == 0 else f"/CN{1 << c}")
+            + ("" if h == 0 else f"/S{1 << h}"))
 PLAN_MAX_CODES = 16
 TIMING_CLASSES = 24
 MAX_ITERS = 100000

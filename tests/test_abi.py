@@ -327,6 +327,23 @@ def test_plan_creation_and_layout_rules():
         plan.set_layout(5, ldpc.LAYOUT_G16F4)
     with pytest.raises(ldpc.LdpcError):
         wide18.set_layout(0, ldpc.LAYOUT_G32F2)        # row weight 18
+    # split layouts (a check row's edges over 2, 4 or 8 lanes): G8, G16, G32
+    # with one frame per lane and one row group per check wave, groups x
+    # lanes per row <= 64, at least two edges per lane
+    S2, S4, S8 = ldpc.LAYOUT_SPLIT2, ldpc.LAYOUT_SPLIT4, ldpc.LAYOUT_SPLIT8
+    for good in (ldpc.LAYOUT_G8 | S2, ldpc.LAYOUT_G8 | S4, ldpc.LAYOUT_G8 | S8, ldpc.LAYOUT_G16 | S2,
+                 ldpc.LAYOUT_G16 | S4, ldpc.LAYOUT_G32 | S2, ldpc.LAYOUT_G8 | ldpc.LAYOUT_VN2 | S4):
+        wide18.set_layout(0, good)
+        assert wide18.layout(0) == good
+    assert ldpc.layout_name(wide18.layout(0)) == "G8/VN2/S4"
+    for bad in (ldpc.LAYOUT_G64 | S2, ldpc.LAYOUT_G32 | S4, ldpc.LAYOUT_G16 | S8, ldpc.LAYOUT_G8F2 | S2,
+                ldpc.LAYOUT_G8 | ldpc.LAYOUT_CN2 | S2, 1024):
+        with pytest.raises(ldpc.LdpcError):
+            wide18.set_layout(0, bad)
+    plan.set_layout(0, ldpc.LAYOUT_G8 | S2)            # row weight 6: 3 edges per lane
+    with pytest.raises(ldpc.LdpcError):
+        plan.set_layout(0, ldpc.LAYOUT_G8 | S4)        # fewer than 2 edges per lane
+    plan.set_layout(0, ldpc.LAYOUT_G8 | ldpc.LAYOUT_VN4)
     plan.set_layout(4, ldpc.LAYOUT_G8)
     assert plan.layout(4) == ldpc.LAYOUT_G8
     plan.set_layout(4, -1)

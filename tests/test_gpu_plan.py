@@ -1,9 +1,10 @@
 """GPU tests of the multi-code plan (through the C ABI): every code of a
 plan decodes exactly as ldpc_decode decodes it alone (same arithmetic and
 edge order, so bit for bit: posteriors, decisions, iteration counts,
-convergence flags), in every lane layout, eagerly and by graph replay; and a
-small code of a plan against the FP64 reference with the tolerances of
-test_gpu_decode."""
+convergence flags), in every lane layout but the split ones, eagerly and by
+graph replay; codes of a plan against the FP64 reference with the tolerances
+of test_gpu_decode, the split layouts (each check row's edges over several
+lanes, FP32 rounding of another order) among them."""
 import numpy as np
 import pytest
 import torch
@@ -49,6 +50,23 @@ def assert_same(outs, refs, what):
     for c, (o, r) in enumerate(zip(outs, refs)):
         for name, a, b in zip(("post", "bits", "iters", "converged"), o, r):
             assert torch.equal(a, b), f"{what}: code {c} {name} differs"
+
+
+def assert_close_to_single_code(out, ref, what):
+    """A code decoded in a split layout against ldpc_decode: the same
+    iteration count on nearly every frame; where both converged after the same
+    number of iterations, the same decisions and posteriors within 2e-4
+    relative (floor 1): the two form the products of Eq. 3 in different
+    orders, so they agree to FP32 rounding, not bit for bit."""
+    post, bits, it, conv = (t.cpu().numpy() for t in out)
+    rpost, rbits, rit, rconv = (t.cpu().numpy() for t in ref)
+    same = it == rit
+    assert same.mean() > 0.95, f"{what}: iteration counts"
+    sel = same & (conv == 1) & (rconv == 1)
+    assert sel.any(), f"{what}: no frame converged on both sides"
+    assert np.array_equal(bits[sel], rbits[sel]), f"{what}: decisions"
+    err = np.abs(post[sel].astype(np.float64) - rpost[sel]) / np.maximum(np.abs(rpost[sel]), 1.0)
+    assert err.max() <= 2e-4, f"{what}: posterior difference {err.max():.3e}"
 
 
 @pytest.mark.parametrize("early", [True, False])
@@ -150,6 +168,73 @@ def test_plan_code_against_fp64_reference():
         assert np.array_equal(o[3].astype(bool), ~H.syndrome(o[1]).any(1))
 
 
+SPLIT_LAYOUTS = [ldpc.LAYOUT_G8 | ldpc.LAYOUT_SPLIT2, ldpc.LAYOUT_G8 | ldpc.LAYOUT_SPLIT4,
+                 ldpc.LAYOUT_G8 | ldpc.LAYOUT_SPLIT8, ldpc.LAYOUT_G16 | ldpc.LAYOUT_SPLIT2,
+                 ldpc.LAYOUT_G16 | ldpc.LAYOUT_SPLIT4, ldpc.LAYOUT_G32 | ldpc.LAYOUT_SPLIT2,
+                 ldpc.LAYOUT_G8 | ldpc.LAYOUT_VN2 | ldpc.LAYOUT_SPLIT4]
+# rows of weight 18 and 9 (ragged last tiles in every group size), and a
+# 3 x 6 code that keeps its default layout in the same plan
+SPLIT_SPEC = [dict(J=3, L=18, p=36, gamma=21, ebn0_db=3.5), dict(J=3, L=9, p=72, gamma=9, ebn0_db=3.0),
+              dict(J=3, L=6, p=27, gamma=20, ebn0_db=2.5)]
+
+
+@pytest.mark.parametrize("layout", SPLIT_LAYOUTS, ids=ldpc.layout_name)
+def test_split_layouts_against_fp64_reference(layout):
+    # each check row's edges over 2, 4 or 8 lanes: 1-3 iterations with every
+    # posterior gated, 20 with early stopping and exact iteration counts
+    graphs, shifts, llr_np = cpu_case(SPLIT_SPEC, 4500)
+    llrs = [torch.from_numpy(x).to(DEV) for x in llr_np]
+    gammas = [c["gamma"] for c in SPLIT_SPEC]
+    for iters, early in [(1, False), (2, False), (3, False), (20, True)]:
+        plan = ldpc.Plan(graphs, gammas, iters, early_stop=early)
+        split = []
+        for c in range(2):
+            try:
+                plan.set_layout(c, layout)
+                split.append(c)
+            except ldpc.LdpcError:
+                pass                       # 8 lanes need rows of weight >= 16
+        assert 0 in split
+        print(f"[gpu] split layout {ldpc.layout_name(layout)} on codes {split}, I={iters} early={early}", flush=True)
+        outs = plan.decode(llrs)
+        torch.cuda.synchronize()
+        for i, c in enumerate(SPLIT_SPEC):
+            H = oracle.qc_parity_check(shifts[i], c["p"])
+            o = tuple(t.cpu().numpy() for t in outs[i])
+            gated = reference_parity(o, H, llr_np[i], iters, early, not early, f"code {i} I={iters}")
+            assert gated > 0
+            if early:
+                assert np.array_equal(o[3].astype(bool), ~H.syndrome(o[1]).any(1))
+        # the code in its default layout: bit for bit what ldpc_decode returns
+        ref = ldpc.decode(graphs[2], llrs[2], iters, early_stop=early)
+        assert_same([outs[2]], [ref], f"default-layout code beside {ldpc.layout_name(layout)}")
+
+
+def test_split_layouts_full_size_heavy_codes_against_reference():
+    # the mixed workload's rate-5/6 and rate-2/3 codes at their real sizes
+    # (3 x 18 p = 3600 with 8 frames, p = 36 with 128; 3 x 9 p = 2400 with
+    # 32, p = 72 with 512) in split layouts; sampled frames against the FP64
+    # reference
+    specs = [c for c in synth.MIXED_CODES if c["L"] in (9, 18) and c["p"] >= 36]
+    graphs, shifts, llr_np = cpu_case(specs, 7500)
+    llrs = [torch.from_numpy(x).to(DEV) for x in llr_np]
+    for iters, early in [(3, False), (20, True)]:
+        plan = ldpc.Plan(graphs, [c["gamma"] for c in specs], iters, early_stop=early)
+        for c, spec in enumerate(specs):
+            plan.set_layout(c, ldpc.LAYOUT_G8 | (ldpc.LAYOUT_SPLIT4 if spec["L"] == 18 else ldpc.LAYOUT_SPLIT2))
+        print(f"[gpu] split layouts at full size I={iters} early={early}: "
+              f"{[(c['L'], c['p'], ldpc.layout_name(plan.layout(i))) for i, c in enumerate(specs)]}", flush=True)
+        outs = plan.decode(llrs)
+        torch.cuda.synchronize()
+        gated = 0
+        for i, c in enumerate(specs):
+            pick = sampled_frames(c["gamma"])
+            H = oracle.qc_parity_check(shifts[i], c["p"])
+            o = tuple(t.cpu().numpy()[pick] for t in outs[i])
+            gated += reference_parity(o, H, llr_np[i][pick], iters, early, not early, f"{c['L']} p={c['p']}")
+        assert gated >= 6
+
+
 def sampled_frames(gamma):
     return np.unique(np.array([0, 1, gamma // 3, gamma // 2, gamma - 2, gamma - 1]).clip(0, gamma - 1))
 
@@ -227,17 +312,30 @@ def test_autotune_keeps_results():
     print("[gpu] plan autotune", flush=True)
     best = plan.autotune(llrs, outs, ws, trials=2)
     assert best > 0
+    split = []
     for c, g in enumerate(graphs):
         l = plan.layout(c)
         base = l & 15
         fpl = {ldpc.LAYOUT_G64F4: 4, ldpc.LAYOUT_G8F4: 4, ldpc.LAYOUT_G16F4: 4, ldpc.LAYOUT_G32F4: 4,
                ldpc.LAYOUT_G64F2: 2, ldpc.LAYOUT_G8F2: 2, ldpc.LAYOUT_G16F2: 2, ldpc.LAYOUT_G32F2: 2}.get(base, 1)
-        assert 0 <= base < ldpc.PLAN_LAYOUTS
+        lanes = 1 << ((l >> 8) & 3)
+        assert 0 <= base < ldpc.PLAN_LAYOUTS and l < 1024
         assert fpl != 4 or g.info["dc_max"] <= 6
         assert fpl != 2 or g.info["dc_max"] <= 12
-        assert (l >> 4) == 0 or base in (0, 1, 2, 3)
-        assert (l >> 6) == 0 or g.info["dc_max"] <= 8
-    assert_same(plan.decode(llrs, outs=outs, ws=ws), single_code(graphs, llrs, 20, True), "after autotune")
+        assert (l >> 4) & 15 == 0 or base in (0, 1, 2, 3)
+        assert (l >> 6) & 3 == 0 or g.info["dc_max"] <= 8
+        assert lanes == 1 or (base in (0, 1, 2) and (l >> 6) & 3 == 0 and g.info["dc_max"] >= 2 * lanes)
+        if lanes > 1:
+            split.append(c)
+    print(f"[gpu] autotuned layouts {[ldpc.layout_name(plan.layout(c)) for c in range(len(graphs))]}", flush=True)
+    outs = plan.decode(llrs, outs=outs, ws=ws)
+    refs = single_code(graphs, llrs, 20, True)
+    torch.cuda.synchronize()
+    # bit for bit in every layout but the split ones; those agree to FP32 rounding
+    assert_same([o for c, o in enumerate(outs) if c not in split],
+                [r for c, r in enumerate(refs) if c not in split], "after autotune")
+    for c in split:
+        assert_close_to_single_code(outs[c], refs[c], f"code {c} after autotune")
 
 
 def test_plan_at_the_code_limit_with_irregular_and_degenerate_codes():
