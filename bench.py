@@ -37,6 +37,10 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_qc36_p3060.json")
 TRAFFIC_FILE_4096 = os.path.join(ROOT, "profiles", "traffic_qc36_p3060_g4096.json")
 TRAFFIC_FILE_PIPELINE = os.path.join(ROOT, "profiles", "traffic_cc36_p512_pipeline.json")
 TRAFFIC_FILE_ONCHIP = os.path.join(ROOT, "profiles", "traffic_onchip_qc36_p3060.json")
+TRAFFIC_FILE_ONCHIP_4096 = os.path.join(ROOT, "profiles", "traffic_onchip_qc36_p3060_g4096.json")
+# counter summaries per batch size of the n = 18360 workload (none for others)
+TRAFFIC_BY_GAMMA = {1024: TRAFFIC_FILE, 4096: TRAFFIC_FILE_4096}
+TRAFFIC_ONCHIP_BY_GAMMA = {1024: TRAFFIC_FILE_ONCHIP, 4096: TRAFFIC_FILE_ONCHIP_4096}
 # sources a counter record stays valid for: the package kernels (and the
 # convolutional-code kernels) live in decode.hip, the on-chip decoder in onchip.hip
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1204_0334_amd", "csrc", f)
@@ -841,7 +845,8 @@ def gamma_control(g, shifts, llr_dev, iters, gamma, steps=5):
     per_kernel = ldpc.timing_read()
     del out, ws, x
     if per_kernel["onchip_decode"][0]:
-        roof = onchip_roofline(per_kernel, shifts, g.info["p"], g.info["E"], iters, gamma, traffic_path=None)
+        roof = onchip_roofline(per_kernel, shifts, g.info["p"], g.info["E"], iters, gamma,
+                               traffic_path=TRAFFIC_ONCHIP_BY_GAMMA.get(gamma))
     else:
         algo = algorithmic_bytes(g.n, g.info["E"], gamma)["variable_node"]
         launches, kms = per_kernel["variable_node"]
@@ -891,7 +896,8 @@ def package_roofline(per_kernel, n: int, E: int, gamma: int):
     avg_s = ms / launches * 1e-3
     achieved = algo[dom] / avg_s / 1e9
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom), "kernel": dom,
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "kernel": dom,
+            "traffic": measured_traffic(dom, TRAFFIC_BY_GAMMA[gamma]) if gamma in TRAFFIC_BY_GAMMA else None,
             "avg_launch_us": round(avg_s * 1e6, 2), "algorithmic_bytes_per_launch": algo[dom]}
 
 
@@ -1031,7 +1037,7 @@ def main():
     ms_per_step, per_kernel, conv_rate = time_block_decode(g, llr, iters, gamma, args.steps, args.warmup)
     value = gamma * n / (ms_per_step * 1e-3) / 1e6
     if path == "onchip":
-        roofline = onchip_roofline(per_kernel, shifts, p, E, iters, gamma)
+        roofline = onchip_roofline(per_kernel, shifts, p, E, iters, gamma, traffic_path=TRAFFIC_ONCHIP_BY_GAMMA.get(gamma))
     else:
         roofline = package_roofline(per_kernel, n, E, gamma)
     kernels = {k: {"launches": v[0], "avg_us": round(v[1] / v[0] * 1e3, 2)} for k, v in per_kernel.items() if v[0]}
