@@ -105,18 +105,28 @@ def window_algorithmic_bytes(info, W: int, gamma: int):
 
 # Issue slots of the FP32 vector ALUs (a transcendental -- exp2, log2,
 # reciprocal -- issues at a quarter of the rate, so it counts 4) for the
-# check rule the decoders run: Eq. 3 in base-2 units in the (t, q) form.
-# A row of weight d takes, over its edges: the input pairs 4d (1 + e,
-# e * r, q = 2 e r, t = 1 - q), the sign product d - 1, the suffix sweep
-# 2 (d - 2), the prefix sweep with the exclusive complements 3 (d - 2), the
-# output pairs 2d (1 + P, times 1/Q), the output signs 2d: 14d - 11 plain
-# operations, and 4d transcendentals (2^-|x| and 1/(1 + e) of each input,
-# 1/Q and log2 of each output): 30d - 11 slots.  Variable side per edge: the
+# check rules the decoders run, Eq. 3 in base-2 units.  Convolutional-code
+# decoders, (t, q) form: a row of weight d takes, over its edges, the input
+# pairs 4d (1 + e, e * r, q = 2 e r, t = 1 - q), the sign product d - 1, the
+# suffix sweep 2 (d - 2), the prefix sweep with the exclusive complements
+# 3 (d - 2), the output pairs 2d (1 + P, times 1/Q), the output signs 2d:
+# 14d - 11 plain operations, and 4d transcendentals (2^-|x| and 1/(1 + e) of
+# each input, 1/Q and log2 of each output): 30d - 11 slots.  On-chip block
+# decoder, the same pairs unnormalised, (u, w, s) = (1 - e, 2e, 1 + e): the
+# input triples 3d, the sign product d - 1, the suffix sweep 4 (d - 2) - 1
+# (U, W, S; the last S is not needed), the prefix sweep with the exclusive
+# triples 6 (d - 2), the outputs 2d (2U + W, times 1/W), the output signs 2d:
+# 18d - 22 plain operations, and 3d transcendentals (2^-|x| of each input,
+# 1/W and log2 of each output): 30d - 22 slots.  Variable side per edge: the
 # on-chip block decoder forms L = mu + sum alpha and beta = clip(L - alpha)
 # (3: the addition, the subtraction, the clip); the window decoder sums the
 # other edges by prefix and suffix (4: two partial sums, mu + sum, the clip).
 def check_row_slots(d: int) -> int:
     return 30 * d - 11
+
+
+def onchip_check_row_slots(d: int) -> int:
+    return 30 * d - 22
 
 
 VN_EDGE_SLOTS = 4
@@ -862,16 +872,16 @@ def gamma_control(g, shifts, llr_dev, iters, gamma, steps=5):
 
 def onchip_row_slots(shifts, p: int) -> int:
     """Check-rule issue slots of one iteration of one frame of the QC code
-    with this shift table: p rows of each base row, check_row_slots(weight)
+    with this shift table: p rows of each base row, onchip_check_row_slots(weight)
     each (the weight: the base row's nonzero blocks)."""
     import numpy as np
-    return sum(p * check_row_slots(int(d)) for d in (np.asarray(shifts) >= 0).sum(1))
+    return sum(p * onchip_check_row_slots(int(d)) for d in (np.asarray(shifts) >= 0).sum(1))
 
 
 def onchip_roofline(per_kernel, shifts, p: int, E: int, iters: int, gamma: int, traffic_path=TRAFFIC_FILE_ONCHIP):
     """ALU roofline of the block decoder that keeps each frame on one compute
     unit (one launch per decode, no message traffic to HBM): FP32 vector issue
-    slots of Eq. 3-5 per launch (check_row_slots per row, 3 per variable
+    slots of Eq. 3-5 per launch (onchip_check_row_slots per row, 3 per variable
     edge; every iteration, every frame) over the launch time, against the
     FP32 vector issue rate."""
     launches, ms = per_kernel["onchip_decode"]
@@ -883,7 +893,7 @@ def onchip_roofline(per_kernel, shifts, p: int, E: int, iters: int, gamma: int, 
             "traffic": measured_traffic("onchip_decode", traffic_path, ONCHIP_SOURCES) if traffic_path else None,
             "kernel": "onchip_decode",
             "avg_launch_us": round(avg_s * 1e6, 2), "algorithmic_ops_per_launch": ops,
-            "note": "FP32 vector issue slots of the check rule (30 d - 11 per row of weight d, transcendentals "
+            "note": "FP32 vector issue slots of the check rule (30 d - 22 per row of weight d, transcendentals "
                     "count 4) and 3 per variable edge, against the FP32 vector issue rate (256 CUs x 128 lanes x "
                     "2.4 GHz); each frame's messages stay in registers and LDS of one compute unit"}
 

@@ -18,7 +18,8 @@
 //     from the previous iteration's sum and the edge's own alpha, so no beta
 //     is stored;
 //   * the check update (Eq. 3) is the FP32 (t, 1 - t) forward-backward form
-//     of the package decoder, in base-2 units (check2.h).
+//     of the package decoder, in base-2 units (check2.h), with each input's
+//     pair left unnormalised (check2u_row: no reciprocal per input).
 //
 // One iteration, for base rows j = 0 .. J-1 in turn (a workgroup barrier
 // after each): every thread updates its rows of base row j from L_old
@@ -144,6 +145,74 @@ __device__ __forceinline__ void nms2_row(const float (&in)[DC], int d, const flo
     }
 }
 
+// Eq. 3 for one row in base-2 units (check2.h's check2_row) with each
+// input's pair left unnormalised: (u, w, s) = (1 - e, 2e, 1 + e), e =
+// 2^-|x|, is (t, q, 1) times 1 + e, so no reciprocal is taken per input.
+// Triples combine as (u_a u_b, w_a s_b + u_a w_b, s_a s_b) (again (t, q, 1)
+// of the combined pair times s_a s_b), and for the exclusive triple
+// (U, W, S) of slot k, S = U + W, so |alpha_k| = log2((S + U) / W) =
+// log2((2U + W) / W); only the suffix sweep needs S.  Magnitudes stay in
+// range: s <= 2, u <= 1, w >= 2^-42.3 for |x| <= 30 log2 e.  Per edge 3
+// transcendentals instead of 4, per sweep step 2 more operations: 30d - 22
+// issue slots per row of weight d instead of 30d - 11.  in[k] = beta of slot
+// k for k < d; out[k] = alpha of slot k for k < d.
+template <int DC>
+__device__ __forceinline__ void check2u_row(const float (&in)[DC], int d, float (&out)[DC]) {
+    static_assert(DC >= 2, "rows carry at least two slots");
+    float u[DC], w[DC], s[DC];
+    uint32_t sgn = 0;
+#pragma unroll
+    for (int k = 0; k < DC; ++k) {
+        if (k < d) {
+            const float e = __builtin_amdgcn_exp2f(-fabsf(in[k]));
+            u[k] = 1.0f - e;
+            w[k] = e + e;
+            s[k] = 1.0f + e;
+            sgn ^= __float_as_uint(in[k]);
+        } else {
+            u[k] = 1.0f;
+            w[k] = 0.0f;
+            s[k] = 1.0f;
+        }
+    }
+    // suffix triples over slots k+1 .. DC-1 (slot DC-1: the identity)
+    float sU[DC], sW[DC], sS[DC];
+    sU[DC - 1] = 1.0f;
+    sW[DC - 1] = 0.0f;
+    sS[DC - 1] = 1.0f;
+    sU[DC - 2] = u[DC - 1];
+    sW[DC - 2] = w[DC - 1];
+    sS[DC - 2] = s[DC - 1];
+#pragma unroll
+    for (int k = DC - 3; k >= 0; --k) {
+        sU[k] = u[k + 1] * sU[k + 1];
+        sW[k] = fmaf(w[k + 1], sS[k + 1], u[k + 1] * sW[k + 1]);
+        sS[k] = s[k + 1] * sS[k + 1];
+    }
+    // prefix (U, W) over slots 0 .. k-1, combined with the suffix
+    float PU = u[0], PW = w[0];
+    float eU[DC], eW[DC];
+    eU[0] = sU[0];
+    eW[0] = sW[0];
+#pragma unroll
+    for (int k = 1; k < DC; ++k) {
+        if (k == DC - 1) {
+            eU[k] = PU;
+            eW[k] = PW;
+        } else {
+            eU[k] = PU * sU[k];
+            eW[k] = fmaf(PW, sS[k], PU * sW[k]);
+            PW = fmaf(PW, s[k], PU * w[k]);
+            PU = PU * u[k];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < DC; ++k) {
+        const float mag = __builtin_amdgcn_logf(fmaf(2.0f, eU[k], eW[k]) * __builtin_amdgcn_rcpf(eW[k]));
+        out[k] = __uint_as_float(__float_as_uint(mag) | ((sgn ^ __float_as_uint(in[k])) & 0x80000000u));
+    }
+}
+
 // Regular bases with rows of weight <= 6 keep the scaled channel LLRs of the
 // thread's base-row-0 edges in registers (the 3 x 9 rows would spill them);
 // the others read them from the frame's LLRs in L2 when a sum starts.
@@ -191,7 +260,7 @@ __device__ __forceinline__ void oc_iteration(const OnchipArgs& A, float2* L, con
                 viol |= par;
                 float out[DC];
                 if constexpr (RULE == 0)
-                    check2_row<DC>(in, d, out);
+                    check2u_row<DC>(in, d, out);
                 else
                     nms2_row<DC>(in, d, wit + 2 * A.rb0[j], out);
 #pragma unroll
