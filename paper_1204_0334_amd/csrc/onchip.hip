@@ -242,7 +242,10 @@ __device__ __forceinline__ void oc_iteration(const OnchipArgs& A, float2* L, con
             if (s8 < p8) {
                 uint32_t va[DC];
                 float in[DC];
-                uint64_t par = 0;
+                // XOR of the signs read: the row's parity in bit 31 (a sum is
+                // never -0: every one starts from mu + 0, and in round-to-nearest
+                // a sum is -0 only if both terms are, so the sign bit is x < 0)
+                uint32_t sx = 0;
 #pragma unroll
                 for (int k = 0; k < DC; ++k) {
                     if (REG || k < d) {
@@ -250,14 +253,14 @@ __device__ __forceinline__ void oc_iteration(const OnchipArgs& A, float2* L, con
                         va[k] = (kMuInRegs && j == 0) ? (uint32_t)A.cb8[k] + s8
                                                       : oc_pair(A, j * kOcSlots + k, s8, p8);
                         const float x = lds_at(L, va[k] + kOld);
-                        if (SYN) par ^= __ballot(x < 0.0f);
+                        if (SYN) sx ^= __float_as_uint(x);
                         in[k] = clip2(x - al[j][q][k]);
                     } else {
                         va[k] = 0;
                         in[k] = 0.0f;
                     }
                 }
-                viol |= par;
+                if (SYN) viol |= __ballot((int32_t)sx < 0);
                 float out[DC];
                 if constexpr (RULE == 0)
                     check2u_row<DC>(in, d, out);
@@ -275,7 +278,7 @@ __device__ __forceinline__ void oc_iteration(const OnchipArgs& A, float2* L, con
                             // mu of variable v at byte 4 v of the frame (va = 8 v)
                             const float m = *reinterpret_cast<const float*>(
                                 reinterpret_cast<const char*>(mu) + (va[k] >> 1));
-                            *acc = m * kLog2eF + out[k];
+                            *acc = (m * kLog2eF + 0.0f) + out[k];
                         } else {
                             // the only update of this variable in this base row: no other
                             // thread touches it before the barrier, so a plain read and
@@ -314,11 +317,11 @@ __global__ void __launch_bounds__(MAXT) onchip_block_kernel(const int n, const i
             for (int u = tid; u < p; u += TB) {
                 int t = u + rot;
                 t = t >= p ? t - p : t;
-                Lpair[l * p + u].x = mu[l * p + t] * kLog2eF;
+                Lpair[l * p + u].x = mu[l * p + t] * kLog2eF + 0.0f;
             }
         }
     } else {
-        for (int v = tid; v < n; v += TB) Lpair[v].x = mu[v] * kLog2eF;
+        for (int v = tid; v < n; v += TB) Lpair[v].x = mu[v] * kLog2eF + 0.0f;
     }
     if (tid < 3) flag[tid] = 0u;
     const uint32_t p8 = 8u * (uint32_t)p, TB8 = 8u * (uint32_t)TB;
@@ -333,7 +336,7 @@ __global__ void __launch_bounds__(MAXT) onchip_block_kernel(const int n, const i
             if (oc_mu_in_regs(REG, DC) && s8 < p8)
                 mu0[q][k] = *reinterpret_cast<const float*>(reinterpret_cast<const char*>(mu) +
                                                             ((A.cb8[k] + oc_wrap8(s8 + A.rot8[k], p8)) >> 1)) *
-                            kLog2eF;
+                            kLog2eF + 0.0f;
         }
     }
 #pragma unroll

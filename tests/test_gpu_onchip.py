@@ -145,3 +145,29 @@ def test_against_the_package_decoder_at_full_size(monkeypatch):
     assert np.array_equal(on["bits"][sel], pk["bits"][sel])
     err = np.abs(on["post"][sel].astype(np.float64) - pk["post"][sel]) / np.maximum(np.abs(pk["post"][sel]), 1.0)
     assert err.max() <= 2e-4
+
+
+@pytest.mark.parametrize("J,L,p", [(3, 9, 72), (3, 6, 64)])
+def test_zero_llrs_of_either_sign_decide_zero(J, L, p):
+    # a posterior of exactly zero, +0 or -0, is decision 0 (L < 0 is false):
+    # frames of all-zero channel LLRs of either sign decode to the all-zero
+    # word and stop after one iteration, also with odd row weights, where
+    # counting -0 as negative would make every row unsatisfied; frames at a
+    # good SNR beside them against the FP64 reference
+    a = synth.draw_qc_shifts(J, L, p, 77)
+    g = ldpc.Graph.qc(a, p)
+    assert ldpc.decode_path(g) == "onchip"
+    n = L * p
+    _, llr, _ = qc_case(J, L, p, 77, 6, 4.0, 808)
+    llr = llr.copy()
+    llr[0] = -0.0
+    llr[1] = 0.0
+    llr[2, : n // 2] = -0.0
+    assert np.signbit(llr[0]).all() and not np.signbit(llr[1]).any()
+    gpu = gpu_decode(g, llr, 10, True)
+    for f in (0, 1):
+        assert gpu["iters"][f] == 1 and gpu["converged"][f] == 1, f
+        assert not gpu["bits"][f].any() and not gpu["post"][f].any()
+    H = oracle.qc_parity_check(a, p)
+    ref = oracle.decode_block(H, llr, 10, early_stop=True)
+    check_parity({k: v[2:] for k, v in gpu.items()}, {k: v[2:] for k, v in ref.items()}, False, "zero LLRs beside")
