@@ -210,6 +210,30 @@ def test_split_layouts_against_fp64_reference(layout):
         assert_same([outs[2]], [ref], f"default-layout code beside {ldpc.layout_name(layout)}")
 
 
+@pytest.mark.parametrize("iters,early", [(3, False), (20, True)])
+def test_split_layouts_persistent_launch_matches_phase_launches(iters, early):
+    # the persistent kernel carries the split bodies too: same layouts, same
+    # device functions, so bit for bit the phase launches' outputs
+    graphs, llrs = make_case(SPLIT_SPEC, 4600)
+    gammas = [c["gamma"] for c in SPLIT_SPEC]
+    layouts = [ldpc.LAYOUT_G8 | ldpc.LAYOUT_SPLIT4, ldpc.LAYOUT_G16 | ldpc.LAYOUT_SPLIT2, None]
+    outs = []
+    for persistent in (False, True):
+        plan = ldpc.Plan(graphs, gammas, iters, early_stop=early)
+        if persistent:
+            plan.set_persistent(True)
+        for c, l in enumerate(layouts):
+            if l is not None:
+                plan.set_layout(c, l)
+        ws = plan.workspace(DEV)
+        print(f"[gpu] split layouts persistent={persistent} I={iters} early={early}", flush=True)
+        outs.append(plan.decode(llrs, ws=ws))
+        torch.cuda.synchronize()
+        if persistent:
+            plan.check(ws)
+    assert_same(outs[1], outs[0], "persistent against phase launches, split layouts")
+
+
 def test_split_layouts_full_size_heavy_codes_against_reference():
     # the mixed workload's rate-5/6 and rate-2/3 codes at their real sizes
     # (3 x 18 p = 3600 with 8 frames, p = 36 with 128; 3 x 9 p = 2400 with
