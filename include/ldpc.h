@@ -177,10 +177,12 @@ ldpc_status ldpc_decode(const ldpc_graph* g, const float* llr, int32_t gamma, in
  * has 3 rows of weight <= 9 or 4 rows of weight <= 8, no empty base column,
  * p <= 3072, two n-float arrays within the device's LDS per workgroup), 0
  * when it runs the message-package decoder (edge messages in the workspace,
- * one launch per half-iteration).  Both compute Algorithm 1 with the same
- * FP32 check rule; the on-chip decoder forms each variable-to-check message
- * as clip(L - alpha) from the posterior sum instead of summing the other
- * edges, so the two agree within FP32 rounding, not bit for bit.  Setting
+ * one launch per half-iteration).  Both compute Algorithm 1 with the FP32
+ * check rule in the (tanh, 1 - tanh) pair form; the on-chip decoder carries
+ * the pairs unnormalised (no reciprocal per input) and forms each
+ * variable-to-check message as clip(L - alpha) from the posterior sum
+ * instead of summing the other edges, so the two agree within FP32
+ * rounding, not bit for bit.  Setting
  * the environment variable LDPC_BLOCK_PATH=packages makes ldpc_decode use
  * the package decoder for every code (read at each call).  The workspace
  * argument of ldpc_decode is validated the same way on both paths.
