@@ -64,7 +64,7 @@ struct OnchipArgs {
     uint8_t* bits;          // [gamma][n]
     int32_t* iters;         // [gamma] or NULL
     uint8_t* conv;          // [gamma] or NULL
-    int max_iters, early;
+    int max_iters;
     // edge slot k of base row j (index j * kOcSlots + k): row (j, s) meets
     // variable l*p + (s + a) mod p of base column l; held as byte offsets
     // into the LDS posterior pairs (8 bytes per variable): cb8 = 8 l p and
@@ -298,8 +298,10 @@ __device__ __forceinline__ void oc_iteration(const OnchipArgs& A, float2* L, con
 
 // REG: every base row has DC nonzero blocks and every block of base row 0 is
 // nonzero (so every base column starts in base row 0); otherwise the row
-// weights and the first blocks of the columns come from the tables.
-template <int NJ, int NQ, int DC, bool REG, int RULE, int MAXT>
+// weights and the first blocks of the columns come from the tables.  EARLY:
+// with early stopping; a kernel of its own, so that the loop
+// without the syndrome test gets the registers to itself.
+template <int NJ, int NQ, int DC, bool REG, int RULE, int MAXT, bool EARLY>
 __global__ void __launch_bounds__(MAXT) onchip_block_kernel(const int n, const int p, const OnchipArgs A) {
     // dynamic LDS: [n] posterior pairs (L of even iterations, L of odd
     // iterations), then three flag words
@@ -370,7 +372,7 @@ __global__ void __launch_bounds__(MAXT) onchip_block_kernel(const int n, const i
     };
     using Odd = std::integral_constant<int, 1>;
     using Even = std::integral_constant<int, 0>;
-    if (A.early) {
+    if constexpr (EARLY) {
         using On = std::true_type;
         for (int it = 1; it <= A.max_iters; it += 2) {
             if (step(it, Odd{}, On{})) break;
@@ -455,19 +457,22 @@ struct Variant {
     int nj, nq, dc;
     bool reg;
     int rule, maxt;
-    const void* fn;
+    const void* fn;         // without early stopping
+    const void* fn_early;   // with early stopping
 };
 
 template <int NJ, int NQ, int DC, bool REG, int RULE = 0, int MAXT = kOcMaxThreads>
 constexpr Variant variant() {
     return Variant{NJ, NQ, DC, REG, RULE, MAXT,
-                   reinterpret_cast<const void*>(&onchip_block_kernel<NJ, NQ, DC, REG, RULE, MAXT>)};
+                   reinterpret_cast<const void*>(&onchip_block_kernel<NJ, NQ, DC, REG, RULE, MAXT, false>),
+                   reinterpret_cast<const void*>(&onchip_block_kernel<NJ, NQ, DC, REG, RULE, MAXT, true>)};
 }
 
 // (base rows, rows per thread and base row, row-weight capacity, regular
-// base); each compiles without spilled vector registers (54 alphas per
-// thread at most: rows of weight 18 would spill and stay with the package
-// decoder)
+// base); each compiles without spilled vector registers but the general
+// 3 x 9 variant with two rows per thread (4 values, 12 with early stopping;
+// 54 alphas per thread at most: rows of weight 18 would spill and stay with
+// the package decoder)
 const Variant kVariants[] = {
     variant<3, 1, 6, true>(),  variant<3, 2, 6, true>(),  variant<3, 3, 6, true>(),
     variant<3, 1, 9, true>(),  variant<3, 2, 9, true>(),
@@ -552,7 +557,6 @@ int onchip_decode(const ldpc_graph* g, const float* llr, int gamma, int max_iter
     A.iters = iters;
     A.conv = converged;
     A.max_iters = max_iters;
-    A.early = early;
     A.nms_w = nms_w;
     A.nb = D.nb;
     // the kernel stores columns rotated by base row 0's shifts when it keeps
@@ -573,14 +577,15 @@ int onchip_decode(const ldpc_graph* g, const float* llr, int gamma, int max_iter
                 A.first |= 1ull << (j * kOcSlots + k);
         }
     }
-    if (hipFuncSetAttribute(c.v->fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c.lds) != hipSuccess) {
+    const void* fn = early ? c.v->fn_early : c.v->fn;
+    if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c.lds) != hipSuccess) {
         (void)hipGetLastError();
         return 0;
     }
     timing::Scope ts(23, st);
     int n = D.n, p = D.p;
     void* args[] = {&n, &p, &A};
-    return hipLaunchKernel(c.v->fn, dim3((unsigned)gamma), dim3((unsigned)c.tb), args, c.lds, st) == hipSuccess ? 1 : -1;
+    return hipLaunchKernel(fn, dim3((unsigned)gamma), dim3((unsigned)c.tb), args, c.lds, st) == hipSuccess ? 1 : -1;
 }
 
 }  // namespace ldpc
