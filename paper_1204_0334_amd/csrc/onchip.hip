@@ -28,8 +28,10 @@
 // one row of its base row, so within one base row no two threads touch the
 // same variable and the additions need no atomics; the base-row order fixes
 // the order of every sum, so results are deterministic.  The lowest nonzero
-// block of each base column starts its variables' sums from mu (read from
-// the caller's LLR array, which stays in L2).  HBM traffic per frame is the
+// block of each base column starts its variables' sums from mu (held in
+// registers for regular bases, whose columns are stored rotated by base row
+// 0's shifts; else read from the caller's LLR array, which stays in L2).
+// HBM traffic per frame is the
 // channel LLRs in and the outputs out; the decode is bound by the vector
 // ALUs (the transcendentals of Eq. 3).
 //
@@ -40,7 +42,8 @@
 // the outputs of iteration i-1, which are still in L_old (iteration i wrote
 // only L_new).  The syndrome of the last iteration is tested once after the
 // loop.  Flags rotate over three words so that clearing the next one never
-// races with a late reader of the previous one.
+// races with a late reader of the previous one.  Decodes with and without
+// early stopping run separate instantiations of the kernel.
 #include <hip/hip_runtime.h>
 
 #include <cstdlib>
